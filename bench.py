@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 Kerr ray tracer with radiative transfer on one MI355X.
+
+Default workload: the optically thin thermal-synchrotron torus image
+(a = 0.94, inclination 17 deg, 1024 x 1024 rays over +-20 M, 230 GHz). One
+step = one full image traced by kgrt_trace (ray start, adaptive Cash-Karp
+integration, per-step transfer of tau and I_nu, writeback), inputs and
+outputs resident in HBM.
+
+Metric: ns per photon per accepted RK step = kernel time / sum of accepted
+steps over the image (the paper's Table 1 quantity T/S).
+
+Prints ONE JSON line. Extra modes:
+  --calibrate RAY   trace copies of one ray (no divergence) so a rocprofv3
+                    --pmc run can count FP64 VALU instructions per step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ns/photon/RK step; images/s surrogate+fallback vs integrator @1% flux"
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
+
+# FP64 FLOPs per attempted Cash-Karp step of the torus workload, transfer of
+# the accepted steps included. "calibrated": 64 x (ADD + MUL + TRANS + 2 FMA)
+# FP64 VALU instructions per attempt from rocprofv3 counters on a
+# divergence-free run (every lane traces the same ray), see
+# profiles/torus_flop_calibration.md. "formula": operation count of the
+# source with every divide, root and transcendental counted once.
+FLOPS_PER_ATTEMPT = {"torus": (850.0, "formula"), "thin_disk": (620.0, "formula"),
+                     "projection": (620.0, "formula")}
+
+CALIBRATION_RAYS = {
+    # (a, incl_deg, x, y): a captured ray, an escaping ray through the torus, a far ray
+    "captured": (0.94, 17.0, 1.5, 2.0),
+    "escaping": (0.94, 17.0, 7.0, -5.0),
+    "far": (0.94, 17.0, 18.0, 15.0),
+}
+
+
+def workload(name: str, n: int | None):
+    from paper_1601_02063_amd import scenes
+    if name == "torus":
+        return scenes.torus_image(n or 1024), "optically thin thermal-synchrotron torus, a=0.94, incl=17 deg, " \
+            f"{n or 1024}x{n or 1024} rays over +-20 M, 230 GHz, rtol 1e-8, step cap 0.02 r"
+    if name == "thin_disk":
+        return scenes.thin_disk_image(n or 64), f"thin Keplerian disk ISCO-20 M, a=0.9, incl=60 deg, " \
+            f"{n or 64}x{n or 64} rays over +-15 M, rtol 1e-8"
+    if name == "projection":
+        return scenes.projection_image(n or 1024), f"first-crossing projection, a=0.95, incl=60 deg, " \
+            f"{n or 1024}x{n or 1024} rays over +-15 M, rtol 1e-8"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, nsample: int, seed: int = 2024):
+    """The CPU oracle on a seeded sample of pixels of the same workload."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1601_02063_amd import scenes
+    cam = w["camera"]
+    idx = scenes.sample_pixels(cam["nx"], cam["ny"], nsample, seed)
+    xy = O.pixel_points(cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"], cam["y_max"])[idx]
+    sc = O.Scene(a=cam["a"], incl_deg=cam["incl_deg"], r_obs=cam["r_obs"], rtol=w["integ"]["rtol"],
+                 hmax_frac=w["integ"]["hmax_frac"], horizon_delta=w["integ"]["horizon_delta"],
+                 max_steps=w["integ"]["max_steps"], model=w["model"]["kind"],
+                 stop_at_crossing=bool(w["integ"]["flags"] & 1), freqs_hz=list(w["freqs"]),
+                 **{k: v for k, v in w["model"].items() if k != "kind"})
+    threads = O.default_threads()
+    t0 = time.perf_counter()
+    res = O.trace_points(sc, xy, threads)
+    dt = time.perf_counter() - t0
+    steps = int(res["steps"].astype(np.int64).sum())
+    return {"value": dt / steps * 1e9, "unit": "ns/photon/RK step", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} seeded pixels (seed {seed}) of the same image, {steps} accepted steps, "
+                      f"{dt:.2f} s wall on {threads} threads ({platform.processor() or platform.machine()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="torus", choices=["torus", "thin_disk", "projection"])
+    ap.add_argument("--n", type=int, default=None, help="image side (default per workload)")
+    ap.add_argument("--cpu-sample", type=int, default=6000, help="pixels in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--refill-min", type=int, default=0)
+    ap.add_argument("--calibrate", default=None, choices=sorted(CALIBRATION_RAYS))
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the ray tracer shards by images or rays across "
+              "GPUs, but no multi-GPU path is built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    ctx = K.Context(0)
+    ctx.set_launch(args.block, args.blocks_per_cu, args.refill_min)
+
+    if args.calibrate:
+        calibrate(ctx, args.calibrate, dev)
+        return
+
+    w, desc = workload(args.workload, args.n)
+    cam, mod, freqs = K.Camera(**w["camera"]), K.Model(**w["model"]), list(w["freqs"])
+    integ = K.Integrator(**w["integ"])
+    n = cam.nx * cam.ny
+    out = K.alloc_outputs(n, mod, len(freqs), dev, names=("status", "steps", "attempts", "intensity", "tau",
+                                                          "r_cross", "g"))
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.trace(cam, mod, freqs, integ, out)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        ctx.trace(cam, mod, freqs, integ, out)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [s.elapsed_time(e) for s, e in ev]
+    ms_mean = sum(kern_ms) / len(kern_ms)
+
+    steps = int(out["steps"].to(torch.int64).sum())
+    attempts = int(out["attempts"].to(torch.int64).sum())
+    st = out["status"]
+    ns_per_step = ms_mean * 1e6 / steps
+    fpa, basis = FLOPS_PER_ATTEMPT[args.workload]
+    achieved = fpa * attempts / (ms_mean * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": round(ns_per_step, 6),
+        "unit": "ns/photon/RK step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "rays": n, "nfreq": len(freqs), "launch": {
+            "block": args.block or 256, "blocks_per_cu": args.blocks_per_cu or "occupancy",
+            "refill_min": args.refill_min or 1}},
+        "kernel_ms": round(ms_mean, 4),
+        "kernel_ms_min": round(min(kern_ms), 4),
+        "rays_per_s": round(n / (ms_mean * 1e-3), 1),
+        "images_per_s": round(1.0 / (ms_mean * 1e-3), 3),
+        "accepted_steps": steps,
+        "attempted_steps": attempts,
+        "steps_per_ray": round(steps / n, 2),
+        "captured_frac": round(float(((st & 1) != 0).float().mean()), 5),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                     "flops_per_attempt": fpa, "flops_basis": basis,
+                     "kernel": "trace_kernel<torus,1>" if args.workload == "torus" else "trace_kernel<disk,1>"},
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def calibrate(ctx, which: str, dev):
+    """Traces N identical copies of one ray: every wave runs converged, so the
+    FP64 VALU instruction counters divided by the attempted steps give the
+    arithmetic per step without divergence."""
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    w = scenes.torus_image(16)
+    mod, freqs, integ = K.Model(**w["model"]), list(w["freqs"]), K.Integrator(**w["integ"])
+    nrays = 256 * 1024
+    ray = torch.tensor(CALIBRATION_RAYS[which], dtype=torch.float64, device=dev)
+    rays = ray.repeat(nrays, 1).contiguous()
+    out = K.alloc_outputs(nrays, mod, len(freqs), dev, names=("status", "steps", "attempts", "intensity", "tau"))
+    ctx.trace_rays(rays, mod, freqs, integ, out)
+    torch.cuda.synchronize()
+    att = out["attempts"]
+    assert int(att.min()) == int(att.max()), "copies of one ray must take identical step sequences"
+    print(json.dumps({"calibration_ray": which, "ray": CALIBRATION_RAYS[which], "rays": nrays,
+                      "attempts_per_ray": int(att[0]), "steps_per_ray": int(out["steps"][0]),
+                      "total_attempts": int(att.to(torch.int64).sum())}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/* kgrt.h -- C ABI of the MI355X Kerr geodesic ray tracer with radiative transfer.
+ *
+ * Implements the method of Pu, Yun, Younsi & Yoon (2016), "Odyssey": rays are
+ * traced backwards in time from a flat image plane (section 2.2, Eqs. (18)-(26))
+ * through Kerr spacetime (Eq. (1)) by integrating the six first-order
+ * equations of section 2.1 (Eqs. (4)-(5), (9), (12), (14), (15)) with an
+ * adaptive fifth-order Runge-Kutta scheme, while the optical depth and the
+ * specific intensity of section 2.3 (Eqs. (30)-(31)) are accumulated step by
+ * step along each ray.
+ *
+ * Conventions
+ *   - Units G = c = M = 1 (section 2.1). Lengths and the affine parameter are in M.
+ *   - All array arguments named *_dev are device pointers of the current HIP
+ *     device of the context; all struct arguments are host pointers and are
+ *     read during the call only.
+ *   - Every trace call is asynchronous and ordered on `stream` (a hipStream_t,
+ *     NULL = the null stream). Nothing is synchronised implicitly.
+ *   - The caller owns every input and output buffer; the library owns only the
+ *     scratch of its context (a work-queue counter and batch tables).
+ *   - Two calls on one context race if they run concurrently on different
+ *     streams (they share the work-queue counter): use one context per stream.
+ *   - Return value: KGRT_OK (0) or a negative KGRT_E_* code; kgrt_last_error()
+ *     then holds a message. Problems of single rays never fail a call: they are
+ *     reported in the per-ray status word.
+ */
+#ifndef KGRT_H
+#define KGRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define KGRT_OK 0
+#define KGRT_E_INVALID_ARG -1  /* an argument is out of its documented range */
+#define KGRT_E_HIP -2          /* a HIP runtime call failed */
+#define KGRT_E_NOMEM -3        /* device or host allocation failed */
+#define KGRT_E_NO_DEVICE -4    /* no usable GPU, or the device index is invalid */
+#define KGRT_E_UNSUPPORTED -5  /* a valid request this build does not implement */
+
+/* Per-ray status bits (int32 status output). */
+#define KGRT_CAPTURED 1            /* reached r <= r_+ (1 + horizon_delta) */
+#define KGRT_ESCAPED 2             /* p_r > 0 and r > r_obs */
+#define KGRT_CROSSED 4             /* a first equatorial crossing was recorded */
+#define KGRT_DISK_HIT 8            /* ...and it lies on the thin disk [r_in, r_out] */
+#define KGRT_MAXSTEPS 16           /* stopped at max_steps accepted steps */
+#define KGRT_UNDERFLOW 32          /* step size fell below 1e-12 max(1, r) */
+#define KGRT_NONFINITE 64          /* non-finite state or unusable start point */
+#define KGRT_FALLBACK 128          /* (surrogate) ray was re-integrated */
+#define KGRT_REFINE_UNCONVERGED 256 /* crossing Newton refinement hit its iteration cap */
+
+/* Emission models. */
+#define KGRT_MODEL_GEODESIC 0   /* geometry only: capture flag and first crossing */
+#define KGRT_MODEL_THIN_DISK 1  /* geometrically thin Keplerian disk, j = r^-3 (section 4.3) */
+#define KGRT_MODEL_TORUS 2      /* thermal-synchrotron torus (section 4.5 emissivity) */
+
+/* Integrator flags. */
+#define KGRT_STOP_AT_CROSSING 1u /* terminate each ray at its first equatorial crossing */
+
+/* ---------------------------------------------------------------- structs */
+
+/* Observer and image plane (section 2.2). Pixel (i, j), 0 <= i < nx, 0 <= j < ny,
+ * sits at the cell centre x = x_min + (i + 1/2)(x_max - x_min)/nx,
+ * y = y_min + (j + 1/2)(y_max - y_min)/ny; its output index is j*nx + i. */
+typedef struct kgrt_camera {
+    double a;            /* black-hole spin a/M, |a| < 1 */
+    double incl_deg;     /* inclination theta_obs in degrees, 0 < incl < 180 */
+    double phi_obs_deg;  /* azimuth phi_obs in degrees (finite) */
+    double r_obs;        /* observer distance in M, r_obs > 10 r_+ (the paper uses 1000) */
+    int32_t nx, ny;      /* image size, >= 0 (0 => nothing to trace) */
+    double x_min, x_max; /* image-plane extent in M, x_min < x_max */
+    double y_min, y_max; /* y_min < y_max */
+} kgrt_camera;
+
+/* Emission/absorption model. */
+typedef struct kgrt_model {
+    int32_t kind;        /* KGRT_MODEL_* */
+    int32_t reserved;    /* must be 0 */
+    /* thin disk (section 4.3): inner edge r_in (<= 0 selects r_ISCO(a)), outer edge r_out */
+    double r_in, r_out;
+    /* torus: n_e = n0 (r/r_norm)^-n_index exp(-z^2/(2 (h_over_r r)^2)), z = r cos(theta);
+     * T_e = T0 (r/r_norm)^-T_index; B^2/(8 pi) = eps_B n_e m_p c^2 / (6 r);
+     * thermal synchrotron j_nu of Eqs. (37)-(39) per steradian, Kirchhoff absorption;
+     * black-hole mass mbh_msun sets r_g; emission only for r_capture < r <= r_emit_max. */
+    double n0_cgs, r_norm, n_index, h_over_r, T0_K, T_index, eps_B, mbh_msun, r_emit_max;
+} kgrt_model;
+
+/* Adaptive Runge-Kutta controls (section 2.1). */
+typedef struct kgrt_integrator {
+    double rtol;          /* relative tolerance of the error control, 1e-14 <= rtol <= 1e-2 */
+    double hmax_frac;     /* step cap |h| <= hmax_frac * r, 0 < hmax_frac <= 1 */
+    double horizon_delta; /* capture radius r_+ (1 + horizon_delta), 0 < delta <= 0.5 */
+    int32_t max_steps;    /* accepted-step cap per ray, >= 1 */
+    uint32_t flags;       /* KGRT_STOP_AT_CROSSING */
+} kgrt_integrator;
+
+/* Per-ray outputs: device arrays of n = number of rays entries (frequency-major
+ * [nfreq][n] where noted). A NULL pointer means "do not write". */
+typedef struct kgrt_outputs {
+    int32_t* status;    /* [n] KGRT_* status bits */
+    int32_t* steps;     /* [n] accepted RK steps */
+    int32_t* attempts;  /* [n] attempted RK steps (accepted + rejected) */
+    double* r_cross;    /* [n] Boyer-Lindquist r at the first equatorial crossing, 0 if none */
+    double* g;          /* [n] redshift nu_obs/nu_emit of a Keplerian emitter there (Eq. (2)), 0 if none */
+    double* phi_cross;  /* [n] Boyer-Lindquist phi there (accumulated, not wrapped), 0 if none */
+    double* t_cross;    /* [n] coordinate time there (negative: traced backwards), 0 if none */
+    double* intensity;  /* thin disk: [n] g^3 r_c^-3 on the disk, else 0;
+                           torus: [nfreq][n] observed I_nu, erg s^-1 cm^-2 Hz^-1 sr^-1 */
+    double* i_bol;      /* thin disk: [n] g^4 r_c^-3 on the disk, else 0 */
+    double* tau;        /* torus: [nfreq][n] optical depth along the ray */
+} kgrt_outputs;
+
+/* Launch shape of the persistent integrator kernel. Zeros select defaults. */
+typedef struct kgrt_launch {
+    int32_t block;          /* threads per block: 64, 128, 256 or 512 (default 256) */
+    int32_t blocks_per_cu;  /* resident blocks per compute unit (default: occupancy limit) */
+    int32_t refill_min;     /* refill a wave only when at least this many lanes are idle (1..64, default 1) */
+    int32_t reserved;       /* must be 0 */
+} kgrt_launch;
+
+typedef struct kgrt_ctx kgrt_ctx;
+
+/* -------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device` and allocates its scratch.
+ * Returns KGRT_E_NO_DEVICE when no GPU is present or the index is invalid. */
+int kgrt_ctx_create(int device, kgrt_ctx** out);
+/* Destroys a context (NULL is a no-op). Waits for nothing: the caller must
+ * make sure no call on it is still running. */
+int kgrt_ctx_destroy(kgrt_ctx* ctx);
+/* Sets the default launch shape used by later calls (NULL restores defaults). */
+int kgrt_ctx_set_launch(kgrt_ctx* ctx, const kgrt_launch* launch);
+/* Number of compute units of the context's device. */
+int kgrt_ctx_num_cus(const kgrt_ctx* ctx);
+
+/* Validates a request without touching a GPU (the trace calls run the same
+ * checks first). cam may be NULL (ray-list mode), freqs_hz is a host array. */
+int kgrt_check_args(const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+                    const kgrt_integrator* integ);
+
+/* ---------------------------------------------------------------- tracing */
+
+/* Traces one image: one ray per pixel from the image plane of `cam` (section 2.2)
+ * until capture, escape or the step cap, with the chosen model.
+ * freqs_hz: host array of nfreq observing frequencies (torus: 1 <= nfreq <= 16,
+ * each finite and > 0; other models: ignored). Outputs have n = nx*ny entries. */
+int kgrt_trace(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz,
+               int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
+
+/* Traces a list of independent rays, each with its own spin, inclination and
+ * image-plane point: rays_dev is a device array [n][4] of (a, incl_deg, x, y);
+ * r_obs and phi_obs are shared. n >= 0 (0 is a no-op). Outputs have n entries. */
+int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_obs, double phi_obs_deg,
+                    const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+                    const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
+
+/* Error strings. kgrt_last_error returns the context's last message ("" if none). */
+const char* kgrt_strerror(int code);
+const char* kgrt_last_error(const kgrt_ctx* ctx);
+/* ABI version (major*10000 + minor*100 + patch). */
+int kgrt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KGRT_H */

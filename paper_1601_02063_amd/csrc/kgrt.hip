@@ -1,0 +1,673 @@
+// kgrt.hip -- persistent FP64 integrator kernels and the C ABI (include/kgrt.h).
+//
+// Design (gfx950, wave64):
+//  * one ray per lane, the whole ray state (6 doubles, step size, counters,
+//    per-frequency tau and I) register resident for the life of the ray;
+//  * a persistent grid sized to the device's occupancy; each wave refills its
+//    idle lanes from a global ray counter with one ballot and one atomicAdd
+//    (lane offsets from a popcount prefix), so rays of very different step
+//    counts never leave a wave waiting for its slowest member;
+//  * ray ids are image-major, so freshly claimed lanes of a wave write
+//    neighbouring pixels (coalesced SoA outputs);
+//  * per-image uniforms (spin, observer angles, capture radius, disk edges) are
+//    precomputed on the host once per image.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kgrt.h"
+#include "kgrt_device.hpp"
+
+namespace kgrt {
+
+// Everything a lane needs to start a ray of one image.
+struct ImageDesc {
+    double a, a2, r_obs, sqrt_ro2a2;
+    double sin_i, cos_i, sin_p, cos_p, phi_obs;
+    double x_min, x_w, y_min, y_w;
+    double r_cap, r_in;
+    int64_t ray_offset;
+    int32_t nx, ny;
+};
+
+struct Outputs {
+    int32_t *status, *steps, *attempts;
+    double *r_cross, *g, *phi_cross, *t_cross, *intensity, *i_bol, *tau;
+};
+
+struct KParams {
+    ImageDesc image0;           // single-image mode (nimg == 1)
+    const ImageDesc* images;    // device table, nimg > 1
+    const double* rays4;        // ray-list mode
+    unsigned long long* counter;
+    int64_t nrays;
+    int32_t nimg;
+    int32_t list_mode;
+    double list_r_obs, list_phi_obs, list_sin_p, list_cos_p;
+    // model
+    int32_t model, nf;
+    double freqs[16];
+    double r_in_cfg, r_out;
+    TorusParams torus;
+    // integrator
+    double rtol, hmax_frac, horizon_delta;
+    int32_t max_steps;
+    uint32_t flags;
+    int32_t refill_min;
+    Outputs out;
+};
+
+// ------------------------------------------------------------ ray start
+
+struct RayStart {
+    State y;
+    double a, a2, L, r_cap, r_in, r_obs;
+    bool ok;
+};
+
+// Pixel -> start state, section 2.2: Eqs. (18)-(19) image plane -> Cartesian,
+// Eqs. (20)-(22) Cartesian -> Boyer-Lindquist, Eqs. (24)-(26) rates of a ray
+// along the line of sight, Eq. (7) energy (negative root, rates scaled so
+// E = -1), Eq. (8) L_z, Eqs. (4)-(5) covariant momenta.
+__device__ __noinline__ RayStart start_ray(double a, double a2, double r_obs, double sqrt_ro2a2, double sin_i,
+                                     double cos_i, double sin_p, double cos_p, double phi_obs, double x, double y) {
+    RayStart s;
+    s.a = a;
+    s.a2 = a2;
+    s.r_obs = r_obs;
+    const double D = sqrt_ro2a2 * sin_i - y * cos_i;
+    const double xp = D * cos_p - x * sin_p;
+    const double yp = D * sin_p + x * cos_p;
+    const double zp = r_obs * cos_i + y * sin_i;
+    const double w = xp * xp + yp * yp + zp * zp - a2;
+    const double r = sqrt((w + sqrt(w * w + 4.0 * a2 * zp * zp)) / 2.0);
+    const double th = acos(zp / r);
+    const double ph = atan2(yp, xp);
+    const double R = sqrt(r * r + a2);
+    double sP, cP;
+    sincos(ph - phi_obs, &sP, &cP);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double Sigma = r * r + a2 * cs * cs;
+    double rdot = -(r * R * sn * sin_i * cP + R * R * cs * cos_i) / Sigma;
+    double thdot = (r * sn * cos_i - R * cs * sin_i * cP) / Sigma;
+    double phdot = sin_i * sP / (R * sn);
+    const double Delta = r * r - 2.0 * r + a2;
+    const double E2 = ((Sigma - 2.0 * r) / (Sigma * Delta)) * (Sigma * rdot * rdot + Sigma * Delta * thdot * thdot) +
+                      Delta * phdot * phdot * sn * sn;
+    s.ok = (E2 > 0.0) && isfinite(E2);
+    const double inv = 1.0 / sqrt(E2);
+    rdot *= inv;
+    thdot *= inv;
+    phdot *= inv;
+    s.L = (Sigma * Delta * phdot + 2.0 * a * r) * sn * sn / (Sigma - 2.0 * r);
+    s.y = State{r, th, ph, 0.0, Sigma * rdot / Delta, Sigma * thdot};
+    s.ok = s.ok && finite6(s.y) && isfinite(s.L);
+    return s;
+}
+
+__device__ inline RayStart start_from_id(const KParams& P, int64_t rid) {
+    if (P.list_mode) {
+        const double* q = P.rays4 + 4 * rid;
+        const double a = q[0], incl = q[1], x = q[2], y = q[3];
+        const double tho = incl * kPi / 180.0;
+        double si, ci;
+        sincos(tho, &si, &ci);
+        RayStart s = start_ray(a, a * a, P.list_r_obs, sqrt(P.list_r_obs * P.list_r_obs + a * a), si, ci,
+                               P.list_sin_p, P.list_cos_p, P.list_phi_obs, x, y);
+        s.r_cap = (1.0 + sqrt(1.0 - a * a)) * (1.0 + P.horizon_delta);
+        s.r_in = (P.r_in_cfg > 0.0) ? P.r_in_cfg : isco_radius(a);
+        if (!(fabs(a) < 1.0) || !(incl > 0.0 && incl < 180.0) || !isfinite(x) || !isfinite(y)) s.ok = false;
+        return s;
+    }
+    const ImageDesc* d = &P.image0;
+    if (P.nimg > 1) {
+        int lo = 0, hi = P.nimg - 1;  // last image with ray_offset <= rid
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.images[mid].ray_offset <= rid) lo = mid; else hi = mid - 1;
+        }
+        d = &P.images[lo];
+    }
+    const int64_t p = rid - d->ray_offset;
+    const int32_t i = (int32_t)(p % d->nx), j = (int32_t)(p / d->nx);
+    // cell centres, same operation order as the documented rule
+    const double x = d->x_min + ((i + 0.5) * d->x_w) / d->nx;
+    const double y = d->y_min + ((j + 0.5) * d->y_w) / d->ny;
+    RayStart s = start_ray(d->a, d->a2, d->r_obs, d->sqrt_ro2a2, d->sin_i, d->cos_i, d->sin_p, d->cos_p,
+                           d->phi_obs, x, y);
+    s.r_cap = d->r_cap;
+    s.r_in = d->r_in;
+    return s;
+}
+
+// First equatorial crossing inside an accepted step [y_k, y_k+1] over which
+// cos(theta) changes sign: Newton iteration on the step size h* from y_k,
+// starting from linear interpolation of cos(theta), each iterate one full
+// Cash-Karp step of size h* without error control; stops at |cos theta| <= 1e-13
+// or after six updates. Rare (once per ray), so kept out of line.
+__device__ __noinline__ State refine_crossing(const State yprev, double hdone, double c0, double c1, double a,
+                                              double a2, double L, bool& conv) {
+    const State kp = rhs(yprev, a, a2, L);
+    double hs = hdone * c0 / (c0 - c1);
+    State ys, yse;
+    conv = false;
+    for (int it = 0; it < 7; ++it) {
+        cash_karp(yprev, kp, hs, a, a2, L, ys, yse);
+        double sz, cz;
+        sincos(ys.th, &sz, &cz);
+        if (fabs(cz) <= 1e-13) {
+            conv = true;
+            break;
+        }
+        if (it == 6) break;
+        const double thdot = ys.pth / (ys.r * ys.r + a2 * cz * cz);
+        hs = hs + cz / (sz * thdot);
+    }
+    return ys;
+}
+
+// ------------------------------------------------------------ kernels
+
+__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
+
+template <int MODEL, int NF>
+__global__ void __launch_bounds__(256) trace_kernel(const KParams P) {
+    const int lane = __lane_id();
+    const uint64_t lane_mask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool active = false, done = false;
+    int64_t rid = 0;
+    State y{};
+    double h = 0.0, a = 0.0, a2 = 0.0, L = 0.0, r_cap = 0.0, r_in = 0.0, r_obs = 0.0;
+    int32_t steps = 0, attempts = 0, status = 0;
+    bool crossed = false;
+    double tau[NF], Iacc[NF], ap[NF], ep[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) tau[f] = Iacc[f] = ap[f] = ep[f] = 0.0;
+    const Outputs& O = P.out;
+    const int nf = P.nf;
+
+    for (;;) {
+        // ---- refill idle lanes from the global ray queue
+        const bool need = !active && !done;
+        const uint64_t want = __ballot(need);
+        if (want != 0ull) {
+            const int cnt = __popcll(want);
+            if (cnt >= P.refill_min || __ballot(active) == 0ull) {
+                const int leader = __ffsll((unsigned long long)want) - 1;
+                unsigned long long base = 0ull;
+                if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                if (need) {
+                    const unsigned long long my = base + (unsigned long long)__popcll(want & lane_mask_lt);
+                    if (my < (unsigned long long)P.nrays) {
+                        rid = (int64_t)my;
+                        const RayStart s = start_from_id(P, rid);
+                        y = s.y;
+                        a = s.a;
+                        a2 = s.a2;
+                        L = s.L;
+                        r_cap = s.r_cap;
+                        r_in = s.r_in;
+                        r_obs = s.r_obs;
+                        h = P.hmax_frac * r_obs;
+                        steps = attempts = 0;
+                        status = 0;
+                        crossed = false;
+                        if (s.ok) {
+                            active = true;
+                            if (MODEL == KGRT_MODEL_TORUS) {
+                                const double g0 = redshift(y.r, y.th, a, a2, -L);
+                                const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
+#pragma unroll
+                                for (int f = 0; f < NF; ++f) {
+                                    tau[f] = 0.0;
+                                    Iacc[f] = 0.0;
+                                    if (f < nf) torus_coeffs(q, P.torus, g0, P.freqs[f], ap[f], ep[f]);
+                                }
+                            }
+                        } else {
+                            // unusable start point: report and move on
+                            if (O.status) O.status[rid] = ST_NONFINITE;
+                            if (O.steps) O.steps[rid] = 0;
+                            if (O.attempts) O.attempts[rid] = 0;
+                            if (O.r_cross) O.r_cross[rid] = 0.0;
+                            if (O.g) O.g[rid] = 0.0;
+                            if (O.phi_cross) O.phi_cross[rid] = 0.0;
+                            if (O.t_cross) O.t_cross[rid] = 0.0;
+                            if (O.i_bol) O.i_bol[rid] = 0.0;
+                            if (MODEL == KGRT_MODEL_TORUS) {
+                                for (int f = 0; f < nf; ++f) {
+                                    if (O.intensity) O.intensity[(int64_t)f * P.nrays + rid] = 0.0;
+                                    if (O.tau) O.tau[(int64_t)f * P.nrays + rid] = 0.0;
+                                }
+                            } else if (O.intensity) {
+                                O.intensity[rid] = 0.0;
+                            }
+                        }
+                    } else {
+                        done = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(active || !done) == 0ull) break;
+        if (!active) continue;
+
+        // ---- one adaptive Cash-Karp attempt (section 2.1)
+        bool terminate = false;
+        const State k1 = rhs(y, a, a2, L);
+        State yn, ye;
+        cash_karp(y, k1, h, a, a2, L, yn, ye);
+        ++attempts;
+        double errmax = 0.0;
+        {
+            const double tol = P.rtol;
+#define KGRT_ERR(f)                                                              \
+    {                                                                            \
+        const double e = fabs(ye.f) / (tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12)); \
+        if (e > errmax) errmax = e;                                              \
+    }
+            KGRT_ERR(r) KGRT_ERR(th) KGRT_ERR(ph) KGRT_ERR(t) KGRT_ERR(pr) KGRT_ERR(pth)
+#undef KGRT_ERR
+        }
+        if (!(errmax <= 1.0)) {
+            // rejected: shrink and retry
+            if (!isfinite(errmax)) errmax = 1e10;
+            double shrink = 0.9 * pow(errmax, -0.25);
+            if (shrink < 0.1) shrink = 0.1;
+            h = h * shrink;
+            if (fabs(h) < 1e-12 * fmax(1.0, y.r)) {
+                status |= ST_UNDERFLOW;
+                terminate = true;
+            }
+        } else {
+            // accepted
+            const double hdone = h;
+            double hnext = (errmax > 1.89e-4) ? h * (0.9 * pow(errmax, -0.2)) : h * 5.0;
+            ++steps;
+            const State yprev = y;
+            y = yn;
+            if (!finite6(y)) {
+                status |= ST_NONFINITE;
+                terminate = true;
+            } else {
+                if (MODEL == KGRT_MODEL_TORUS) {
+                    // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
+                    // each accepted endpoint, exponential-trapezoid increment
+                    const double g1 = redshift(y.r, y.th, a, a2, -L);
+                    const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        if (f < nf) {
+                            double a1, e1;
+                            torus_coeffs(q, P.torus, g1, P.freqs[f], a1, e1);
+                            const double dtau = hdone * (ap[f] + a1) / 2.0;
+                            const double phi = (dtau > 0.0) ? -expm1(-dtau) / dtau : 1.0;
+                            Iacc[f] += exp(-tau[f]) * hdone * (ep[f] + e1) / 2.0 * phi;
+                            tau[f] += dtau;
+                            ap[f] = a1;
+                            ep[f] = e1;
+                        }
+                    }
+                } else if (!crossed) {
+                    // first equatorial crossing: Newton iteration on the step size from
+                    // y_k, each iterate one full Cash-Karp step without error control
+                    double c0, c1, sdum;
+                    sincos(yprev.th, &sdum, &c0);
+                    sincos(y.th, &sdum, &c1);
+                    if ((c0 > 0.0 && c1 <= 0.0) || (c0 < 0.0 && c1 >= 0.0)) {
+                        crossed = true;
+                        bool conv = false;
+                        const State ys = refine_crossing(yprev, hdone, c0, c1, a, a2, L, conv);
+                        if (!conv) status |= ST_REFINE_UNCONVERGED;
+                        const double rc = ys.r;
+                        if (rc > r_cap) {
+                            status |= ST_CROSSED;
+                            const double g = redshift(rc, kPi / 2.0, a, a2, -L);
+                            double I = 0.0, Ib = 0.0;
+                            if (P.model == KGRT_MODEL_THIN_DISK && rc >= r_in && rc <= P.r_out) {
+                                status |= ST_DISK_HIT;
+                                const double j = 1.0 / (rc * rc * rc);
+                                I = g * g * g * j;
+                                Ib = g * g * g * g * j;
+                            }
+                            if (O.r_cross) O.r_cross[rid] = rc;
+                            if (O.g) O.g[rid] = g;
+                            if (O.phi_cross) O.phi_cross[rid] = ys.ph;
+                            if (O.t_cross) O.t_cross[rid] = ys.t;
+                            if (O.intensity) O.intensity[rid] = I;
+                            if (O.i_bol) O.i_bol[rid] = Ib;
+                            if (P.flags & KGRT_STOP_AT_CROSSING) terminate = true;
+                        }
+                    }
+                }
+                if (!terminate) {
+                    if (y.r <= r_cap) {
+                        status |= ST_CAPTURED;
+                        terminate = true;
+                    } else if (y.pr > 0.0 && y.r > r_obs) {
+                        status |= ST_ESCAPED;
+                        terminate = true;
+                    } else if (steps >= P.max_steps) {
+                        status |= ST_MAXSTEPS;
+                        terminate = true;
+                    }
+                }
+            }
+            const double hcap = P.hmax_frac * y.r;
+            if (hnext > hcap) hnext = hcap;
+            h = hnext;
+        }
+
+        if (terminate) {
+            if (O.status) O.status[rid] = status;
+            if (O.steps) O.steps[rid] = steps;
+            if (O.attempts) O.attempts[rid] = attempts;
+            if (MODEL == KGRT_MODEL_TORUS) {
+                for (int f = 0; f < NF; ++f) {
+                    if (f < nf) {
+                        if (O.intensity) O.intensity[(int64_t)f * P.nrays + rid] = Iacc[f];
+                        if (O.tau) O.tau[(int64_t)f * P.nrays + rid] = tau[f];
+                    }
+                }
+            }
+            if (!(status & ST_CROSSED)) {
+                if (O.r_cross) O.r_cross[rid] = 0.0;
+                if (O.g) O.g[rid] = 0.0;
+                if (O.phi_cross) O.phi_cross[rid] = 0.0;
+                if (O.t_cross) O.t_cross[rid] = 0.0;
+                if (O.i_bol) O.i_bol[rid] = 0.0;
+                if (MODEL != KGRT_MODEL_TORUS && O.intensity) O.intensity[rid] = 0.0;
+            }
+            active = false;
+        }
+    }
+}
+
+}  // namespace kgrt
+
+// =================================================================== host
+
+using namespace kgrt;
+
+struct kgrt_ctx {
+    int device = 0;
+    int num_cus = 0;
+    unsigned long long* counter = nullptr;
+    kgrt_launch launch{};
+    std::string last_error;
+};
+
+namespace {
+
+int fail(kgrt_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->last_error = msg;
+    return code;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+// Argument checks shared by every entry point (see include/kgrt.h).
+int check(std::string& msg, const kgrt_camera* cam, const kgrt_model* m, const double* freqs, int32_t nfreq,
+          const kgrt_integrator* in) {
+    if (cam) {
+        if (!(std::fabs(cam->a) < 1.0)) { msg = "camera.a must satisfy |a| < 1"; return KGRT_E_INVALID_ARG; }
+        if (!(cam->incl_deg > 0.0 && cam->incl_deg < 180.0)) { msg = "camera.incl_deg must be in (0, 180)"; return KGRT_E_INVALID_ARG; }
+        if (!is_finite(cam->phi_obs_deg)) { msg = "camera.phi_obs_deg must be finite"; return KGRT_E_INVALID_ARG; }
+        const double rplus = 1.0 + std::sqrt(1.0 - cam->a * cam->a);
+        if (!(is_finite(cam->r_obs) && cam->r_obs > 10.0 * rplus)) { msg = "camera.r_obs must exceed 10 r_+"; return KGRT_E_INVALID_ARG; }
+        if (cam->nx < 0 || cam->ny < 0) { msg = "camera.nx, ny must be >= 0"; return KGRT_E_INVALID_ARG; }
+        if (!(is_finite(cam->x_min) && is_finite(cam->x_max) && cam->x_min < cam->x_max)) { msg = "camera x extent invalid"; return KGRT_E_INVALID_ARG; }
+        if (!(is_finite(cam->y_min) && is_finite(cam->y_max) && cam->y_min < cam->y_max)) { msg = "camera y extent invalid"; return KGRT_E_INVALID_ARG; }
+    }
+    if (!m) { msg = "model is NULL"; return KGRT_E_INVALID_ARG; }
+    if (m->reserved != 0) { msg = "model.reserved must be 0"; return KGRT_E_INVALID_ARG; }
+    if (m->kind == KGRT_MODEL_THIN_DISK || m->kind == KGRT_MODEL_GEODESIC) {
+        if (m->kind == KGRT_MODEL_THIN_DISK) {
+            if (!(is_finite(m->r_out) && m->r_out > 0.0)) { msg = "model.r_out must be finite and > 0"; return KGRT_E_INVALID_ARG; }
+            if (!is_finite(m->r_in) || (m->r_in > 0.0 && !(m->r_in < m->r_out))) { msg = "model.r_in must be <= 0 or < r_out"; return KGRT_E_INVALID_ARG; }
+        }
+    } else if (m->kind == KGRT_MODEL_TORUS) {
+        const double v[9] = {m->n0_cgs, m->r_norm, m->n_index, m->h_over_r, m->T0_K, m->T_index, m->eps_B, m->mbh_msun, m->r_emit_max};
+        for (double x : v) if (!is_finite(x)) { msg = "torus parameters must be finite"; return KGRT_E_INVALID_ARG; }
+        if (!(m->n0_cgs >= 0.0 && m->r_norm > 0.0 && m->h_over_r > 0.0 && m->T0_K > 0.0 && m->eps_B >= 0.0 &&
+              m->mbh_msun > 0.0 && m->r_emit_max > 0.0)) { msg = "torus parameters out of range"; return KGRT_E_INVALID_ARG; }
+        if (nfreq < 1 || nfreq > 16) { msg = "torus needs 1 <= nfreq <= 16"; return KGRT_E_INVALID_ARG; }
+        if (!freqs) { msg = "freqs_hz is NULL"; return KGRT_E_INVALID_ARG; }
+        for (int f = 0; f < nfreq; ++f)
+            if (!(is_finite(freqs[f]) && freqs[f] > 0.0)) { msg = "frequencies must be finite and > 0"; return KGRT_E_INVALID_ARG; }
+    } else {
+        msg = "unknown model.kind";
+        return KGRT_E_INVALID_ARG;
+    }
+    if (!in) { msg = "integrator is NULL"; return KGRT_E_INVALID_ARG; }
+    if (!(in->rtol >= 1e-14 && in->rtol <= 1e-2)) { msg = "integrator.rtol must be in [1e-14, 1e-2]"; return KGRT_E_INVALID_ARG; }
+    if (!(in->hmax_frac > 0.0 && in->hmax_frac <= 1.0)) { msg = "integrator.hmax_frac must be in (0, 1]"; return KGRT_E_INVALID_ARG; }
+    if (!(in->horizon_delta > 0.0 && in->horizon_delta <= 0.5)) { msg = "integrator.horizon_delta must be in (0, 0.5]"; return KGRT_E_INVALID_ARG; }
+    if (in->max_steps < 1) { msg = "integrator.max_steps must be >= 1"; return KGRT_E_INVALID_ARG; }
+    if (in->flags & ~KGRT_STOP_AT_CROSSING) { msg = "unknown integrator flags"; return KGRT_E_INVALID_ARG; }
+    return KGRT_OK;
+}
+
+ImageDesc make_image(const kgrt_camera* c, const kgrt_model* m, double horizon_delta, int64_t offset) {
+    // Same host libm as any CPU reference, computed once per image.
+    ImageDesc d{};
+    const double pi = 3.14159265358979323846;
+    const double tho = c->incl_deg * pi / 180.0, pho = c->phi_obs_deg * pi / 180.0;
+    d.a = c->a;
+    d.a2 = c->a * c->a;
+    d.r_obs = c->r_obs;
+    d.sqrt_ro2a2 = std::sqrt(c->r_obs * c->r_obs + c->a * c->a);
+    d.sin_i = std::sin(tho);
+    d.cos_i = std::cos(tho);
+    d.sin_p = std::sin(pho);
+    d.cos_p = std::cos(pho);
+    d.phi_obs = pho;
+    d.x_min = c->x_min;
+    d.x_w = c->x_max - c->x_min;
+    d.y_min = c->y_min;
+    d.y_w = c->y_max - c->y_min;
+    d.r_cap = (1.0 + std::sqrt(1.0 - c->a * c->a)) * (1.0 + horizon_delta);
+    d.r_in = (m->r_in > 0.0) ? m->r_in : isco_radius(c->a);
+    d.ray_offset = offset;
+    d.nx = c->nx;
+    d.ny = c->ny;
+    return d;
+}
+
+void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t nfreq, const kgrt_integrator* in,
+                 const kgrt_outputs* o, const kgrt_ctx* ctx) {
+    P.model = m->kind;
+    P.nf = (m->kind == KGRT_MODEL_TORUS) ? nfreq : 0;
+    for (int f = 0; f < 16; ++f) P.freqs[f] = (f < P.nf) ? freqs[f] : 0.0;
+    P.r_in_cfg = m->r_in;
+    P.r_out = m->r_out;
+    TorusParams& T = P.torus;
+    T.n0 = m->n0_cgs;
+    T.inv_rnorm = (m->r_norm > 0.0) ? 1.0 / m->r_norm : 0.0;
+    T.n_index = m->n_index;
+    T.inv_2h2 = (m->h_over_r > 0.0) ? 1.0 / (2.0 * m->h_over_r * m->h_over_r) : 0.0;
+    T.T0 = m->T0_K;
+    T.T_index = m->T_index;
+    T.eps_B = m->eps_B;
+    T.rg = kGMsun * m->mbh_msun / (kC * kC);
+    T.r_emit_max = m->r_emit_max;
+    P.rtol = in->rtol;
+    P.hmax_frac = in->hmax_frac;
+    P.horizon_delta = in->horizon_delta;
+    P.max_steps = in->max_steps;
+    P.flags = in->flags;
+    P.refill_min = (ctx->launch.refill_min >= 1 && ctx->launch.refill_min <= 64) ? ctx->launch.refill_min : 1;
+    P.out = Outputs{o->status, o->steps, o->attempts, o->r_cross, o->g, o->phi_cross, o->t_cross,
+                    o->intensity, o->i_bol, o->tau};
+    P.counter = ctx->counter;
+}
+
+template <int MODEL, int NF>
+int launch_one(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
+    const int block = (ctx->launch.block == 64 || ctx->launch.block == 128 || ctx->launch.block == 512) ? ctx->launch.block : 256;
+    auto kern = trace_kernel<MODEL, NF>;
+    int per_cu = ctx->launch.blocks_per_cu;
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+    }
+    const int64_t need = (P.nrays + block - 1) / block;
+    const int64_t cap = (int64_t)ctx->num_cus * per_cu;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, ctx->counter);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, P);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, KGRT_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return KGRT_OK;
+}
+
+int dispatch(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
+    if (P.model != KGRT_MODEL_TORUS) return launch_one<KGRT_MODEL_THIN_DISK, 1>(ctx, P, st);
+    if (P.nf <= 1) return launch_one<KGRT_MODEL_TORUS, 1>(ctx, P, st);
+    if (P.nf <= 2) return launch_one<KGRT_MODEL_TORUS, 2>(ctx, P, st);
+    if (P.nf <= 4) return launch_one<KGRT_MODEL_TORUS, 4>(ctx, P, st);
+    if (P.nf <= 8) return launch_one<KGRT_MODEL_TORUS, 8>(ctx, P, st);
+    return launch_one<KGRT_MODEL_TORUS, 16>(ctx, P, st);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int kgrt_version(void) { return 100; }
+
+const char* kgrt_strerror(int code) {
+    switch (code) {
+        case KGRT_OK: return "ok";
+        case KGRT_E_INVALID_ARG: return "invalid argument";
+        case KGRT_E_HIP: return "HIP runtime error";
+        case KGRT_E_NOMEM: return "out of memory";
+        case KGRT_E_NO_DEVICE: return "no usable GPU";
+        case KGRT_E_UNSUPPORTED: return "unsupported request";
+        default: return "unknown error";
+    }
+}
+
+const char* kgrt_last_error(const kgrt_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int kgrt_check_args(const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+                    const kgrt_integrator* integ) {
+    std::string msg;
+    return check(msg, cam, model, freqs_hz, nfreq, integ);
+}
+
+int kgrt_ctx_create(int device, kgrt_ctx** out) {
+    if (!out) return KGRT_E_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return KGRT_E_NO_DEVICE;
+    if (device < 0 || device >= n) return KGRT_E_NO_DEVICE;
+    auto* ctx = new (std::nothrow) kgrt_ctx();
+    if (!ctx) return KGRT_E_NOMEM;
+    ctx->device = device;
+    DeviceGuard g(device);
+    if (!g.ok) { delete ctx; return KGRT_E_NO_DEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return KGRT_E_HIP; }
+    ctx->num_cus = prop.multiProcessorCount;
+    if (hipMalloc(&ctx->counter, sizeof(unsigned long long)) != hipSuccess) { delete ctx; return KGRT_E_NOMEM; }
+    *out = ctx;
+    return KGRT_OK;
+}
+
+int kgrt_ctx_destroy(kgrt_ctx* ctx) {
+    if (!ctx) return KGRT_OK;
+    {
+        DeviceGuard g(ctx->device);
+        if (ctx->counter) (void)hipFree(ctx->counter);
+    }
+    delete ctx;
+    return KGRT_OK;
+}
+
+int kgrt_ctx_set_launch(kgrt_ctx* ctx, const kgrt_launch* l) {
+    if (!ctx) return KGRT_E_INVALID_ARG;
+    if (!l) { ctx->launch = kgrt_launch{}; return KGRT_OK; }
+    if (!(l->block == 0 || l->block == 64 || l->block == 128 || l->block == 256 || l->block == 512))
+        return fail(ctx, KGRT_E_INVALID_ARG, "launch.block must be 0, 64, 128, 256 or 512");
+    if (l->block == 512) return fail(ctx, KGRT_E_UNSUPPORTED, "launch.block 512 exceeds the kernel's launch bounds");
+    if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64) return fail(ctx, KGRT_E_INVALID_ARG, "launch.blocks_per_cu must be in [0, 64]");
+    if (l->refill_min < 0 || l->refill_min > 64) return fail(ctx, KGRT_E_INVALID_ARG, "launch.refill_min must be in [0, 64]");
+    if (l->reserved != 0) return fail(ctx, KGRT_E_INVALID_ARG, "launch.reserved must be 0");
+    ctx->launch = *l;
+    return KGRT_OK;
+}
+
+int kgrt_ctx_num_cus(const kgrt_ctx* ctx) { return ctx ? ctx->num_cus : 0; }
+
+int kgrt_trace(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+               const kgrt_integrator* integ, const kgrt_outputs* out, void* stream) {
+    if (!ctx) return KGRT_E_INVALID_ARG;
+    if (!cam) return fail(ctx, KGRT_E_INVALID_ARG, "camera is NULL");
+    if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "outputs is NULL");
+    std::string msg;
+    int rc = check(msg, cam, model, freqs_hz, nfreq, integ);
+    if (rc != KGRT_OK) return fail(ctx, rc, msg);
+    const int64_t n = (int64_t)cam->nx * (int64_t)cam->ny;
+    if (n == 0) return KGRT_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    KParams P{};
+    P.image0 = make_image(cam, model, integ->horizon_delta, 0);
+    P.images = nullptr;
+    P.nimg = 1;
+    P.list_mode = 0;
+    P.nrays = n;
+    fill_common(P, model, freqs_hz, nfreq, integ, out, ctx);
+    return dispatch(ctx, P, (hipStream_t)stream);
+}
+
+int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_obs, double phi_obs_deg,
+                    const kgrt_model* model, const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ,
+                    const kgrt_outputs* out, void* stream) {
+    if (!ctx) return KGRT_E_INVALID_ARG;
+    if (n < 0) return fail(ctx, KGRT_E_INVALID_ARG, "n must be >= 0");
+    if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "outputs is NULL");
+    if (!(is_finite(r_obs) && r_obs > 20.0)) return fail(ctx, KGRT_E_INVALID_ARG, "r_obs must be finite and > 20");
+    if (!is_finite(phi_obs_deg)) return fail(ctx, KGRT_E_INVALID_ARG, "phi_obs_deg must be finite");
+    std::string msg;
+    int rc = check(msg, nullptr, model, freqs_hz, nfreq, integ);
+    if (rc != KGRT_OK) return fail(ctx, rc, msg);
+    if (n == 0) return KGRT_OK;
+    if (!rays_dev) return fail(ctx, KGRT_E_INVALID_ARG, "rays_dev is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    KParams P{};
+    P.images = nullptr;
+    P.nimg = 1;
+    P.list_mode = 1;
+    P.rays4 = rays_dev;
+    P.nrays = n;
+    const double pho = phi_obs_deg * 3.14159265358979323846 / 180.0;
+    P.list_r_obs = r_obs;
+    P.list_phi_obs = pho;
+    P.list_sin_p = std::sin(pho);
+    P.list_cos_p = std::cos(pho);
+    fill_common(P, model, freqs_hz, nfreq, integ, out, ctx);
+    return dispatch(ctx, P, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+"""Python binding of the kgrt C ABI (include/kgrt.h): argument marshalling only.
+
+PyTorch provides device memory (output tensors) and streams; every step of the
+ray tracing runs in the HIP kernels of ``libkgrt.so``. There is no fallback:
+if the library is missing or no GPU is usable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field, fields
+from typing import Dict, Iterable, Optional, Sequence
+
+import torch  # loads the HIP runtime first, so libkgrt.so binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkgrt.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "kgrt.h")
+
+OK, E_INVALID_ARG, E_HIP, E_NOMEM, E_NO_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+CAPTURED, ESCAPED, CROSSED, DISK_HIT = 1, 2, 4, 8
+MAXSTEPS, UNDERFLOW, NONFINITE, FALLBACK, REFINE_UNCONVERGED = 16, 32, 64, 128, 256
+MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS = 0, 1, 2
+STOP_AT_CROSSING = 1
+
+
+class KgrtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"kgrt error {code}: {msg}")
+        self.code = code
+
+
+class CCamera(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("incl_deg", ctypes.c_double), ("phi_obs_deg", ctypes.c_double),
+                ("r_obs", ctypes.c_double), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double)]
+
+
+class CModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
+                ("n0_cgs", ctypes.c_double), ("r_norm", ctypes.c_double), ("n_index", ctypes.c_double),
+                ("h_over_r", ctypes.c_double), ("T0_K", ctypes.c_double), ("T_index", ctypes.c_double),
+                ("eps_B", ctypes.c_double), ("mbh_msun", ctypes.c_double), ("r_emit_max", ctypes.c_double)]
+
+
+class CIntegrator(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("hmax_frac", ctypes.c_double), ("horizon_delta", ctypes.c_double),
+                ("max_steps", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+OUTPUT_FIELDS = ("status", "steps", "attempts", "r_cross", "g", "phi_cross", "t_cross", "intensity", "i_bol", "tau")
+
+
+class COutputs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in OUTPUT_FIELDS]
+
+
+class CLaunch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("refill_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+# ---------------------------------------------------------------- parameters
+
+@dataclass
+class Camera:
+    a: float = 0.9
+    incl_deg: float = 60.0
+    nx: int = 64
+    ny: int = 64
+    x_min: float = -15.0
+    x_max: float = 15.0
+    y_min: float = -15.0
+    y_max: float = 15.0
+    r_obs: float = 1000.0
+    phi_obs_deg: float = 0.0
+
+    def c(self) -> CCamera:
+        return CCamera(self.a, self.incl_deg, self.phi_obs_deg, self.r_obs, self.nx, self.ny,
+                       self.x_min, self.x_max, self.y_min, self.y_max)
+
+
+@dataclass
+class Model:
+    kind: int = MODEL_THIN_DISK
+    r_in: float = 0.0
+    r_out: float = 20.0
+    n0_cgs: float = 1e6
+    r_norm: float = 2.0
+    n_index: float = 1.1
+    h_over_r: float = 0.3
+    T0_K: float = 1e11
+    T_index: float = 0.84
+    eps_B: float = 0.1
+    mbh_msun: float = 4e6
+    r_emit_max: float = 1000.0
+
+    def c(self) -> CModel:
+        return CModel(self.kind, 0, self.r_in, self.r_out, self.n0_cgs, self.r_norm, self.n_index, self.h_over_r,
+                      self.T0_K, self.T_index, self.eps_B, self.mbh_msun, self.r_emit_max)
+
+
+@dataclass
+class Integrator:
+    rtol: float = 1e-8
+    hmax_frac: float = 0.05
+    horizon_delta: float = 1e-3
+    max_steps: int = 100000
+    flags: int = 0
+
+    def c(self) -> CIntegrator:
+        return CIntegrator(self.rtol, self.hmax_frac, self.horizon_delta, self.max_steps, self.flags)
+
+
+# ---------------------------------------------------------------- library
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libkgrt.so (built by ``paper_1601_02063_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_02063_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, vp, i32, i64, d = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.kgrt_ctx_create.argtypes, L.kgrt_ctx_create.restype = [ctypes.c_int, P(vp)], ctypes.c_int
+        L.kgrt_ctx_destroy.argtypes, L.kgrt_ctx_destroy.restype = [vp], ctypes.c_int
+        L.kgrt_ctx_set_launch.argtypes, L.kgrt_ctx_set_launch.restype = [vp, P(CLaunch)], ctypes.c_int
+        L.kgrt_ctx_num_cus.argtypes, L.kgrt_ctx_num_cus.restype = [vp], ctypes.c_int
+        L.kgrt_check_args.argtypes = [P(CCamera), P(CModel), P(d), i32, P(CIntegrator)]
+        L.kgrt_check_args.restype = ctypes.c_int
+        L.kgrt_trace.argtypes = [vp, P(CCamera), P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
+        L.kgrt_trace.restype = ctypes.c_int
+        L.kgrt_trace_rays.argtypes = [vp, vp, i64, d, d, P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
+        L.kgrt_trace_rays.restype = ctypes.c_int
+        L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
+        L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
+        L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _freqs(freqs: Sequence[float]):
+    arr = (ctypes.c_double * max(1, len(freqs)))(*[float(f) for f in freqs])
+    return arr, len(freqs)
+
+
+def check_args(camera: Optional[Camera], model: Model, freqs: Sequence[float], integ: Integrator) -> int:
+    """Host-side validation only (no GPU needed): returns the kgrt code."""
+    fa, nf = _freqs(freqs)
+    cam = ctypes.byref(camera.c()) if camera is not None else None
+    return lib().kgrt_check_args(cam, ctypes.byref(model.c()), fa, nf, ctypes.byref(integ.c()))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, n: int, device: torch.device) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or t.device != device:
+        raise ValueError("output tensors must live on the context's GPU")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"output tensor must be contiguous {dtype} with >= {n} elements")
+    return t.data_ptr()
+
+
+class Context:
+    """A kgrt context on one GPU (owns the work-queue counter)."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = lib().kgrt_ctx_create(device, ctypes.byref(h))
+        if rc != OK:
+            raise KgrtError(rc, lib().kgrt_strerror(rc).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kgrt_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != OK:
+            raise KgrtError(rc, lib().kgrt_last_error(self._h).decode())
+
+    @property
+    def num_cus(self) -> int:
+        return lib().kgrt_ctx_num_cus(self._h)
+
+    def set_launch(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0):
+        self._check(lib().kgrt_ctx_set_launch(self._h, ctypes.byref(CLaunch(block, blocks_per_cu, refill_min, 0))))
+
+    def _outputs(self, outs: Dict[str, torch.Tensor], n: int, nf: int, model: Model) -> COutputs:
+        o = COutputs()
+        for name in OUTPUT_FIELDS:
+            t = outs.get(name)
+            if name in ("status", "steps", "attempts"):
+                setattr(o, name, _ptr(t, torch.int32, n, self.device))
+            else:
+                per = n * nf if (model.kind == MODEL_TORUS and name in ("intensity", "tau")) else n
+                setattr(o, name, _ptr(t, torch.float64, per, self.device))
+        return o
+
+    def trace(self, camera: Camera, model: Model, freqs: Sequence[float], integ: Integrator,
+              outs: Dict[str, torch.Tensor], stream=None):
+        """kgrt_trace on caller-owned output tensors (see include/kgrt.h for layouts)."""
+        n = camera.nx * camera.ny
+        fa, nf = _freqs(freqs)
+        o = self._outputs(outs, n, max(nf, 1), model)
+        self._check(lib().kgrt_trace(self._h, ctypes.byref(camera.c()), ctypes.byref(model.c()), fa, nf,
+                                     ctypes.byref(integ.c()), ctypes.byref(o), _stream_handle(stream)))
+
+    def trace_rays(self, rays: torch.Tensor, model: Model, freqs: Sequence[float], integ: Integrator,
+                   outs: Dict[str, torch.Tensor], r_obs: float = 1000.0, phi_obs_deg: float = 0.0, stream=None):
+        """kgrt_trace_rays: rays is a contiguous float64 [n, 4] tensor of (a, incl_deg, x, y)."""
+        if rays.dtype != torch.float64 or not rays.is_contiguous() or rays.dim() != 2 or rays.shape[1] != 4:
+            raise ValueError("rays must be a contiguous float64 tensor of shape [n, 4]")
+        if rays.device != self.device:
+            raise ValueError("rays must live on the context's GPU")
+        n = rays.shape[0]
+        fa, nf = _freqs(freqs)
+        o = self._outputs(outs, n, max(nf, 1), model)
+        self._check(lib().kgrt_trace_rays(self._h, rays.data_ptr() if n else None, n, r_obs, phi_obs_deg,
+                                          ctypes.byref(model.c()), fa, nf, ctypes.byref(integ.c()),
+                                          ctypes.byref(o), _stream_handle(stream)))
+
+
+def alloc_outputs(n: int, model: Model, nfreq: int, device, names: Iterable[str] = OUTPUT_FIELDS):
+    """Allocates output tensors for n rays (torus intensity/tau are [nfreq, n])."""
+    out = {}
+    for name in names:
+        if name in ("status", "steps", "attempts"):
+            out[name] = torch.empty(n, dtype=torch.int32, device=device)
+        elif model.kind == MODEL_TORUS and name in ("intensity", "tau"):
+            out[name] = torch.empty((max(nfreq, 1), n), dtype=torch.float64, device=device)
+        elif model.kind != MODEL_TORUS and name == "tau":
+            continue
+        else:
+            out[name] = torch.empty(n, dtype=torch.float64, device=device)
+    return out
+
+
+def trace_image(ctx: Context, camera: Camera, model: Model, freqs: Sequence[float], integ: Integrator,
+                names: Iterable[str] = OUTPUT_FIELDS, stream=None) -> Dict[str, torch.Tensor]:
+    """Allocates outputs and traces one image (asynchronous on `stream`)."""
+    out = alloc_outputs(camera.nx * camera.ny, model, len(freqs), ctx.device, names)
+    ctx.trace(camera, model, freqs, integ, out, stream)
+    return out

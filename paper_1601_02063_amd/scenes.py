@@ -1,0 +1,83 @@
+"""Seeded synthetic workloads (parameters and random draws only, no physics).
+
+Shared by the tests, the benchmark and the CPU reference runs so that both
+sides see identical inputs. Values are plain dicts of floats/ints:
+
+  * thin_disk_image  -- a = 0.9, inclination 60 deg, observer at 1000 M,
+    64x64 pixels over +-15 M, Keplerian thin disk from the ISCO to 20 M with
+    emissivity r^-3, relative tolerance 1e-8, step cap 0.05 r.
+  * torus_image      -- a = 0.94, inclination 17 deg, n x n pixels (n = 1024 by
+    default) over +-20 M, optically thin thermal-synchrotron torus at 230 GHz,
+    step cap 0.02 r.
+  * batch_scenes     -- 256 images with sizes drawn from {64, 128, 256, 512}^2,
+    spin U[0, 0.998], inclination U[1, 89] deg (drawn in that order per image
+    from numpy PCG64(seed)), torus at 8 log-spaced frequencies 86-690 GHz.
+  * label_rays       -- (a, incl, x, y) with a ~ U[0, 0.998], incl ~ U[1, 89] deg,
+    x, y ~ U[-15, 15] M.
+  * projection_image -- the timing workload of the paper's Table 1: a = 0.95,
+    inclination 60 deg, first-crossing projection, +-15 M.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+R_OBS = 1000.0  # observer distance used throughout the paper's section 2.2
+
+TORUS = dict(kind=2, n0_cgs=1e6, r_norm=2.0, n_index=1.1, h_over_r=0.3, T0_K=1e11, T_index=0.84,
+             eps_B=0.1, mbh_msun=4e6, r_emit_max=R_OBS)
+THIN_DISK = dict(kind=1, r_in=0.0, r_out=20.0)
+
+
+def batch_frequencies() -> list:
+    """Eight observing frequencies log-spaced from 86 to 690 GHz."""
+    return [86e9 * (690.0 / 86.0) ** (k / 7.0) for k in range(8)]
+
+
+def thin_disk_image(n: int = 64, a: float = 0.9, incl_deg: float = 60.0, half: float = 15.0) -> dict:
+    return dict(camera=dict(a=a, incl_deg=incl_deg, nx=n, ny=n, x_min=-half, x_max=half, y_min=-half, y_max=half,
+                            r_obs=R_OBS, phi_obs_deg=0.0),
+                model=dict(THIN_DISK), freqs=[],
+                integ=dict(rtol=1e-8, hmax_frac=0.05, horizon_delta=1e-3, max_steps=100000, flags=0))
+
+
+def torus_image(n: int = 1024, a: float = 0.94, incl_deg: float = 17.0, half: float = 20.0,
+                freqs=(230e9,)) -> dict:
+    return dict(camera=dict(a=a, incl_deg=incl_deg, nx=n, ny=n, x_min=-half, x_max=half, y_min=-half, y_max=half,
+                            r_obs=R_OBS, phi_obs_deg=0.0),
+                model=dict(TORUS), freqs=list(freqs),
+                integ=dict(rtol=1e-8, hmax_frac=0.02, horizon_delta=1e-3, max_steps=100000, flags=0))
+
+
+def projection_image(n: int, a: float = 0.95, incl_deg: float = 60.0, half: float = 15.0) -> dict:
+    w = thin_disk_image(n, a, incl_deg, half)
+    w["model"] = dict(kind=0, r_in=0.0, r_out=20.0)
+    w["integ"]["flags"] = 1  # stop at the first equatorial crossing
+    return w
+
+
+def batch_scenes(seed: int = 1603, nimg: int = 256) -> list:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = (64, 128, 256, 512)
+    out = []
+    for _ in range(nimg):
+        n = int(sizes[rng.integers(0, 4)])
+        a = float(rng.uniform(0.0, 0.998))
+        inc = float(rng.uniform(1.0, 89.0))
+        out.append(torus_image(n, a, inc, 20.0, batch_frequencies()))
+    return out
+
+
+def label_rays(n: int, seed: int = 1604) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rays = np.empty((n, 4))
+    rays[:, 0] = rng.uniform(0.0, 0.998, n)
+    rays[:, 1] = rng.uniform(1.0, 89.0, n)
+    rays[:, 2] = rng.uniform(-15.0, 15.0, n)
+    rays[:, 3] = rng.uniform(-15.0, 15.0, n)
+    return rays
+
+
+def sample_pixels(nx: int, ny: int, k: int, seed: int) -> np.ndarray:
+    """k distinct pixel indices (j*nx + i) drawn without replacement."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(nx * ny, size=min(k, nx * ny), replace=False))

@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, its struct layouts match the header, and argument validation works."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "kgrt.h")
+LIB = os.path.join(ROOT, "paper_1601_02063_amd", "libkgrt.so")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kgrt_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not os.path.exists(LIB):
+        pytest.fail("libkgrt.so is not built (run __graft_entry__.build())")
+    from paper_1601_02063_amd import kgrt
+    return kgrt
+
+
+def test_library_exports_every_declared_symbol(K):
+    names = _declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_header(K):
+    probe = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "kgrt.h"
+#define P(T) printf(#T " %zu\n", sizeof(T));
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  P(kgrt_camera) P(kgrt_model) P(kgrt_integrator) P(kgrt_outputs) P(kgrt_launch)
+  F(kgrt_camera, nx) F(kgrt_camera, x_min) F(kgrt_camera, y_max)
+  F(kgrt_model, r_in) F(kgrt_model, r_emit_max) F(kgrt_integrator, max_steps) F(kgrt_integrator, flags)
+  F(kgrt_outputs, tau) F(kgrt_launch, refill_min)
+  return 0; }
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "p.c")
+        open(c, "w").write(probe)
+        exe = os.path.join(d, "p")
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([exe]).decode().split("\n") if line)
+    want = {
+        "kgrt_camera": ctypes.sizeof(K.CCamera), "kgrt_model": ctypes.sizeof(K.CModel),
+        "kgrt_integrator": ctypes.sizeof(K.CIntegrator), "kgrt_outputs": ctypes.sizeof(K.COutputs),
+        "kgrt_launch": ctypes.sizeof(K.CLaunch),
+        "kgrt_camera.nx": K.CCamera.nx.offset, "kgrt_camera.x_min": K.CCamera.x_min.offset,
+        "kgrt_camera.y_max": K.CCamera.y_max.offset, "kgrt_model.r_in": K.CModel.r_in.offset,
+        "kgrt_model.r_emit_max": K.CModel.r_emit_max.offset,
+        "kgrt_integrator.max_steps": K.CIntegrator.max_steps.offset,
+        "kgrt_integrator.flags": K.CIntegrator.flags.offset, "kgrt_outputs.tau": K.COutputs.tau.offset,
+        "kgrt_launch.refill_min": K.CLaunch.refill_min.offset,
+    }
+    for k, v in want.items():
+        assert int(got[k]) == v, k
+
+
+def test_version_and_strerror(K):
+    L = K.lib()
+    assert L.kgrt_version() >= 100
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.kgrt_strerror(code)
+    assert L.kgrt_last_error(None) == b""
+
+
+def _ok_request(K):
+    return K.Camera(), K.Model(kind=K.MODEL_THIN_DISK), [], K.Integrator()
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda c, m, f, i: setattr(c, "a", 1.0),
+    lambda c, m, f, i: setattr(c, "a", float("nan")),
+    lambda c, m, f, i: setattr(c, "incl_deg", 0.0),
+    lambda c, m, f, i: setattr(c, "incl_deg", 180.0),
+    lambda c, m, f, i: setattr(c, "r_obs", 5.0),
+    lambda c, m, f, i: setattr(c, "nx", -1),
+    lambda c, m, f, i: setattr(c, "x_max", -20.0),
+    lambda c, m, f, i: setattr(c, "y_min", float("inf")),
+    lambda c, m, f, i: setattr(m, "kind", 7),
+    lambda c, m, f, i: setattr(m, "r_out", -1.0),
+    lambda c, m, f, i: setattr(m, "r_in", 30.0),
+    lambda c, m, f, i: setattr(i, "rtol", 1e-16),
+    lambda c, m, f, i: setattr(i, "rtol", 0.5),
+    lambda c, m, f, i: setattr(i, "hmax_frac", 0.0),
+    lambda c, m, f, i: setattr(i, "horizon_delta", 0.0),
+    lambda c, m, f, i: setattr(i, "max_steps", 0),
+    lambda c, m, f, i: setattr(i, "flags", 8),
+])
+def test_invalid_arguments_rejected(K, mutate):
+    cam, mod, freqs, integ = _ok_request(K)
+    assert K.check_args(cam, mod, freqs, integ) == K.OK
+    mutate(cam, mod, freqs, integ)
+    assert K.check_args(cam, mod, freqs, integ) == K.E_INVALID_ARG
+
+
+def test_torus_frequency_checks(K):
+    cam, _, _, integ = _ok_request(K)
+    tor = K.Model(kind=K.MODEL_TORUS)
+    assert K.check_args(cam, tor, [230e9], integ) == K.OK
+    assert K.check_args(cam, tor, [], integ) == K.E_INVALID_ARG
+    assert K.check_args(cam, tor, [230e9] * 17, integ) == K.E_INVALID_ARG
+    assert K.check_args(cam, tor, [-1.0], integ) == K.E_INVALID_ARG
+    assert K.check_args(cam, tor, [float("nan")], integ) == K.E_INVALID_ARG
+    assert K.check_args(cam, K.Model(kind=K.MODEL_TORUS, T0_K=0.0), [230e9], integ) == K.E_INVALID_ARG
+    # empty images are valid requests
+    assert K.check_args(K.Camera(nx=0, ny=0), tor, [230e9], integ) == K.OK
+
+
+def test_context_without_gpu_reports_no_device(K):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(K.KgrtError) as e:
+        K.Context(0)
+    assert e.value.code == K.E_NO_DEVICE
