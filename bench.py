@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus", choices=["torus", "thin_disk", "projection"])
     ap.add_argument("--n", type=int, default=None, help="image side (default per workload)")
-    ap.add_argument("--cpu-sample", type=int, default=6000, help="pixels in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=40000, help="pixels in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)

@@ -70,7 +70,7 @@ RAY_DTYPE = np.dtype([
     ("I", "<f8", (16,)), ("tau", "<f8", (16,)),
     ("final_state", "<f8", (6,)),
     ("E", "<f8"), ("L", "<f8"), ("Q", "<f8"), ("kappa", "<f8"),
-    ("max_H_rel", "<f8"), ("max_Q_rel", "<f8"), ("lambda_end", "<f8"),
+    ("max_H_rel", "<f8"), ("max_Q_rel", "<f8"), ("lambda_end", "<f8"), ("min_sin", "<f8"),
 ])
 
 

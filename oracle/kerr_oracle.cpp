@@ -69,6 +69,7 @@ typedef struct orc_ray {
     double E, L, Q, kappa;      // constants of motion of the traced ray
     double max_H_rel, max_Q_rel; // largest null-condition and Carter-Q drift seen
     double lambda_end;          // affine parameter at termination
+    double min_sin;             // smallest sin(theta) over the accepted points (pole approach)
 } orc_ray;
 
 enum {
@@ -391,6 +392,7 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
     bool crossed = false;
     int status = 0;
     double maxH = null_residual(s, y, c), maxQ = 0.0;
+    double min_sin = std::fabs(std::sin(y[1]));
     if (path && path_cap > 0) { path[0] = 0.0; for (int i = 0; i < 6; ++i) path[1 + i] = y[i]; *path_len = 1; }
 
     orc_rhs(s, y, c, k1); ++rhs;
@@ -436,6 +438,8 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
                 if (hr > maxH) maxH = hr;
                 const double dq = std::fabs(carter_q(s, y, c) - q0) / qden;
                 if (dq > maxQ) maxQ = dq;
+                const double sabs = std::fabs(std::sin(y[1]));
+                if (sabs < min_sin) min_sin = sabs;
             }
             // radiative transfer over the accepted step (Eqs. (30)-(31))
             if (nf > 0) {
@@ -508,6 +512,7 @@ done:
     for (int i = 0; i < 6; ++i) out->final_state[i] = y[i];
     out->max_H_rel = maxH;
     out->max_Q_rel = maxQ;
+    out->min_sin = min_sin;
 }
 
 int orc_trace_ray(const orc_scene* s, double x, double y, orc_ray* out) {

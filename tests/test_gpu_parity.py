@@ -50,35 +50,50 @@ def rel(a, b):
     return np.where((a == b), 0.0, np.abs(a - b) / den)
 
 
+POLE_SIN = 1e-6  # rays passing closer to the pole run into the clamp sin(theta) >= 1e-8
+
+
 def compare_disk(w, g, o, label):
-    """Compare GPU outputs g (dict) with oracle rays o (structured, flat)."""
+    """Compare GPU outputs g (dict) with oracle rays o (structured, flat).
+
+    Strict set: rays with identical step sequences that neither pass within
+    sin(theta) < 1e-6 of the pole (where the pole clamp of section 2.1 breaks the
+    Hamiltonian form and amplifies last-ulp differences) nor lie within 1e-6 M of
+    the critical curve. On it, disk hits agree to 1e-9 in r_c and g. Every other
+    crossing is compared at the method's own accuracy, 1e-6 (g relative to
+    max(g, 1e-3): g -> 0 at the photon orbit, where it is ill-conditioned)."""
     cam = w["camera"]
-    n = len(o)
     st_o = o["status"]
     st_g = g["status"]
     assert not np.any(st_g == -7), "some ray was never written"
     xi = o["L"] / o["E"]
     eta = o["Q"] / o["E"] ** 2
     dcrit = critical_curve_distance(cam["a"], cam["incl_deg"], xi, eta)
-    same_steps = (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
-    near = dcrit < 1e-6
+    near_crit = dcrit < 1e-6
+    near_pole = o["min_sin"] < POLE_SIN
+    ident = (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
+    regular = ~near_crit & ~near_pole
     # capture classification
-    cap_mismatch = ((st_g & 1) != (st_o & 1)) & ~near
+    cap_mismatch = ((st_g & 1) != (st_o & 1)) & ~near_crit
     assert not cap_mismatch.any(), (label, np.nonzero(cap_mismatch)[0][:10])
-    # status bits where the step sequence is the same
-    assert np.array_equal(st_g[same_steps], st_o[same_steps]), label
-    frac = same_steps.mean()
-    assert frac >= 0.995, (label, frac)
+    # step sequences: identical for (nearly) every regular ray
+    frac = ident[regular].mean() if regular.any() else 1.0
+    assert frac >= 0.999, (label, frac, np.nonzero(regular & ~ident)[0][:10])
+    assert np.array_equal(st_g[ident], st_o[ident]), label
     both = ((st_g & 4) != 0) & ((st_o & 4) != 0)
-    tight = both & same_steps
-    for k in ("r_cross", "g", "phi_cross"):
-        assert rel(g[k][tight], o[k][tight]).max(initial=0) <= REL_GEOM, (label, k, rel(g[k][tight], o[k][tight]).max())
-        loose = both & ~same_steps
-        assert rel(g[k][loose], o[k][loose]).max(initial=0) <= REL_RT, (label, k)
+    disk = both & ((st_o & 8) != 0) & ((st_g & 8) != 0)
+    strict = disk & ident & regular
+    for k in ("r_cross", "g", "phi_cross", "t_cross"):
+        e = rel(g[k][strict], o[k][strict]).max(initial=0)
+        assert e <= REL_GEOM, (label, k, e)
     for k in ("intensity", "i_bol"):  # g^3 r^-3 and g^4 r^-3 amplify the geometric error a few times
-        assert rel(g[k][tight], o[k][tight]).max(initial=0) <= REL_GEOM * 10, (label, k)
-    # t at the crossing is carried too
-    assert rel(g["t_cross"][tight], o["t_cross"][tight]).max(initial=0) <= REL_GEOM * 10, label
+        e = rel(g[k][strict], o[k][strict]).max(initial=0)
+        assert e <= 10 * REL_GEOM, (label, k, e)
+    loose = both & ~strict
+    assert rel(g["r_cross"][loose], o["r_cross"][loose]).max(initial=0) <= REL_RT, label
+    gerr = np.abs(g["g"][loose] - o["g"][loose]) / np.maximum(np.abs(o["g"][loose]), 1e-3)
+    assert gerr.max(initial=0) <= REL_RT, (label, gerr.max(initial=0))
+    assert np.array_equal((st_g & 4)[regular], (st_o & 4)[regular]), label
     return frac
 
 
@@ -210,12 +225,17 @@ def test_ray_list_matches_oracle(ctx):
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items()}
     o = O.trace_ray_list(oracle_scene(w), rays)
-    same = (g["steps"] == o["steps"])
-    assert same.mean() >= 0.99
-    assert np.array_equal(g["status"][same], o["status"][same])
-    both = ((g["status"] & 4) != 0) & same
-    for k in ("r_cross", "g"):
-        assert rel(g[k][both], o[k][both]).max() <= REL_GEOM, k
+    assert not np.any(g["status"] == -7)
+    regular = o["min_sin"] >= POLE_SIN
+    ident = (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
+    assert ident[regular].mean() >= 0.999
+    assert np.array_equal(g["status"][ident], o["status"][ident])
+    strict = ((g["status"] & 8) != 0) & ((o["status"] & 8) != 0) & ident & regular
+    assert strict.sum() > 500
+    for k in ("r_cross", "g", "phi_cross"):
+        assert rel(g[k][strict], o[k][strict]).max() <= REL_GEOM, k
+    crossed = ((g["status"] & 4) != 0) & ((o["status"] & 4) != 0)
+    assert rel(g["r_cross"][crossed], o["r_cross"][crossed]).max() <= REL_RT
 
 
 def test_ray_list_invalid_rays_flagged(ctx):
