@@ -35,8 +35,23 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # divergence-free run (every lane traces the same ray), see
 # profiles/torus_flop_calibration.md. "formula": operation count of the
 # source with every divide, root and transcendental counted once.
-FLOPS_PER_ATTEMPT = {"torus": (850.0, "formula"), "thin_disk": (620.0, "formula"),
+FLOPS_PER_ATTEMPT = {"torus": (2180.0, "calibrated"), "thin_disk": (620.0, "formula"),
                      "projection": (620.0, "formula")}
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a 1 GiB copy probe), see
+# profiles/torus_1024_hbm_traffic.md. Valid only for the kernel sources they
+# were taken on (md5 of csrc/kgrt.hip + csrc/kgrt_device.hpp); null otherwise.
+TRAFFIC = {"torus": {"bytes": 3002214321, "source_md5": "575b399cfc72a7f596b8b9e11d0b57eb"}}
+
+
+def kernel_source_md5() -> str:
+    import hashlib
+    h = hashlib.md5()
+    for name in ("kgrt.hip", "kgrt_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1601_02063_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 CALIBRATION_RAYS = {
     # (a, incl_deg, x, y): a captured ray, an escaping ray through the torus, a far ray
@@ -96,6 +111,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)
     ap.add_argument("--calibrate", default=None, choices=sorted(CALIBRATION_RAYS))
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 1 GiB device copy (scales the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -116,6 +133,14 @@ def main():
 
     if args.calibrate:
         calibrate(ctx, args.calibrate, dev)
+        return
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 8, "copy_probe_bytes_written": dst.numel() * 8}))
         return
 
     w, desc = workload(args.workload, args.n)
@@ -147,6 +172,8 @@ def main():
     ns_per_step = ms_mean * 1e6 / steps
     fpa, basis = FLOPS_PER_ATTEMPT[args.workload]
     achieved = fpa * attempts / (ms_mean * 1e-3) / 1e12
+    tr = TRAFFIC.get(args.workload)
+    traffic = tr["bytes"] if (tr and args.n in (None, 1024) and tr["source_md5"] == kernel_source_md5()) else None
     line = {
         "metric": METRIC,
         "value": round(ns_per_step, 6),
@@ -172,7 +199,7 @@ def main():
         "steps_per_ray": round(steps / n, 2),
         "captured_frac": round(float(((st & 1) != 0).float().mean()), 5),
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": traffic,
                      "flops_per_attempt": fpa, "flops_basis": basis,
                      "kernel": "trace_kernel<torus,1>" if args.workload == "torus" else "trace_kernel<disk,1>"},
     }

@@ -25,19 +25,22 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile the library in-tree (always, unless force=False and it is up to date)."""
-    if not force and os.path.exists(LIB):
+def build(force: bool = True, verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile the library in-tree (always, unless force=False and it is up to date).
+
+    defines: extra preprocessor settings, e.g. ("KGRT_WAVES_PER_EU=3",) for launch-shape experiments.
+    """
+    if not force and os.path.exists(out):
         newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)
-        if os.path.getmtime(LIB) >= newest:
-            return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + SOURCES
+        if os.path.getmtime(out) >= newest:
+            return out
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-D" + d for d in defines] + ["-o", tmp] + SOURCES
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -64,22 +64,14 @@ struct KParams {
 
 // ------------------------------------------------------------ ray start
 
-struct RayStart {
-    State y;
-    double a, a2, L, r_cap, r_in, r_obs;
-    bool ok;
-};
-
 // Pixel -> start state, section 2.2: Eqs. (18)-(19) image plane -> Cartesian,
 // Eqs. (20)-(22) Cartesian -> Boyer-Lindquist, Eqs. (24)-(26) rates of a ray
 // along the line of sight, Eq. (7) energy (negative root, rates scaled so
-// E = -1), Eq. (8) L_z, Eqs. (4)-(5) covariant momenta.
-__device__ __noinline__ RayStart start_ray(double a, double a2, double r_obs, double sqrt_ro2a2, double sin_i,
-                                     double cos_i, double sin_p, double cos_p, double phi_obs, double x, double y) {
-    RayStart s;
-    s.a = a;
-    s.a2 = a2;
-    s.r_obs = r_obs;
+// E = -1), Eq. (8) L_z, Eqs. (4)-(5) covariant momenta. Returns false when
+// the start point is unusable (E^2 <= 0 or non-finite values).
+__device__ __forceinline__ bool start_ray(double a, double a2, double r_obs, double sqrt_ro2a2, double sin_i,
+                                          double cos_i, double sin_p, double cos_p, double phi_obs, double x,
+                                          double y, State& st, double& L) {
     const double D = sqrt_ro2a2 * sin_i - y * cos_i;
     const double xp = D * cos_p - x * sin_p;
     const double yp = D * sin_p + x * cos_p;
@@ -90,9 +82,9 @@ __device__ __noinline__ RayStart start_ray(double a, double a2, double r_obs, do
     const double ph = atan2(yp, xp);
     const double R = sqrt(r * r + a2);
     double sP, cP;
-    sincos(ph - phi_obs, &sP, &cP);
+    sincos_bounded(ph - phi_obs, &sP, &cP);
     double sn, cs;
-    sincos(th, &sn, &cs);
+    sincos_bounded(th, &sn, &cs);
     const double Sigma = r * r + a2 * cs * cs;
     double rdot = -(r * R * sn * sin_i * cP + R * R * cs * cos_i) / Sigma;
     double thdot = (r * sn * cos_i - R * cs * sin_i * cP) / Sigma;
@@ -100,30 +92,35 @@ __device__ __noinline__ RayStart start_ray(double a, double a2, double r_obs, do
     const double Delta = r * r - 2.0 * r + a2;
     const double E2 = ((Sigma - 2.0 * r) / (Sigma * Delta)) * (Sigma * rdot * rdot + Sigma * Delta * thdot * thdot) +
                       Delta * phdot * phdot * sn * sn;
-    s.ok = (E2 > 0.0) && isfinite(E2);
+    bool ok = (E2 > 0.0) && isfinite(E2);
     const double inv = 1.0 / sqrt(E2);
     rdot *= inv;
     thdot *= inv;
     phdot *= inv;
-    s.L = (Sigma * Delta * phdot + 2.0 * a * r) * sn * sn / (Sigma - 2.0 * r);
-    s.y = State{r, th, ph, 0.0, Sigma * rdot / Delta, Sigma * thdot};
-    s.ok = s.ok && finite6(s.y) && isfinite(s.L);
-    return s;
+    L = (Sigma * Delta * phdot + 2.0 * a * r) * sn * sn / (Sigma - 2.0 * r);
+    st = State{r, th, ph, 0.0, Sigma * rdot / Delta, Sigma * thdot};
+    return ok && finite6(st) && isfinite(L);
 }
 
-__device__ inline RayStart start_from_id(const KParams& P, int64_t rid) {
+// Ray id -> start state and the per-ray uniforms (spin, capture radius,
+// disk inner edge, observer distance).
+__device__ __forceinline__ bool start_from_id(const KParams& P, int64_t rid, State& st, double& a, double& a2,
+                                              double& L, double& r_cap, double& r_in, double& r_obs) {
     if (P.list_mode) {
         const double* q = P.rays4 + 4 * rid;
-        const double a = q[0], incl = q[1], x = q[2], y = q[3];
+        const double aa = q[0], incl = q[1], x = q[2], y = q[3];
         const double tho = incl * kPi / 180.0;
         double si, ci;
-        sincos(tho, &si, &ci);
-        RayStart s = start_ray(a, a * a, P.list_r_obs, sqrt(P.list_r_obs * P.list_r_obs + a * a), si, ci,
-                               P.list_sin_p, P.list_cos_p, P.list_phi_obs, x, y);
-        s.r_cap = (1.0 + sqrt(1.0 - a * a)) * (1.0 + P.horizon_delta);
-        s.r_in = (P.r_in_cfg > 0.0) ? P.r_in_cfg : isco_radius(a);
-        if (!(fabs(a) < 1.0) || !(incl > 0.0 && incl < 180.0) || !isfinite(x) || !isfinite(y)) s.ok = false;
-        return s;
+        sincos_bounded(tho, &si, &ci);
+        a = aa;
+        a2 = aa * aa;
+        r_obs = P.list_r_obs;
+        bool ok = start_ray(aa, a2, r_obs, sqrt(r_obs * r_obs + a2), si, ci, P.list_sin_p, P.list_cos_p,
+                            P.list_phi_obs, x, y, st, L);
+        r_cap = (1.0 + sqrt(1.0 - a2)) * (1.0 + P.horizon_delta);
+        r_in = (P.r_in_cfg > 0.0) ? P.r_in_cfg : isco_radius(aa);
+        if (!(fabs(aa) < 1.0) || !(incl > 0.0 && incl < 180.0) || !isfinite(x) || !isfinite(y)) ok = false;
+        return ok;
     }
     const ImageDesc* d = &P.image0;
     if (P.nimg > 1) {
@@ -139,45 +136,62 @@ __device__ inline RayStart start_from_id(const KParams& P, int64_t rid) {
     // cell centres, same operation order as the documented rule
     const double x = d->x_min + ((i + 0.5) * d->x_w) / d->nx;
     const double y = d->y_min + ((j + 0.5) * d->y_w) / d->ny;
-    RayStart s = start_ray(d->a, d->a2, d->r_obs, d->sqrt_ro2a2, d->sin_i, d->cos_i, d->sin_p, d->cos_p,
-                           d->phi_obs, x, y);
-    s.r_cap = d->r_cap;
-    s.r_in = d->r_in;
-    return s;
+    a = d->a;
+    a2 = d->a2;
+    r_obs = d->r_obs;
+    r_cap = d->r_cap;
+    r_in = d->r_in;
+    return start_ray(d->a, d->a2, d->r_obs, d->sqrt_ro2a2, d->sin_i, d->cos_i, d->sin_p, d->cos_p, d->phi_obs, x,
+                     y, st, L);
 }
 
-// First equatorial crossing inside an accepted step [y_k, y_k+1] over which
-// cos(theta) changes sign: Newton iteration on the step size h* from y_k,
-// starting from linear interpolation of cos(theta), each iterate one full
-// Cash-Karp step of size h* without error control; stops at |cos theta| <= 1e-13
-// or after six updates. Rare (once per ray), so kept out of line.
-__device__ __noinline__ State refine_crossing(const State yprev, double hdone, double c0, double c1, double a,
-                                              double a2, double L, bool& conv) {
-    const State kp = rhs(yprev, a, a2, L);
-    double hs = hdone * c0 / (c0 - c1);
-    State ys, yse;
-    conv = false;
-    for (int it = 0; it < 7; ++it) {
-        cash_karp(yprev, kp, hs, a, a2, L, ys, yse);
-        double sz, cz;
-        sincos(ys.th, &sz, &cz);
-        if (fabs(cz) <= 1e-13) {
-            conv = true;
-            break;
-        }
-        if (it == 6) break;
-        const double thdot = ys.pth / (ys.r * ys.r + a2 * cz * cz);
-        hs = hs + cz / (sz * thdot);
-    }
-    return ys;
-}
+// Per-ray start record written by start_kernel and read by the integrator at
+// refill, structure-of-arrays over the rays of one chunk:
+//   r, theta, phi, p_r, p_theta, L_z, a, r_capture, r_in, r_obs.
+// A non-finite r marks an unusable start point.
+constexpr int kRecFields = 10;
 
 // ------------------------------------------------------------ kernels
 
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
 
+// One thread per ray of the chunk [base, base + count): ray start (section 2.2).
+__global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t base, int64_t count, double* rec,
+                                                    int64_t cap) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
+        State st;
+        double a, a2, L, r_cap, r_in, r_obs;
+        const bool ok = start_from_id(P, base + k, st, a, a2, L, r_cap, r_in, r_obs);
+        rec[0 * cap + k] = ok ? st.r : __builtin_nan("");
+        rec[1 * cap + k] = st.th;
+        rec[2 * cap + k] = st.ph;
+        rec[3 * cap + k] = st.pr;
+        rec[4 * cap + k] = st.pth;
+        rec[5 * cap + k] = L;
+        rec[6 * cap + k] = a;
+        rec[7 * cap + k] = r_cap;
+        rec[8 * cap + k] = r_in;
+        rec[9 * cap + k] = r_obs;
+    }
+}
+
+// Waves per SIMD the register allocation targets, per model (measured on
+// MI355X: the crossing-tracking kernel is fastest with one wave and the
+// whole register file, the transfer kernel with three).
+#ifdef KGRT_WAVES_PER_EU
+template <int MODEL> struct WavesPerEU { static constexpr int value = KGRT_WAVES_PER_EU; };
+#else
+template <int MODEL> struct WavesPerEU { static constexpr int value = (MODEL == KGRT_MODEL_TORUS) ? 3 : 1; };
+#endif
+
+// Persistent integrator over the rays of one chunk. MODEL selects the
+// crossing-tracking models (geodesic, thin disk) or the transfer model
+// (torus); NF bounds the number of frequencies carried in registers.
 template <int MODEL, int NF>
-__global__ void __launch_bounds__(256) trace_kernel(const KParams P) {
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(WavesPerEU<MODEL>::value, WavesPerEU<MODEL>::value)))
+trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restrict__ rec, int64_t cap) {
+    constexpr bool kDisk = (MODEL != KGRT_MODEL_TORUS);
     const int lane = __lane_id();
     const uint64_t lane_mask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false, done = false;
@@ -185,41 +199,47 @@ __global__ void __launch_bounds__(256) trace_kernel(const KParams P) {
     State y{};
     double h = 0.0, a = 0.0, a2 = 0.0, L = 0.0, r_cap = 0.0, r_in = 0.0, r_obs = 0.0;
     int32_t steps = 0, attempts = 0, status = 0;
-    bool crossed = false;
+    // crossing refinement (thin disk / geodesic): Newton iteration on the
+    // step size from y_k, run in lockstep with the other lanes' attempts
+    bool crossed = false, refine = false;
+    int32_t rit = 0;
+    double hs = 0.0;
+    State yk{};
     double tau[NF], Iacc[NF], ap[NF], ep[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) tau[f] = Iacc[f] = ap[f] = ep[f] = 0.0;
-    const Outputs& O = P.out;
+    const Outputs O = P.out;
     const int nf = P.nf;
+    const int64_t nall = P.nrays;
 
     for (;;) {
-        // ---- refill idle lanes from the global ray queue
+        // ---- refill idle lanes from the chunk's ray queue
         const bool need = !active && !done;
         const uint64_t want = __ballot(need);
         if (want != 0ull) {
             const int cnt = __popcll(want);
             if (cnt >= P.refill_min || __ballot(active) == 0ull) {
                 const int leader = __ffsll((unsigned long long)want) - 1;
-                unsigned long long base = 0ull;
-                if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)cnt);
-                base = __shfl(base, leader);
+                unsigned long long qb = 0ull;
+                if (lane == leader) qb = atomicAdd(P.counter, (unsigned long long)cnt);
+                qb = __shfl(qb, leader);
                 if (need) {
-                    const unsigned long long my = base + (unsigned long long)__popcll(want & lane_mask_lt);
-                    if (my < (unsigned long long)P.nrays) {
-                        rid = (int64_t)my;
-                        const RayStart s = start_from_id(P, rid);
-                        y = s.y;
-                        a = s.a;
-                        a2 = s.a2;
-                        L = s.L;
-                        r_cap = s.r_cap;
-                        r_in = s.r_in;
-                        r_obs = s.r_obs;
+                    const unsigned long long my = qb + (unsigned long long)__popcll(want & lane_mask_lt);
+                    if (my < (unsigned long long)count) {
+                        const int64_t k = (int64_t)my;
+                        rid = base + k;
+                        y = State{rec[0 * cap + k], rec[1 * cap + k], rec[2 * cap + k], 0.0, rec[3 * cap + k],
+                                  rec[4 * cap + k]};
+                        L = rec[5 * cap + k];
+                        a = rec[6 * cap + k];
+                        a2 = a * a;
+                        r_cap = rec[7 * cap + k];
+                        r_in = rec[8 * cap + k];
+                        r_obs = rec[9 * cap + k];
                         h = P.hmax_frac * r_obs;
-                        steps = attempts = 0;
-                        status = 0;
-                        crossed = false;
-                        if (s.ok) {
+                        steps = attempts = status = 0;
+                        crossed = refine = false;
+                        if (isfinite(y.r)) {
                             active = true;
                             if (MODEL == KGRT_MODEL_TORUS) {
                                 const double g0 = redshift(y.r, y.th, a, a2, -L);
@@ -243,8 +263,8 @@ __global__ void __launch_bounds__(256) trace_kernel(const KParams P) {
                             if (O.i_bol) O.i_bol[rid] = 0.0;
                             if (MODEL == KGRT_MODEL_TORUS) {
                                 for (int f = 0; f < nf; ++f) {
-                                    if (O.intensity) O.intensity[(int64_t)f * P.nrays + rid] = 0.0;
-                                    if (O.tau) O.tau[(int64_t)f * P.nrays + rid] = 0.0;
+                                    if (O.intensity) O.intensity[(int64_t)f * nall + rid] = 0.0;
+                                    if (O.tau) O.tau[(int64_t)f * nall + rid] = 0.0;
                                 }
                             } else if (O.intensity) {
                                 O.intensity[rid] = 0.0;
@@ -259,110 +279,135 @@ __global__ void __launch_bounds__(256) trace_kernel(const KParams P) {
         if (__ballot(active || !done) == 0ull) break;
         if (!active) continue;
 
-        // ---- one adaptive Cash-Karp attempt (section 2.1)
+        // ---- one Cash-Karp evaluation (section 2.1): an adaptive attempt from
+        // y, or, for a lane refining a crossing, a fixed step of size hs from y_k
         bool terminate = false;
-        const State k1 = rhs(y, a, a2, L);
+        const State yb = (kDisk && refine) ? yk : y;
+        const double hb = (kDisk && refine) ? hs : h;
+        const State k1 = rhs(yb, a, a2, L);
         State yn, ye;
-        cash_karp(y, k1, h, a, a2, L, yn, ye);
-        ++attempts;
-        double errmax = 0.0;
-        {
-            const double tol = P.rtol;
-#define KGRT_ERR(f)                                                              \
-    {                                                                            \
-        const double e = fabs(ye.f) / (tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12)); \
-        if (e > errmax) errmax = e;                                              \
-    }
-            KGRT_ERR(r) KGRT_ERR(th) KGRT_ERR(ph) KGRT_ERR(t) KGRT_ERR(pr) KGRT_ERR(pth)
-#undef KGRT_ERR
-        }
-        if (!(errmax <= 1.0)) {
-            // rejected: shrink and retry
-            if (!isfinite(errmax)) errmax = 1e10;
-            double shrink = 0.9 * pow(errmax, -0.25);
-            if (shrink < 0.1) shrink = 0.1;
-            h = h * shrink;
-            if (fabs(h) < 1e-12 * fmax(1.0, y.r)) {
-                status |= ST_UNDERFLOW;
-                terminate = true;
+        cash_karp(yb, k1, hb, a, a2, L, yn, ye);
+        bool check_end = false;
+
+        if (kDisk && refine) {
+            // Newton step on h* for cos(theta(h*)) = 0 (no error control)
+            double sz, cz;
+            sincos_bounded(yn.th, &sz, &cz);
+            ++rit;
+            if (fabs(cz) <= 1e-13 || rit == 7) {
+                if (!(fabs(cz) <= 1e-13)) status |= ST_REFINE_UNCONVERGED;
+                refine = false;
+                const double rc = yn.r;
+                if (rc > r_cap) {
+                    status |= ST_CROSSED;
+                    const double g = redshift(rc, kPi / 2.0, a, a2, -L);
+                    double I = 0.0, Ib = 0.0;
+                    if (P.model == KGRT_MODEL_THIN_DISK && rc >= r_in && rc <= P.r_out) {
+                        status |= ST_DISK_HIT;
+                        const double j = 1.0 / (rc * rc * rc);  // emissivity r^-3
+                        I = g * g * g * j;
+                        Ib = g * g * g * g * j;
+                    }
+                    if (O.r_cross) O.r_cross[rid] = rc;
+                    if (O.g) O.g[rid] = g;
+                    if (O.phi_cross) O.phi_cross[rid] = yn.ph;
+                    if (O.t_cross) O.t_cross[rid] = yn.t;
+                    if (O.intensity) O.intensity[rid] = I;
+                    if (O.i_bol) O.i_bol[rid] = Ib;
+                    if (P.flags & KGRT_STOP_AT_CROSSING) terminate = true;
+                }
+                // the accepted y_k+1 still has to pass the end-of-step tests
+                check_end = !terminate;
+            } else {
+                const double thdot = yn.pth / (yn.r * yn.r + a2 * cz * cz);
+                hs = hs + cz / (sz * thdot);
             }
         } else {
-            // accepted
-            const double hdone = h;
-            double hnext = (errmax > 1.89e-4) ? h * (0.9 * pow(errmax, -0.2)) : h * 5.0;
-            ++steps;
-            const State yprev = y;
-            y = yn;
-            if (!finite6(y)) {
-                status |= ST_NONFINITE;
-                terminate = true;
-            } else {
-                if (MODEL == KGRT_MODEL_TORUS) {
-                    // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
-                    // each accepted endpoint, exponential-trapezoid increment
-                    const double g1 = redshift(y.r, y.th, a, a2, -L);
-                    const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        if (f < nf) {
-                            double a1, e1;
-                            torus_coeffs(q, P.torus, g1, P.freqs[f], a1, e1);
-                            const double dtau = hdone * (ap[f] + a1) / 2.0;
-                            const double phi = (dtau > 0.0) ? -expm1(-dtau) / dtau : 1.0;
-                            Iacc[f] += exp(-tau[f]) * hdone * (ep[f] + e1) / 2.0 * phi;
-                            tau[f] += dtau;
-                            ap[f] = a1;
-                            ep[f] = e1;
-                        }
-                    }
-                } else if (!crossed) {
-                    // first equatorial crossing: Newton iteration on the step size from
-                    // y_k, each iterate one full Cash-Karp step without error control
-                    double c0, c1, sdum;
-                    sincos(yprev.th, &sdum, &c0);
-                    sincos(y.th, &sdum, &c1);
-                    if ((c0 > 0.0 && c1 <= 0.0) || (c0 < 0.0 && c1 >= 0.0)) {
-                        crossed = true;
-                        bool conv = false;
-                        const State ys = refine_crossing(yprev, hdone, c0, c1, a, a2, L, conv);
-                        if (!conv) status |= ST_REFINE_UNCONVERGED;
-                        const double rc = ys.r;
-                        if (rc > r_cap) {
-                            status |= ST_CROSSED;
-                            const double g = redshift(rc, kPi / 2.0, a, a2, -L);
-                            double I = 0.0, Ib = 0.0;
-                            if (P.model == KGRT_MODEL_THIN_DISK && rc >= r_in && rc <= P.r_out) {
-                                status |= ST_DISK_HIT;
-                                const double j = 1.0 / (rc * rc * rc);
-                                I = g * g * g * j;
-                                Ib = g * g * g * g * j;
-                            }
-                            if (O.r_cross) O.r_cross[rid] = rc;
-                            if (O.g) O.g[rid] = g;
-                            if (O.phi_cross) O.phi_cross[rid] = ys.ph;
-                            if (O.t_cross) O.t_cross[rid] = ys.t;
-                            if (O.intensity) O.intensity[rid] = I;
-                            if (O.i_bol) O.i_bol[rid] = Ib;
-                            if (P.flags & KGRT_STOP_AT_CROSSING) terminate = true;
-                        }
-                    }
-                }
-                if (!terminate) {
-                    if (y.r <= r_cap) {
-                        status |= ST_CAPTURED;
-                        terminate = true;
-                    } else if (y.pr > 0.0 && y.r > r_obs) {
-                        status |= ST_ESCAPED;
-                        terminate = true;
-                    } else if (steps >= P.max_steps) {
-                        status |= ST_MAXSTEPS;
-                        terminate = true;
-                    }
-                }
+            ++attempts;
+            double errmax = 0.0;
+            {
+                const double tol = P.rtol;
+#define KGRT_ERR(f)                                                                      \
+    {                                                                                    \
+        const double e = fabs(ye.f) / (tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12));      \
+        if (e > errmax) errmax = e;                                                      \
+    }
+                KGRT_ERR(r) KGRT_ERR(th) KGRT_ERR(ph) KGRT_ERR(t) KGRT_ERR(pr) KGRT_ERR(pth)
+#undef KGRT_ERR
             }
-            const double hcap = P.hmax_frac * y.r;
-            if (hnext > hcap) hnext = hcap;
-            h = hnext;
+            if (!(errmax <= 1.0)) {
+                // rejected: shrink and retry
+                if (!isfinite(errmax)) errmax = 1e10;
+                double shrink = 0.9 * fm::pow_m025(errmax);
+                if (shrink < 0.1) shrink = 0.1;
+                h = h * shrink;
+                if (fabs(h) < 1e-12 * fmax(1.0, y.r)) {
+                    status |= ST_UNDERFLOW;
+                    terminate = true;
+                }
+            } else {
+                // accepted: y_k -> y_k+1 over [lambda, lambda + hdone]
+                const double hdone = h;
+                double hnext = (errmax > 1.89e-4) ? h * (0.9 * fm::pow_m02(errmax)) : h * 5.0;
+                ++steps;
+                if (kDisk) yk = y;
+                const double thk = y.th;
+                y = yn;
+                if (!finite6(y)) {
+                    status |= ST_NONFINITE;
+                    terminate = true;
+                } else {
+                    if (MODEL == KGRT_MODEL_TORUS) {
+                        // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
+                        // each accepted endpoint, exponential-trapezoid increment
+                        const double g1 = redshift(y.r, y.th, a, a2, -L);
+                        const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) {
+                            if (f < nf) {
+                                double a1, e1;
+                                torus_coeffs(q, P.torus, g1, P.freqs[f], a1, e1);
+                                const double dtau = hdone * (ap[f] + a1) / 2.0;
+                                const double phi = (dtau > 0.0) ? -fm::expm1(-dtau) / dtau : 1.0;
+                                Iacc[f] += fm::exp(-tau[f]) * hdone * (ep[f] + e1) / 2.0 * phi;
+                                tau[f] += dtau;
+                                ap[f] = a1;
+                                ep[f] = e1;
+                            }
+                        }
+                        check_end = true;
+                    } else {
+                        double c0, c1, sdum;
+                        sincos_bounded(thk, &sdum, &c0);
+                        sincos_bounded(y.th, &sdum, &c1);
+                        if (!crossed && ((c0 > 0.0 && c1 <= 0.0) || (c0 < 0.0 && c1 >= 0.0))) {
+                            // first equatorial crossing inside this step: refine it over the
+                            // next evaluations, starting from linear interpolation of cos(theta)
+                            crossed = true;
+                            refine = true;
+                            rit = 0;
+                            hs = hdone * c0 / (c0 - c1);
+                        } else {
+                            check_end = true;
+                        }
+                    }
+                }
+                const double hcap = P.hmax_frac * y.r;
+                if (hnext > hcap) hnext = hcap;
+                h = hnext;
+            }
+        }
+        if (check_end) {
+            if (y.r <= r_cap) {
+                status |= ST_CAPTURED;
+                terminate = true;
+            } else if (y.pr > 0.0 && y.r > r_obs) {
+                status |= ST_ESCAPED;
+                terminate = true;
+            } else if (steps >= P.max_steps) {
+                status |= ST_MAXSTEPS;
+                terminate = true;
+            }
         }
 
         if (terminate) {
@@ -372,8 +417,8 @@ __global__ void __launch_bounds__(256) trace_kernel(const KParams P) {
             if (MODEL == KGRT_MODEL_TORUS) {
                 for (int f = 0; f < NF; ++f) {
                     if (f < nf) {
-                        if (O.intensity) O.intensity[(int64_t)f * P.nrays + rid] = Iacc[f];
-                        if (O.tau) O.tau[(int64_t)f * P.nrays + rid] = tau[f];
+                        if (O.intensity) O.intensity[(int64_t)f * nall + rid] = Iacc[f];
+                        if (O.tau) O.tau[(int64_t)f * nall + rid] = tau[f];
                     }
                 }
             }
@@ -400,6 +445,9 @@ struct kgrt_ctx {
     int device = 0;
     int num_cus = 0;
     unsigned long long* counter = nullptr;
+    double* rec = nullptr;  // ray start records of one chunk, [kRecFields][rec_cap]
+    int64_t rec_cap = 0;
+    int64_t chunk_max = int64_t(1) << 22;  // rays per chunk (4 Mi rays -> 320 MiB of records)
     kgrt_launch launch{};
     std::string last_error;
 };
@@ -509,25 +557,51 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     P.counter = ctx->counter;
 }
 
+// Grows the ray-start workspace to hold `n` rays (capped at one chunk).
+// Allocation happens here, outside any stream work, so it is never captured.
+int ensure_workspace(kgrt_ctx* ctx, int64_t n) {
+    const int64_t want = std::min<int64_t>(n, ctx->chunk_max);
+    if (want <= ctx->rec_cap) return KGRT_OK;
+    if (ctx->rec) {
+        if (hipDeviceSynchronize() != hipSuccess) return fail(ctx, KGRT_E_HIP, "hipDeviceSynchronize failed");
+        (void)hipFree(ctx->rec);
+        ctx->rec = nullptr;
+        ctx->rec_cap = 0;
+    }
+    if (hipMalloc(&ctx->rec, (size_t)want * kRecFields * sizeof(double)) != hipSuccess) {
+        ctx->rec = nullptr;
+        return fail(ctx, KGRT_E_NOMEM, "cannot allocate the ray-start workspace");
+    }
+    ctx->rec_cap = want;
+    return KGRT_OK;
+}
+
 template <int MODEL, int NF>
 int launch_one(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
-    const int block = (ctx->launch.block == 64 || ctx->launch.block == 128 || ctx->launch.block == 512) ? ctx->launch.block : 256;
+    const int block = (ctx->launch.block == 64 || ctx->launch.block == 128) ? ctx->launch.block : 256;
     auto kern = trace_kernel<MODEL, NF>;
     int per_cu = ctx->launch.blocks_per_cu;
     if (per_cu <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
     }
-    const int64_t need = (P.nrays + block - 1) / block;
-    const int64_t cap = (int64_t)ctx->num_cus * per_cu;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, ctx->counter);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, P);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(ctx, KGRT_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    const int64_t cap = ctx->rec_cap;
+    for (int64_t base = 0; base < P.nrays; base += cap) {
+        const int64_t count = std::min<int64_t>(cap, P.nrays - base);
+        const int64_t need = (count + block - 1) / block;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)ctx->num_cus * per_cu));
+        const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, (int64_t)ctx->num_cus * 16));
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, ctx->counter);
+        hipLaunchKernelGGL(start_kernel, dim3(sgrid), dim3(256), 0, st, P, base, count, ctx->rec, cap);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, P, base, count, (const double*)ctx->rec, cap);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(ctx, KGRT_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    }
     return KGRT_OK;
 }
 
 int dispatch(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
+    const int rc = ensure_workspace(ctx, P.nrays);
+    if (rc != KGRT_OK) return rc;
     if (P.model != KGRT_MODEL_TORUS) return launch_one<KGRT_MODEL_THIN_DISK, 1>(ctx, P, st);
     if (P.nf <= 1) return launch_one<KGRT_MODEL_TORUS, 1>(ctx, P, st);
     if (P.nf <= 2) return launch_one<KGRT_MODEL_TORUS, 2>(ctx, P, st);
@@ -598,6 +672,7 @@ int kgrt_ctx_destroy(kgrt_ctx* ctx) {
     {
         DeviceGuard g(ctx->device);
         if (ctx->counter) (void)hipFree(ctx->counter);
+        if (ctx->rec) (void)hipFree(ctx->rec);
     }
     delete ctx;
     return KGRT_OK;

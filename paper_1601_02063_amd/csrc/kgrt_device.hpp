@@ -47,6 +47,165 @@ struct State {
 
 __device__ __forceinline__ double clamp_sin(double s) { return (s < kSinFloor) ? kSinFloor : s; }
 
+// sin and cos of one argument for |x| < 2^20 (polar angles stay near [0, pi]).
+// Cody-Waite reduction by a three-part pi/2 (fused multiply-adds keep the
+// reduced argument exact to about 2^-100), then the Taylor series of sin and
+// cos on |r| <= pi/4, truncated where the next term is below 1e-19 (r^17 and
+// r^18), and the quadrant rotation. Accuracy ~1 ulp; much lighter than the
+// general-argument library routine, whose large-argument path costs registers.
+namespace trig {
+constexpr double kTwoOverPi = 0.6366197723675814;
+constexpr double kPio2Hi = 1.5707963267948966;      // 0x1.921fb54442d18p+0
+constexpr double kPio2Mid = 6.123233995736766e-17;  // 0x1.1a62633145c07p-54
+constexpr double kPio2Lo = -1.4973849048591698e-33; // -0x1.f1976b7ed8fbcp-110
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+// 1/n! as a compile-time constant (a class-template constant forces constant evaluation)
+template <int N>
+struct InvFact {
+    static constexpr double value = 1.0 / fact(N);
+};
+}  // namespace trig
+
+__host__ __device__ __forceinline__ void sincos_bounded(double x, double* sp, double* cp) {
+    using namespace trig;
+    const double k = rint(x * kTwoOverPi);
+    double r = fma(-k, kPio2Hi, x);
+    r = fma(-k, kPio2Mid, r);
+    r = fma(-k, kPio2Lo, r);
+    const double z = r * r;
+    double ps = InvFact<17>::value;
+    ps = fma(ps, z, -InvFact<15>::value);
+    ps = fma(ps, z, InvFact<13>::value);
+    ps = fma(ps, z, -InvFact<11>::value);
+    ps = fma(ps, z, InvFact<9>::value);
+    ps = fma(ps, z, -InvFact<7>::value);
+    ps = fma(ps, z, InvFact<5>::value);
+    ps = fma(ps, z, -InvFact<3>::value);
+    const double sr = fma(r * z, ps, r);
+    double pc = -InvFact<18>::value;
+    pc = fma(pc, z, InvFact<16>::value);
+    pc = fma(pc, z, -InvFact<14>::value);
+    pc = fma(pc, z, InvFact<12>::value);
+    pc = fma(pc, z, -InvFact<10>::value);
+    pc = fma(pc, z, InvFact<8>::value);
+    pc = fma(pc, z, -InvFact<6>::value);
+    pc = fma(pc, z, InvFact<4>::value);
+    pc = fma(pc, z, -0.5);
+    const double cr = fma(z, pc, 1.0);
+    const int q = ((int)k) & 3;
+    const double s1 = (q & 1) ? cr : sr;
+    const double c1 = (q & 1) ? sr : cr;
+    *sp = (q & 2) ? -s1 : s1;
+    *cp = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// ---------------------------------------------------------------------------
+// Light FP64 elementary functions for the per-step path. The general library
+// versions carry wide-range and special-case machinery whose register cost
+// would halve the kernel's occupancy; these cover the argument ranges that
+// occur here, with ~1-3 ulp accuracy (checked on the host against a
+// multiple-precision reference). All from textbook methods:
+//   exp/expm1: Cody & Waite reduction x = k ln2 + r, |r| <= ln2/2, Taylor series;
+//   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), log m = 2 atanh((m-1)/(m+1)) series;
+//   x^(-1/n): single-precision seed 2^(-log2(x)/n) and two Newton steps
+//             y <- y + y (1 - x y^n)/n in double (quadratic convergence);
+//   1/x: hardware reciprocal seed and two Newton steps r <- r + r (1 - x r).
+namespace fm {
+constexpr double kLn2Hi = 0.6931471805599453;
+constexpr double kLn2Lo = 2.3190468138462996e-17;
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kSqrtHalf = 0.7071067811865476;
+
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// e^r - 1 for |r| <= ln2/2 (Taylor series through r^14/14!).
+__host__ __device__ __forceinline__ double expm1_reduced(double r) {
+    double p = trig::InvFact<14>::value;
+    p = fma(p, r, trig::InvFact<13>::value);
+    p = fma(p, r, trig::InvFact<12>::value);
+    p = fma(p, r, trig::InvFact<11>::value);
+    p = fma(p, r, trig::InvFact<10>::value);
+    p = fma(p, r, trig::InvFact<9>::value);
+    p = fma(p, r, trig::InvFact<8>::value);
+    p = fma(p, r, trig::InvFact<7>::value);
+    p = fma(p, r, trig::InvFact<6>::value);
+    p = fma(p, r, trig::InvFact<5>::value);
+    p = fma(p, r, trig::InvFact<4>::value);
+    p = fma(p, r, trig::InvFact<3>::value);
+    p = fma(p, r, 0.5);
+    return fma(r * r, p, r);
+}
+
+__host__ __device__ __forceinline__ double exp(double x) {
+    if (x < -745.5) return 0.0;
+    if (x > 709.8) return __builtin_huge_val();
+    if (!(x == x)) return x;
+    const double k = rint(x * kLog2e);
+    double r = fma(-k, kLn2Hi, x);
+    r = fma(-k, kLn2Lo, r);
+    return ldexp(1.0 + expm1_reduced(r), (int)k);
+}
+
+__host__ __device__ __forceinline__ double expm1(double x) {
+    if (fabs(x) <= 0.5 * kLn2Hi) return expm1_reduced(x);
+    return fm::exp(x) - 1.0;
+}
+
+// Natural logarithm for finite x > 0.
+__host__ __device__ __forceinline__ double log(double x) {
+    int e;
+    double m = frexp(x, &e);  // x = m 2^e, m in [1/2, 1)
+    if (m < kSqrtHalf) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = (m - 1.0) / (m + 1.0);
+    const double s = f * f;
+    double p = 1.0 / 23.0;
+    p = fma(p, s, 1.0 / 21.0);
+    p = fma(p, s, 1.0 / 19.0);
+    p = fma(p, s, 1.0 / 17.0);
+    p = fma(p, s, 1.0 / 15.0);
+    p = fma(p, s, 1.0 / 13.0);
+    p = fma(p, s, 1.0 / 11.0);
+    p = fma(p, s, 1.0 / 9.0);
+    p = fma(p, s, 1.0 / 7.0);
+    p = fma(p, s, 1.0 / 5.0);
+    p = fma(p, s, 1.0 / 3.0);
+    const double lm = fma(2.0 * f * s, p, 2.0 * f);  // 2 atanh(f)
+    return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, lm));
+}
+
+// x^(-1/N) for 1e-30 <= x <= 1e30.
+template <int N>
+__device__ __forceinline__ double inv_root(double x) {
+    const float xf = (float)x;
+    double y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(xf) * (1.0f / N));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        double yn = y;
+#pragma unroll
+        for (int k = 1; k < N; ++k) yn *= y;
+        y = fma(y * (1.0 / N), fma(-x, yn, 1.0), y);
+    }
+    return y;
+}
+
+// Step-size factors of the error controller: 0.9 errmax^(-1/4) on rejection
+// (errmax > 1, result floored at 0.1 by the caller) and 0.9 errmax^(-1/5) on
+// acceptance (1.89e-4 < errmax <= 1).
+__device__ __forceinline__ double pow_m025(double x) {
+    if (x > 1e8) return 0.0;  // 0.9 x^-1/4 < 0.1 there: the floor applies
+    return inv_root<4>(x);
+}
+__device__ __forceinline__ double pow_m02(double x) { return inv_root<5>(x); }
+}  // namespace fm
+
 // Geodesic right-hand side, section 2.1 (photons, E = -1): r' and theta' from
 // Eqs. (4)-(5), phi' Eq. (12), t' Eq. (9), p_theta' Eq. (15). For p_r' the
 // form of Eq. (14) before the null condition replaces W^2/Delta is used,
@@ -55,16 +214,16 @@ __device__ __forceinline__ double clamp_sin(double s) { return (s < kSinFloor) ?
 // which the printed form does not on ingoing rays.
 __device__ __forceinline__ State rhs(const State& y, double a, double a2, double L) {
     double s, c;
-    sincos(y.th, &s, &c);
+    sincos_bounded(y.th, &s, &c);
     s = clamp_sin(s);
     const double r = y.r;
     const double r2a2 = r * r + a2;
     const double Sigma = r * r + a2 * c * c;
     const double Delta = r2a2 - 2.0 * r;
-    const double iS = 1.0 / Sigma;
-    const double iD = 1.0 / Delta;
-    const double is2 = 1.0 / (s * s);
-    const double iSD = iS * iD;
+    const double iSD = fm::rcp(Sigma * Delta);
+    const double iS = Delta * iSD;
+    const double iD = Sigma * iSD;
+    const double is2 = fm::rcp(s * s);
     const double W = -r2a2 - a * L;
     const double WiD = W * iD;
     State d;
@@ -137,7 +296,7 @@ __device__ __host__ inline double isco_radius(double a) {
 // observer replaces it where u.u = -1 has no solution. xi = L_z/E.
 __device__ __forceinline__ double redshift(double r, double th, double a, double a2, double xi) {
     double s, c;
-    sincos(th, &s, &c);
+    sincos_bounded(th, &s, &c);
     s = clamp_sin(s);
     const double s2 = s * s;
     const double Sigma = r * r + a2 * c * c;
@@ -166,7 +325,7 @@ __device__ __forceinline__ double redshift(double r, double th, double a, double
 __device__ inline double bessel_k2(double x) {
     if (x <= 2.0) {
         const double q = 0.25 * x * x;
-        const double lg = log(0.5 * x) + kEulerGamma;
+        const double lg = fm::log(0.5 * x) + kEulerGamma;
         double t = 0.5, hk = 0.0, hk2 = 1.5;
         double sum = t * (0.5 * (hk + hk2) - lg);
 #pragma unroll
@@ -179,19 +338,20 @@ __device__ inline double bessel_k2(double x) {
         return 2.0 / (x * x) - 0.5 + q * sum;
     }
     const double h = fmin(0.2, 0.6 / sqrt(x));
-    const double sh = sinh(0.5 * h);
+    const double u = 0.5 * h, u2 = u * u;  // sinh(u), u <= 0.1, Taylor through u^9
+    const double sh = u + u * u2 * (1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (1.0 / 5040.0 + u2 / 362880.0)));
     const double e1 = 2.0 * sh * sh;  // cosh(h) - 1
     const double c1 = 1.0 + e1;
     double em1 = 0.0, e = e1, sum = 0.5;
     for (int k = 1; k < 64; ++k) {
-        const double term = exp(-x * e) * (1.0 + 4.0 * e + 2.0 * e * e);
+        const double term = fm::exp(-x * e) * (1.0 + 4.0 * e + 2.0 * e * e);
         sum += term;
         if (term < 1e-18 * sum) break;
         const double en = 2.0 * c1 * e - em1 + 2.0 * e1;
         em1 = e;
         e = en;
     }
-    return h * exp(-x) * sum;
+    return h * fm::exp(-x) * sum;
 }
 
 // Torus and emission parameters in the form the kernels use.
@@ -217,10 +377,12 @@ __device__ inline Plasma torus_plasma(const TorusParams& P, double r, double th,
         q.ne = q.Te = q.nu_c = q.jpref = q.hkT = 0.0;
         return q;
     }
-    const double z = r * cos(th);
-    const double lx = log(r * P.inv_rnorm);
-    q.ne = P.n0 * exp(-P.n_index * lx - z * z * P.inv_2h2 / (r * r));
-    q.Te = P.T0 * exp(-P.T_index * lx);
+    double sth, cth;
+    sincos_bounded(th, &sth, &cth);
+    const double z = r * cth;
+    const double lx = fm::log(r * P.inv_rnorm);
+    q.ne = P.n0 * fm::exp(-P.n_index * lx - z * z * P.inv_2h2 / (r * r));
+    q.Te = P.T0 * fm::exp(-P.T_index * lx);
     const double B = sqrt(8.0 * kPi * P.eps_B * q.ne * kMp * kC * kC / (6.0 * r));
     const double theta_e = kKb * q.Te / (kMe * kC * kC);
     q.nu_c = 3.0 * kQe * B / (4.0 * kPi * kMe * kC) * theta_e * theta_e;
@@ -238,15 +400,17 @@ __device__ inline void torus_coeffs(const Plasma& q, const TorusParams& P, doubl
     }
     const double nu0 = nu / g;
     const double xm = nu0 / q.nu_c;
-    const double x3 = cbrt(xm);
-    const double x2 = sqrt(xm);
-    const double x4 = sqrt(x2);
-    const double x6 = sqrt(x3);
-    const double Mx = 4.0505 / x6 * (1.0 + 0.40 / x4 + 0.5316 / x2) * exp(-1.8899 * x3);  // Eq. (38)
-    const double j = nu0 * q.jpref * Mx;                                               // Eq. (37)/(4 pi)
+    double j = 0.0;
+    if (xm < 1e9) {  // beyond, exp(-1.8899 x^1/3) underflows to zero
+        // w = x^(-1/12): x^(-1/6) = w^2, x^(-1/4) = w^3, x^(-1/2) = w^6, x^(1/3) = x w^8
+        const double w = fm::inv_root<12>(fmax(xm, 1e-30));
+        const double w2 = w * w, w3 = w2 * w, w6 = w3 * w3, w8 = w6 * w2;
+        const double Mx = 4.0505 * w2 * (1.0 + 0.40 * w3 + 0.5316 * w6) * fm::exp(-1.8899 * (xm * w8));  // Eq. (38)
+        j = nu0 * q.jpref * Mx;                                                                          // Eq. (37)/(4 pi)
+    }
     double alpha = 0.0;
     if (j > 0.0) {
-        const double bnu = 2.0 * kH * nu0 * nu0 * nu0 / (kC * kC) / expm1(nu0 * q.hkT);
+        const double bnu = 2.0 * kH * nu0 * nu0 * nu0 / (kC * kC) / fm::expm1(nu0 * q.hkT);
         alpha = j / bnu;
     }
     a_lam = P.rg * alpha / g;
