@@ -104,7 +104,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="torus", choices=["torus", "thin_disk", "projection"])
+    ap.add_argument("--workload", default="torus", choices=["torus", "thin_disk", "projection", "batch"])
+    ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch shape first")
+    ap.add_argument("--baselines", action="store_true", help="batch: also time per-image launches")
+    ap.add_argument("--nfreq", type=int, default=1, help="calibration: number of frequencies (1 or 8)")
     ap.add_argument("--n", type=int, default=None, help="image side (default per workload)")
     ap.add_argument("--cpu-sample", type=int, default=40000, help="pixels in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--block", type=int, default=0)
@@ -132,7 +135,7 @@ def main():
     ctx.set_launch(args.block, args.blocks_per_cu, args.refill_min)
 
     if args.calibrate:
-        calibrate(ctx, args.calibrate, dev)
+        calibrate(ctx, args.calibrate, dev, args.nfreq)
         return
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -141,6 +144,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": src.numel() * 8, "copy_probe_bytes_written": dst.numel() * 8}))
+        return
+
+    if args.workload == "batch":
+        bench_batch(ctx, args, dev)
         return
 
     w, desc = workload(args.workload, args.n)
@@ -209,7 +216,70 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def calibrate(ctx, which: str, dev):
+def bench_batch(ctx, args, dev):
+    """256 uneven torus images at 8 frequencies in one persistent, graph-replayed launch."""
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    ws = scenes.batch_scenes(1603)
+    cams = [K.Camera(**w["camera"]) for w in ws]
+    mod, freqs, integ = K.Model(**ws[0]["model"]), list(ws[0]["freqs"]), K.Integrator(**ws[0]["integ"])
+    plan = K.Plan(ctx, cams, mod, freqs, integ)
+    out = plan.alloc_outputs(("status", "steps", "attempts", "intensity", "tau"))
+    stream = torch.cuda.current_stream()
+    tuned = plan.autotune(out) if args.autotune else None
+    for _ in range(args.warmup):
+        plan.launch(out, graph=True)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        plan.launch(out, graph=True)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sum(s.elapsed_time(e) for s, e in ev) / len(ev)
+    steps = int(out["steps"].to(torch.int64).sum())
+    attempts = int(out["attempts"].to(torch.int64).sum())
+    fpa, basis = FLOPS_PER_ATTEMPT.get("batch", (None, None))
+    line = {
+        "metric": METRIC, "value": round(ms * 1e6 / steps, 6), "unit": "ns/photon/RK step", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "256 uneven torus images (sides 64-512, a ~ U[0,0.998], incl ~ U[1,89] deg, "
+                               "seed 1603), 8 frequencies 86-690 GHz, one persistent launch replayed as a hipGraph",
+                   "rays": plan.num_rays, "images": len(cams), "autotuned": tuned},
+        "kernel_ms": round(ms, 3), "images_per_s": round(len(cams) / (ms * 1e-3), 3),
+        "rays_per_s": round(plan.num_rays / (ms * 1e-3), 1), "accepted_steps": steps, "attempted_steps": attempts,
+    }
+    if fpa:
+        ach = fpa * attempts / (ms * 1e-3) / 1e12
+        line["roofline"] = {"bound": "alu", "achieved": round(ach, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                            "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                            "flops_per_attempt": fpa, "flops_basis": basis, "kernel": "trace_kernel<torus,8>"}
+    if args.baselines:
+        for label, mode in (("per_image_persistent", K.LAUNCH_PERSISTENT),
+                            ("per_image_one_ray_per_thread", K.LAUNCH_ONE_RAY_PER_THREAD)):
+            ctx.set_launch(mode=mode)
+            per = [K.alloc_outputs(c.nx * c.ny, mod, len(freqs), dev, names=tuple(out)) for c in cams]
+            torch.cuda.synchronize()
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            for cam, view in zip(cams, per):
+                ctx.trace(cam, mod, freqs, integ, view)
+            s1.record(stream)
+            torch.cuda.synchronize()
+            bms = s0.elapsed_time(s1)
+            line[label] = {"ms": round(bms, 3), "images_per_s": round(len(cams) / (bms * 1e-3), 3),
+                           "batch_speedup": round(bms / ms, 3)}
+        ctx.set_launch()
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+def calibrate(ctx, which: str, dev, nfreq: int = 1):
     """Traces N identical copies of one ray: every wave runs converged, so the
     FP64 VALU instruction counters divided by the attempted steps give the
     arithmetic per step without divergence."""
@@ -217,7 +287,7 @@ def calibrate(ctx, which: str, dev):
 
     from paper_1601_02063_amd import kgrt as K
     from paper_1601_02063_amd import scenes
-    w = scenes.torus_image(16)
+    w = scenes.torus_image(16, freqs=(230e9,) if nfreq == 1 else scenes.batch_frequencies())
     mod, freqs, integ = K.Model(**w["model"]), list(w["freqs"]), K.Integrator(**w["integ"])
     nrays = 256 * 1024
     ray = torch.tensor(CALIBRATION_RAYS[which], dtype=torch.float64, device=dev)
@@ -227,7 +297,7 @@ def calibrate(ctx, which: str, dev):
     torch.cuda.synchronize()
     att = out["attempts"]
     assert int(att.min()) == int(att.max()), "copies of one ray must take identical step sequences"
-    print(json.dumps({"calibration_ray": which, "ray": CALIBRATION_RAYS[which], "rays": nrays,
+    print(json.dumps({"calibration_ray": which, "nfreq": len(freqs), "ray": CALIBRATION_RAYS[which], "rays": nrays,
                       "attempts_per_ray": int(att[0]), "steps_per_ray": int(out["steps"][0]),
                       "total_attempts": int(att.to(torch.int64).sum())}), flush=True)
 

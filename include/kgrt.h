@@ -112,15 +112,24 @@ typedef struct kgrt_outputs {
     double* tau;        /* torus: [nfreq][n] optical depth along the ray */
 } kgrt_outputs;
 
-/* Launch shape of the persistent integrator kernel. Zeros select defaults. */
+/* Launch modes. */
+#define KGRT_LAUNCH_PERSISTENT 0          /* persistent grid, idle lanes refilled from a ray queue */
+#define KGRT_LAUNCH_ONE_RAY_PER_THREAD 1  /* one ray per thread, no queue: the paper's mapping (section 3,
+                                             Fig. 1), kept as the in-house baseline */
+
+/* Launch shape of the integrator kernel. Zeros select defaults. */
 typedef struct kgrt_launch {
-    int32_t block;          /* threads per block: 64, 128, 256 or 512 (default 256) */
+    int32_t block;          /* threads per block: 64, 128 or 256 (default 256) */
     int32_t blocks_per_cu;  /* resident blocks per compute unit (default: occupancy limit) */
     int32_t refill_min;     /* refill a wave only when at least this many lanes are idle (1..64, default 1) */
-    int32_t reserved;       /* must be 0 */
+    int32_t mode;           /* KGRT_LAUNCH_* (default persistent) */
 } kgrt_launch;
 
+/* Plan launch flags. */
+#define KGRT_PLAN_GRAPH 1u  /* replay the plan's kernels as one captured hipGraph */
+
 typedef struct kgrt_ctx kgrt_ctx;
+typedef struct kgrt_plan kgrt_plan;
 
 /* -------------------------------------------------------------- context */
 
@@ -155,6 +164,42 @@ int kgrt_trace(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, c
 int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_obs, double phi_obs_deg,
                     const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
                     const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
+
+/* ------------------------------------------------------------ batches */
+
+/* A plan holds many images of uneven size, spin and inclination (one model,
+ * one frequency set, one integrator) traced together in one persistent launch
+ * per chunk of rays. This generalises the paper's per-image tracing (section
+ * 3) to scene batches. The rays of image k occupy output indices
+ * [offset_k, offset_k + nx_k ny_k), offsets the prefix sums of the image sizes
+ * in the order given; torus outputs are [nfreq][total rays].
+ * kgrt_plan_create validates every camera (as kgrt_trace does; empty images are
+ * allowed), uploads the image table and allocates the plan's workspace
+ * (synchronously). The plan keeps a pointer to ctx; destroy plans first. */
+int kgrt_plan_create(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const kgrt_model* model,
+                     const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, kgrt_plan** out);
+/* Total number of rays (sum of image sizes). */
+int64_t kgrt_plan_num_rays(const kgrt_plan* plan);
+/* Launches the plan on `stream` (asynchronous). With KGRT_PLAN_GRAPH the
+ * kernels are captured once into a hipGraph (on a stream private to the plan)
+ * and replayed; a new capture happens when the output pointers or the launch
+ * shape change. Two launches of one plan must not overlap in time. */
+int kgrt_plan_launch(kgrt_plan* plan, const kgrt_outputs* out, uint32_t flags, void* stream);
+/* Times candidate launch shapes (block 64/128/256, residency, refill
+ * granularity) on the plan's first <= 524288 rays and keeps the fastest for
+ * later launches; writes it to *best if best != NULL. Synchronous: it waits
+ * for `stream`. Outputs of the sampled rays are overwritten. */
+int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, kgrt_launch* best);
+/* Sets the plan's launch shape explicitly (NULL = context default). */
+int kgrt_plan_set_launch(kgrt_plan* plan, const kgrt_launch* launch);
+/* Releases the plan (waits for its private stream; the caller must make sure
+ * no launch of it is still running on other streams). NULL is a no-op. */
+int kgrt_plan_destroy(kgrt_plan* plan);
+
+/* One-shot batch: plan, launch, wait for `stream`, destroy. */
+int kgrt_trace_batch(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const kgrt_model* model,
+                     const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out,
+                     void* stream);
 
 /* Error strings. kgrt_last_error returns the context's last message ("" if none). */
 const char* kgrt_strerror(int code);

@@ -59,6 +59,7 @@ struct KParams {
     int32_t max_steps;
     uint32_t flags;
     int32_t refill_min;
+    int32_t naive;  // 1: one ray per thread, no queue (the paper's mapping, kept as a baseline)
     Outputs out;
 };
 
@@ -194,7 +195,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
     constexpr bool kDisk = (MODEL != KGRT_MODEL_TORUS);
     const int lane = __lane_id();
     const uint64_t lane_mask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    bool active = false, done = false;
+    bool active = false, done = false, fresh = true;
     int64_t rid = 0;
     State y{};
     double h = 0.0, a = 0.0, a2 = 0.0, L = 0.0, r_cap = 0.0, r_in = 0.0, r_obs = 0.0;
@@ -218,13 +219,19 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
         const uint64_t want = __ballot(need);
         if (want != 0ull) {
             const int cnt = __popcll(want);
-            if (cnt >= P.refill_min || __ballot(active) == 0ull) {
-                const int leader = __ffsll((unsigned long long)want) - 1;
+            if (P.naive || cnt >= P.refill_min || __ballot(active) == 0ull) {
                 unsigned long long qb = 0ull;
-                if (lane == leader) qb = atomicAdd(P.counter, (unsigned long long)cnt);
-                qb = __shfl(qb, leader);
+                if (!P.naive) {
+                    const int leader = __ffsll((unsigned long long)want) - 1;
+                    if (lane == leader) qb = atomicAdd(P.counter, (unsigned long long)cnt);
+                    qb = __shfl(qb, leader);
+                }
                 if (need) {
-                    const unsigned long long my = qb + (unsigned long long)__popcll(want & lane_mask_lt);
+                    unsigned long long my = qb + (unsigned long long)__popcll(want & lane_mask_lt);
+                    if (P.naive) {
+                        my = fresh ? (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x : ~0ull;
+                        fresh = false;
+                    }
                     if (my < (unsigned long long)count) {
                         const int64_t k = (int64_t)my;
                         rid = base + k;
@@ -529,6 +536,11 @@ ImageDesc make_image(const kgrt_camera* c, const kgrt_model* m, double horizon_d
     return d;
 }
 
+void set_outputs(KParams& P, const kgrt_outputs* o) {
+    P.out = Outputs{o->status, o->steps, o->attempts, o->r_cross, o->g, o->phi_cross, o->t_cross,
+                    o->intensity, o->i_bol, o->tau};
+}
+
 void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t nfreq, const kgrt_integrator* in,
                  const kgrt_outputs* o, const kgrt_ctx* ctx) {
     P.model = m->kind;
@@ -551,10 +563,7 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     P.horizon_delta = in->horizon_delta;
     P.max_steps = in->max_steps;
     P.flags = in->flags;
-    P.refill_min = (ctx->launch.refill_min >= 1 && ctx->launch.refill_min <= 64) ? ctx->launch.refill_min : 1;
-    P.out = Outputs{o->status, o->steps, o->attempts, o->r_cross, o->g, o->phi_cross, o->t_cross,
-                    o->intensity, o->i_bol, o->tau};
-    P.counter = ctx->counter;
+    if (o) set_outputs(P, o);
 }
 
 // Grows the ray-start workspace to hold `n` rays (capped at one chunk).
@@ -576,38 +585,58 @@ int ensure_workspace(kgrt_ctx* ctx, int64_t n) {
     return KGRT_OK;
 }
 
+// Where one trace's kernels run: workspace, counter and launch shape.
+struct LaunchEnv {
+    double* rec;
+    int64_t rec_cap;
+    unsigned long long* counter;
+    kgrt_launch launch;
+    int num_cus;
+    int64_t limit;  // trace only the first `limit` rays (autotuner sampling); < 0 = all
+};
+
 template <int MODEL, int NF>
-int launch_one(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
-    const int block = (ctx->launch.block == 64 || ctx->launch.block == 128) ? ctx->launch.block : 256;
+int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
+    const int block = (env.launch.block == 64 || env.launch.block == 128) ? env.launch.block : 256;
     auto kern = trace_kernel<MODEL, NF>;
-    int per_cu = ctx->launch.blocks_per_cu;
+    int per_cu = env.launch.blocks_per_cu;
     if (per_cu <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
     }
-    const int64_t cap = ctx->rec_cap;
-    for (int64_t base = 0; base < P.nrays; base += cap) {
-        const int64_t count = std::min<int64_t>(cap, P.nrays - base);
+    P.counter = env.counter;
+    P.naive = (env.launch.mode == KGRT_LAUNCH_ONE_RAY_PER_THREAD) ? 1 : 0;
+    P.refill_min = (env.launch.refill_min >= 1 && env.launch.refill_min <= 64) ? env.launch.refill_min : 1;
+    const int64_t total = (env.limit >= 0) ? std::min<int64_t>(env.limit, P.nrays) : P.nrays;
+    const int64_t cap = env.rec_cap;
+    for (int64_t base = 0; base < total; base += cap) {
+        const int64_t count = std::min<int64_t>(cap, total - base);
         const int64_t need = (count + block - 1) / block;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)ctx->num_cus * per_cu));
-        const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, (int64_t)ctx->num_cus * 16));
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, ctx->counter);
-        hipLaunchKernelGGL(start_kernel, dim3(sgrid), dim3(256), 0, st, P, base, count, ctx->rec, cap);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, P, base, count, (const double*)ctx->rec, cap);
+        const int grid = P.naive ? (int)need
+                                 : (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)env.num_cus * per_cu));
+        const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, (int64_t)env.num_cus * 16));
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, env.counter);
+        hipLaunchKernelGGL(start_kernel, dim3(sgrid), dim3(256), 0, st, P, base, count, env.rec, cap);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, P, base, count, (const double*)env.rec, cap);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(ctx, KGRT_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     }
     return KGRT_OK;
 }
 
+int dispatch_env(kgrt_ctx* ctx, const LaunchEnv& env, const KParams& P, hipStream_t st) {
+    if (P.model != KGRT_MODEL_TORUS) return launch_one<KGRT_MODEL_THIN_DISK, 1>(ctx, env, P, st);
+    if (P.nf <= 1) return launch_one<KGRT_MODEL_TORUS, 1>(ctx, env, P, st);
+    if (P.nf <= 2) return launch_one<KGRT_MODEL_TORUS, 2>(ctx, env, P, st);
+    if (P.nf <= 4) return launch_one<KGRT_MODEL_TORUS, 4>(ctx, env, P, st);
+    if (P.nf <= 8) return launch_one<KGRT_MODEL_TORUS, 8>(ctx, env, P, st);
+    return launch_one<KGRT_MODEL_TORUS, 16>(ctx, env, P, st);
+}
+
 int dispatch(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
     const int rc = ensure_workspace(ctx, P.nrays);
     if (rc != KGRT_OK) return rc;
-    if (P.model != KGRT_MODEL_TORUS) return launch_one<KGRT_MODEL_THIN_DISK, 1>(ctx, P, st);
-    if (P.nf <= 1) return launch_one<KGRT_MODEL_TORUS, 1>(ctx, P, st);
-    if (P.nf <= 2) return launch_one<KGRT_MODEL_TORUS, 2>(ctx, P, st);
-    if (P.nf <= 4) return launch_one<KGRT_MODEL_TORUS, 4>(ctx, P, st);
-    if (P.nf <= 8) return launch_one<KGRT_MODEL_TORUS, 8>(ctx, P, st);
-    return launch_one<KGRT_MODEL_TORUS, 16>(ctx, P, st);
+    const LaunchEnv env{ctx->rec, ctx->rec_cap, ctx->counter, ctx->launch, ctx->num_cus, -1};
+    return dispatch_env(ctx, env, P, st);
 }
 
 struct DeviceGuard {
@@ -686,7 +715,8 @@ int kgrt_ctx_set_launch(kgrt_ctx* ctx, const kgrt_launch* l) {
     if (l->block == 512) return fail(ctx, KGRT_E_UNSUPPORTED, "launch.block 512 exceeds the kernel's launch bounds");
     if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64) return fail(ctx, KGRT_E_INVALID_ARG, "launch.blocks_per_cu must be in [0, 64]");
     if (l->refill_min < 0 || l->refill_min > 64) return fail(ctx, KGRT_E_INVALID_ARG, "launch.refill_min must be in [0, 64]");
-    if (l->reserved != 0) return fail(ctx, KGRT_E_INVALID_ARG, "launch.reserved must be 0");
+    if (l->mode != KGRT_LAUNCH_PERSISTENT && l->mode != KGRT_LAUNCH_ONE_RAY_PER_THREAD)
+        return fail(ctx, KGRT_E_INVALID_ARG, "launch.mode must be KGRT_LAUNCH_PERSISTENT or KGRT_LAUNCH_ONE_RAY_PER_THREAD");
     ctx->launch = *l;
     return KGRT_OK;
 }
@@ -743,6 +773,216 @@ int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_o
     P.list_cos_p = std::cos(pho);
     fill_common(P, model, freqs_hz, nfreq, integ, out, ctx);
     return dispatch(ctx, P, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+struct kgrt_plan {
+    kgrt_ctx* ctx = nullptr;
+    KParams P{};
+    ImageDesc* images = nullptr;
+    double* rec = nullptr;
+    int64_t rec_cap = 0;
+    unsigned long long* counter = nullptr;
+    kgrt_launch launch{};
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    kgrt_outputs graph_out{};
+    kgrt_launch graph_launch{};
+};
+
+namespace {
+
+void drop_graph(kgrt_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+bool same_outputs(const kgrt_outputs& a, const kgrt_outputs& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+bool same_launch(const kgrt_launch& a, const kgrt_launch& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+int plan_enqueue(kgrt_plan* p, const kgrt_outputs* out, hipStream_t st, int64_t limit) {
+    KParams P = p->P;
+    set_outputs(P, out);
+    const LaunchEnv env{p->rec, p->rec_cap, p->counter, p->launch, p->ctx->num_cus, limit};
+    return dispatch_env(p->ctx, env, P, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int kgrt_plan_create(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const kgrt_model* model,
+                     const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, kgrt_plan** out) {
+    if (!ctx) return KGRT_E_INVALID_ARG;
+    if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nimg < 1 || !cams) return fail(ctx, KGRT_E_INVALID_ARG, "a plan needs nimg >= 1 cameras");
+    std::string msg;
+    for (int32_t k = 0; k < nimg; ++k) {
+        const int rc = check(msg, &cams[k], model, freqs_hz, nfreq, integ);
+        if (rc != KGRT_OK) return fail(ctx, rc, "camera " + std::to_string(k) + ": " + msg);
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    std::vector<ImageDesc> tab(nimg);
+    int64_t total = 0;
+    for (int32_t k = 0; k < nimg; ++k) {
+        tab[k] = make_image(&cams[k], model, integ->horizon_delta, total);
+        total += (int64_t)cams[k].nx * (int64_t)cams[k].ny;
+    }
+    auto* p = new (std::nothrow) kgrt_plan();
+    if (!p) return fail(ctx, KGRT_E_NOMEM, "plan allocation failed");
+    p->ctx = ctx;
+    p->launch = ctx->launch;
+    KParams& P = p->P;
+    fill_common(P, model, freqs_hz, nfreq, integ, nullptr, ctx);
+    P.image0 = tab[0];
+    P.nimg = nimg;
+    P.list_mode = 0;
+    P.nrays = total;
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(total, ctx->chunk_max));
+    bool ok = hipMalloc(&p->images, sizeof(ImageDesc) * nimg) == hipSuccess &&
+              hipMalloc(&p->rec, (size_t)cap * kRecFields * sizeof(double)) == hipSuccess &&
+              hipMalloc(&p->counter, sizeof(unsigned long long)) == hipSuccess &&
+              hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipMemcpy(p->images, tab.data(), sizeof(ImageDesc) * nimg, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        kgrt_plan_destroy(p);
+        return fail(ctx, KGRT_E_NOMEM, "plan workspace allocation failed");
+    }
+    p->rec_cap = cap;
+    P.images = p->images;
+    *out = p;
+    return KGRT_OK;
+}
+
+int64_t kgrt_plan_num_rays(const kgrt_plan* plan) { return plan ? plan->P.nrays : 0; }
+
+int kgrt_plan_set_launch(kgrt_plan* plan, const kgrt_launch* l) {
+    if (!plan) return KGRT_E_INVALID_ARG;
+    kgrt_ctx* ctx = plan->ctx;
+    if (!l) {
+        plan->launch = ctx->launch;
+        return KGRT_OK;
+    }
+    const kgrt_launch keep = ctx->launch;
+    const int rc = kgrt_ctx_set_launch(ctx, l);  // same validation
+    if (rc == KGRT_OK) plan->launch = ctx->launch;
+    ctx->launch = keep;
+    return rc;
+}
+
+int kgrt_plan_launch(kgrt_plan* plan, const kgrt_outputs* out, uint32_t flags, void* stream) {
+    if (!plan) return KGRT_E_INVALID_ARG;
+    kgrt_ctx* ctx = plan->ctx;
+    if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "outputs is NULL");
+    if (flags & ~KGRT_PLAN_GRAPH) return fail(ctx, KGRT_E_INVALID_ARG, "unknown plan flags");
+    if (plan->P.nrays == 0) return KGRT_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & KGRT_PLAN_GRAPH)) return plan_enqueue(plan, out, st, -1);
+    if (!plan->exec || !same_outputs(plan->graph_out, *out) || !same_launch(plan->graph_launch, plan->launch)) {
+        drop_graph(plan);
+        if (hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(ctx, KGRT_E_HIP, "hipStreamBeginCapture failed");
+        const int rc = plan_enqueue(plan, out, plan->capture_stream, -1);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(plan->capture_stream, &graph);
+        if (rc != KGRT_OK || e != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc != KGRT_OK ? rc : fail(ctx, KGRT_E_HIP, "hipStreamEndCapture failed");
+        }
+        plan->graph = graph;
+        if (hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(plan);
+            return fail(ctx, KGRT_E_HIP, "hipGraphInstantiate failed");
+        }
+        plan->graph_out = *out;
+        plan->graph_launch = plan->launch;
+    }
+    if (hipGraphLaunch(plan->exec, st) != hipSuccess) return fail(ctx, KGRT_E_HIP, "hipGraphLaunch failed");
+    return KGRT_OK;
+}
+
+int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, kgrt_launch* best) {
+    if (!plan) return KGRT_E_INVALID_ARG;
+    kgrt_ctx* ctx = plan->ctx;
+    if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "outputs is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t sample = std::min<int64_t>(plan->P.nrays, 524288);
+    if (sample == 0) {
+        if (best) *best = plan->launch;
+        return KGRT_OK;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, KGRT_E_HIP, "hipEventCreate failed");
+    const kgrt_launch base = plan->launch;
+    kgrt_launch winner = base;
+    float best_ms = 1e30f;
+    int rc = KGRT_OK;
+    for (int block : {64, 128, 256}) {
+        for (int per_cu : {0, 1, 2}) {
+            for (int refill : {1, 16}) {
+                plan->launch = kgrt_launch{block, per_cu, refill, KGRT_LAUNCH_PERSISTENT};
+                rc = plan_enqueue(plan, out, st, sample);  // warm-up
+                if (rc != KGRT_OK) break;
+                (void)hipEventRecord(e0, st);
+                rc = plan_enqueue(plan, out, st, sample);
+                (void)hipEventRecord(e1, st);
+                if (rc != KGRT_OK || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = (rc != KGRT_OK) ? rc : fail(ctx, KGRT_E_HIP, "autotune timing failed");
+                    break;
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    winner = plan->launch;
+                }
+            }
+            if (rc != KGRT_OK) break;
+        }
+        if (rc != KGRT_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->launch = (rc == KGRT_OK) ? winner : base;
+    if (best) *best = plan->launch;
+    return rc;
+}
+
+int kgrt_plan_destroy(kgrt_plan* plan) {
+    if (!plan) return KGRT_OK;
+    DeviceGuard g(plan->ctx->device);
+    if (plan->capture_stream) (void)hipStreamSynchronize(plan->capture_stream);
+    drop_graph(plan);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    if (plan->images) (void)hipFree(plan->images);
+    if (plan->rec) (void)hipFree(plan->rec);
+    if (plan->counter) (void)hipFree(plan->counter);
+    delete plan;
+    return KGRT_OK;
+}
+
+int kgrt_trace_batch(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const kgrt_model* model,
+                     const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out,
+                     void* stream) {
+    kgrt_plan* p = nullptr;
+    int rc = kgrt_plan_create(ctx, cams, nimg, model, freqs_hz, nfreq, integ, &p);
+    if (rc != KGRT_OK) return rc;
+    rc = kgrt_plan_launch(p, out, 0u, stream);
+    if (rc == KGRT_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        rc = fail(ctx, KGRT_E_HIP, "hipStreamSynchronize failed");
+    kgrt_plan_destroy(p);
+    return rc;
 }
 
 }  // extern "C"

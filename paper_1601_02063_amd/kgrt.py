@@ -59,7 +59,15 @@ class COutputs(ctypes.Structure):
 
 class CLaunch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("refill_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("refill_min", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"block": self.block, "blocks_per_cu": self.blocks_per_cu, "refill_min": self.refill_min,
+                "mode": self.mode}
+
+
+LAUNCH_PERSISTENT, LAUNCH_ONE_RAY_PER_THREAD = 0, 1
+PLAN_GRAPH = 1
 
 
 # ---------------------------------------------------------------- parameters
@@ -138,6 +146,15 @@ def lib() -> ctypes.CDLL:
         L.kgrt_trace.restype = ctypes.c_int
         L.kgrt_trace_rays.argtypes = [vp, vp, i64, d, d, P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
         L.kgrt_trace_rays.restype = ctypes.c_int
+        L.kgrt_plan_create.argtypes = [vp, vp, i32, P(CModel), P(d), i32, P(CIntegrator), P(vp)]
+        L.kgrt_plan_create.restype = ctypes.c_int
+        L.kgrt_plan_num_rays.argtypes, L.kgrt_plan_num_rays.restype = [vp], i64
+        L.kgrt_plan_launch.argtypes, L.kgrt_plan_launch.restype = [vp, P(COutputs), ctypes.c_uint32, vp], ctypes.c_int
+        L.kgrt_plan_autotune.argtypes, L.kgrt_plan_autotune.restype = [vp, P(COutputs), vp, P(CLaunch)], ctypes.c_int
+        L.kgrt_plan_set_launch.argtypes, L.kgrt_plan_set_launch.restype = [vp, P(CLaunch)], ctypes.c_int
+        L.kgrt_plan_destroy.argtypes, L.kgrt_plan_destroy.restype = [vp], ctypes.c_int
+        L.kgrt_trace_batch.argtypes = [vp, vp, i32, P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
+        L.kgrt_trace_batch.restype = ctypes.c_int
         L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
         L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
@@ -203,8 +220,8 @@ class Context:
     def num_cus(self) -> int:
         return lib().kgrt_ctx_num_cus(self._h)
 
-    def set_launch(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0):
-        self._check(lib().kgrt_ctx_set_launch(self._h, ctypes.byref(CLaunch(block, blocks_per_cu, refill_min, 0))))
+    def set_launch(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0, mode: int = 0):
+        self._check(lib().kgrt_ctx_set_launch(self._h, ctypes.byref(CLaunch(block, blocks_per_cu, refill_min, mode))))
 
     def _outputs(self, outs: Dict[str, torch.Tensor], n: int, nf: int, model: Model) -> COutputs:
         o = COutputs()
@@ -239,6 +256,68 @@ class Context:
         self._check(lib().kgrt_trace_rays(self._h, rays.data_ptr() if n else None, n, r_obs, phi_obs_deg,
                                           ctypes.byref(model.c()), fa, nf, ctypes.byref(integ.c()),
                                           ctypes.byref(o), _stream_handle(stream)))
+
+
+    def trace_batch(self, cameras: Sequence[Camera], model: Model, freqs: Sequence[float], integ: Integrator,
+                    outs: Dict[str, torch.Tensor], stream=None):
+        """kgrt_trace_batch: images concatenated in order; waits for the stream."""
+        cams = (CCamera * len(cameras))(*[c.c() for c in cameras])
+        n = sum(c.nx * c.ny for c in cameras)
+        fa, nf = _freqs(freqs)
+        o = self._outputs(outs, n, max(nf, 1), model)
+        self._check(lib().kgrt_trace_batch(self._h, cams, len(cameras), ctypes.byref(model.c()), fa, nf,
+                                           ctypes.byref(integ.c()), ctypes.byref(o), _stream_handle(stream)))
+
+
+class Plan:
+    """kgrt_plan: many images of uneven size, spin and inclination in one persistent launch."""
+
+    def __init__(self, ctx: Context, cameras: Sequence[Camera], model: Model, freqs: Sequence[float],
+                 integ: Integrator):
+        self.ctx, self.model, self.freqs = ctx, model, list(freqs)
+        cams = (CCamera * len(cameras))(*[c.c() for c in cameras])
+        fa, nf = _freqs(freqs)
+        h = ctypes.c_void_p()
+        ctx._check(lib().kgrt_plan_create(ctx._h, cams, len(cameras), ctypes.byref(model.c()), fa, nf,
+                                          ctypes.byref(integ.c()), ctypes.byref(h)))
+        self._h = h
+        sizes = [c.nx * c.ny for c in cameras]
+        self.offsets = [0]
+        for n in sizes:
+            self.offsets.append(self.offsets[-1] + n)
+        self.num_rays = int(lib().kgrt_plan_num_rays(h))
+        assert self.num_rays == self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kgrt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_outputs(self, names: Iterable[str] = OUTPUT_FIELDS):
+        return alloc_outputs(self.num_rays, self.model, len(self.freqs), self.ctx.device, names)
+
+    def launch(self, outs: Dict[str, torch.Tensor], graph: bool = False, stream=None):
+        o = self.ctx._outputs(outs, self.num_rays, max(len(self.freqs), 1), self.model)
+        self._keep = o
+        self.ctx._check(lib().kgrt_plan_launch(self._h, ctypes.byref(o), PLAN_GRAPH if graph else 0,
+                                               _stream_handle(stream)))
+
+    def autotune(self, outs: Dict[str, torch.Tensor], stream=None) -> dict:
+        o = self.ctx._outputs(outs, self.num_rays, max(len(self.freqs), 1), self.model)
+        best = CLaunch()
+        self.ctx._check(lib().kgrt_plan_autotune(self._h, ctypes.byref(o), _stream_handle(stream),
+                                                 ctypes.byref(best)))
+        return best.as_dict()
+
+    def set_launch(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0, mode: int = 0):
+        self.ctx._check(lib().kgrt_plan_set_launch(self._h, ctypes.byref(CLaunch(block, blocks_per_cu,
+                                                                                 refill_min, mode))))
 
 
 def alloc_outputs(n: int, model: Model, nfreq: int, device, names: Iterable[str] = OUTPUT_FIELDS):
