@@ -201,6 +201,54 @@ int kgrt_trace_batch(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const
                      const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out,
                      void* stream);
 
+/* ----------------------------------------------------------- surrogate */
+
+/* A learned surrogate of the integrator: a perceptron 4 -> 256 -> 256 -> 256 -> 256 -> 5
+ * with SiLU on the hidden layers, mapping ray features (a, cos(inclination),
+ * x/15, y/15) to (capture logit, log r_c, g, sin phi_c, cos phi_c) of the first
+ * equatorial crossing (section 4.3 thin-disk quantities). Weights and
+ * activations are BF16 with FP32 accumulation (MFMA) on the 256x256 layers;
+ * the input layer and the output head run in FP32. Parameters are one FP32
+ * vector, layer by layer W[out][in] then b[out] (199941 values). */
+typedef struct kgrt_mlp kgrt_mlp;
+typedef struct kgrt_adam {
+    float lr, beta1, beta2, eps;  /* Kingma & Ba (2015) */
+} kgrt_adam;
+
+/* Number of parameters (199941). */
+int64_t kgrt_mlp_num_params(void);
+/* Creates a network on the current device of ctx with workspace for batches
+ * of up to max_batch samples (16 <= max_batch <= 2^24, a multiple of 16).
+ * Parameters are undefined until kgrt_mlp_set_params. */
+int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out);
+int kgrt_mlp_destroy(kgrt_mlp* mlp);
+const char* kgrt_mlp_last_error(const kgrt_mlp* mlp);
+/* Host FP32 parameter vector in/out (synchronous). set_params also resets Adam. */
+int kgrt_mlp_set_params(kgrt_mlp* mlp, const float* params_host, int64_t n);
+int kgrt_mlp_get_params(kgrt_mlp* mlp, float* params_host, int64_t n);
+/* Inference: x_dev [n][4] FP32 features -> y_dev [n][5] FP32 outputs, any n >= 0. */
+int kgrt_mlp_forward(kgrt_mlp* mlp, const float* x_dev, float* y_dev, int64_t n, void* stream);
+/* Loss and gradients of one batch. x_dev [*][4] features, t_dev [*][6] targets
+ * (capture 0/1, log r_c, g, sin phi_c, cos phi_c, phi valid 0/1); the batch is
+ * rows idx_dev[0..n) (int32, device) or rows 0..n if idx_dev is NULL;
+ * 32 <= n <= max_batch, n a multiple of 32. Loss per sample:
+ * BCE-with-logits(o0, t0) + 10 (o1-t1)^2 + 10 (o2-t2)^2 + t5 ((o3-t3)^2 + (o4-t4)^2),
+ * averaged; written to loss_dev (one float). If grads_dev is not NULL the
+ * gradient (num_params floats) is copied there. */
+int kgrt_mlp_loss_grads(kgrt_mlp* mlp, const float* x_dev, const float* t_dev, const int32_t* idx_dev, int64_t n,
+                        float* loss_dev, float* grads_dev, void* stream);
+/* One Adam step on the batch (as kgrt_mlp_loss_grads), then refreshes the BF16 weights. */
+int kgrt_mlp_train_step(kgrt_mlp* mlp, const float* x_dev, const float* t_dev, const int32_t* idx_dev, int64_t n,
+                        const kgrt_adam* opt, float* loss_dev, void* stream);
+/* Ray features (a, cos(incl), x/15, y/15) from rays_dev [n][4] = (a, incl_deg, x, y). */
+int kgrt_surrogate_features(const double* rays_dev, int64_t n, float* features_dev, void* stream);
+/* Training targets [n][6] from integrator outputs of the same rays (thin-disk or
+ * geodesic model): rays without a recorded crossing get r_c = r_+, g = 0 and no
+ * phi target. */
+int kgrt_surrogate_targets(const double* rays_dev, const int32_t* status_dev, const double* r_cross_dev,
+                           const double* g_dev, const double* phi_cross_dev, int64_t n, float* targets_dev,
+                           void* stream);
+
 /* Error strings. kgrt_last_error returns the context's last message ("" if none). */
 const char* kgrt_strerror(int code);
 const char* kgrt_last_error(const kgrt_ctx* ctx);

@@ -66,6 +66,10 @@ class CLaunch(ctypes.Structure):
                 "mode": self.mode}
 
 
+class CAdam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 LAUNCH_PERSISTENT, LAUNCH_ONE_RAY_PER_THREAD = 0, 1
 PLAN_GRAPH = 1
 
@@ -155,6 +159,21 @@ def lib() -> ctypes.CDLL:
         L.kgrt_plan_destroy.argtypes, L.kgrt_plan_destroy.restype = [vp], ctypes.c_int
         L.kgrt_trace_batch.argtypes = [vp, vp, i32, P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
         L.kgrt_trace_batch.restype = ctypes.c_int
+        fp = P(ctypes.c_float)
+        L.kgrt_mlp_num_params.argtypes, L.kgrt_mlp_num_params.restype = [], i64
+        L.kgrt_mlp_create.argtypes, L.kgrt_mlp_create.restype = [vp, i64, P(vp)], ctypes.c_int
+        L.kgrt_mlp_destroy.argtypes, L.kgrt_mlp_destroy.restype = [vp], ctypes.c_int
+        L.kgrt_mlp_last_error.argtypes, L.kgrt_mlp_last_error.restype = [vp], ctypes.c_char_p
+        L.kgrt_mlp_set_params.argtypes, L.kgrt_mlp_set_params.restype = [vp, vp, i64], ctypes.c_int
+        L.kgrt_mlp_get_params.argtypes, L.kgrt_mlp_get_params.restype = [vp, vp, i64], ctypes.c_int
+        L.kgrt_mlp_forward.argtypes, L.kgrt_mlp_forward.restype = [vp, vp, vp, i64, vp], ctypes.c_int
+        L.kgrt_mlp_loss_grads.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+        L.kgrt_mlp_loss_grads.restype = ctypes.c_int
+        L.kgrt_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, P(CAdam), vp, vp]
+        L.kgrt_mlp_train_step.restype = ctypes.c_int
+        L.kgrt_surrogate_features.argtypes, L.kgrt_surrogate_features.restype = [vp, i64, vp, vp], ctypes.c_int
+        L.kgrt_surrogate_targets.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.kgrt_surrogate_targets.restype = ctypes.c_int
         L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
         L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
@@ -341,3 +360,99 @@ def trace_image(ctx: Context, camera: Camera, model: Model, freqs: Sequence[floa
     out = alloc_outputs(camera.nx * camera.ny, model, len(freqs), ctx.device, names)
     ctx.trace(camera, model, freqs, integ, out, stream)
     return out
+
+
+# ------------------------------------------------------------ surrogate
+
+def _dev_check(t: torch.Tensor, dtype, shape_tail, name):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor of shape [n, {shape_tail}]")
+
+
+class Mlp:
+    """kgrt_mlp: the surrogate network (BF16-MFMA hidden layers, FP32 head, Adam)."""
+
+    def __init__(self, ctx: Context, max_batch: int = 65536):
+        self.ctx = ctx
+        self.max_batch = max_batch
+        h = ctypes.c_void_p()
+        rc = lib().kgrt_mlp_create(ctx._h, max_batch, ctypes.byref(h))
+        if rc != OK:
+            raise KgrtError(rc, "kgrt_mlp_create failed")
+        self._h = h
+
+    @staticmethod
+    def num_params() -> int:
+        return int(lib().kgrt_mlp_num_params())
+
+    def _check(self, rc):
+        if rc != OK:
+            raise KgrtError(rc, lib().kgrt_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kgrt_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().kgrt_mlp_set_params(self._h, p.ctypes.data, p.size))
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(self.num_params(), dtype=np.float32)
+        self._check(lib().kgrt_mlp_get_params(self._h, p.ctypes.data, p.size))
+        return p
+
+    def forward(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _dev_check(x, torch.float32, (4,), "x")
+        y = out if out is not None else torch.empty((x.shape[0], 5), dtype=torch.float32, device=x.device)
+        self._check(lib().kgrt_mlp_forward(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], _stream_handle(stream)))
+        return y
+
+    def loss_grads(self, x: torch.Tensor, t: torch.Tensor, idx: Optional[torch.Tensor] = None,
+                   n: Optional[int] = None, stream=None):
+        _dev_check(x, torch.float32, (4,), "x")
+        _dev_check(t, torch.float32, (6,), "t")
+        n = n if n is not None else (idx.numel() if idx is not None else x.shape[0])
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        grads = torch.empty(self.num_params(), dtype=torch.float32, device=x.device)
+        self._check(lib().kgrt_mlp_loss_grads(self._h, x.data_ptr(), t.data_ptr(),
+                                              idx.data_ptr() if idx is not None else None, n, loss.data_ptr(),
+                                              grads.data_ptr(), _stream_handle(stream)))
+        return loss, grads
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, idx: Optional[torch.Tensor], n: int, lr: float,
+                   loss: torch.Tensor, betas=(0.9, 0.999), eps: float = 1e-8, stream=None):
+        opt = CAdam(lr, betas[0], betas[1], eps)
+        self._check(lib().kgrt_mlp_train_step(self._h, x.data_ptr(), t.data_ptr(),
+                                              idx.data_ptr() if idx is not None else None, n, ctypes.byref(opt),
+                                              loss.data_ptr(), _stream_handle(stream)))
+
+
+def surrogate_features(rays: torch.Tensor, stream=None) -> torch.Tensor:
+    _dev_check(rays, torch.float64, (4,), "rays")
+    f = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
+    rc = lib().kgrt_surrogate_features(rays.data_ptr(), rays.shape[0], f.data_ptr(), _stream_handle(stream))
+    if rc != OK:
+        raise KgrtError(rc, "kgrt_surrogate_features failed")
+    return f
+
+
+def surrogate_targets(rays: torch.Tensor, outs: Dict[str, torch.Tensor], stream=None) -> torch.Tensor:
+    _dev_check(rays, torch.float64, (4,), "rays")
+    n = rays.shape[0]
+    t = torch.empty((n, 6), dtype=torch.float32, device=rays.device)
+    rc = lib().kgrt_surrogate_targets(rays.data_ptr(), outs["status"].data_ptr(), outs["r_cross"].data_ptr(),
+                                      outs["g"].data_ptr(), outs["phi_cross"].data_ptr(), n, t.data_ptr(),
+                                      _stream_handle(stream))
+    if rc != OK:
+        raise KgrtError(rc, "kgrt_surrogate_targets failed")
+    return t

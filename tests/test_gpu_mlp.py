@@ -1,0 +1,143 @@
+"""The surrogate network's GPU kernels versus the FP64 reference network.
+
+The GPU runs the three 256x256 layers in BF16 with FP32 accumulation, so it is
+compared with the reference evaluated on the same BF16-rounded weights and
+inputs, within 2e-2 relative (Frobenius norm per output column or per
+parameter tensor).
+"""
+import numpy as np
+import pytest
+
+import oracle.mlp as M
+
+pytestmark = pytest.mark.gpu
+
+REL = 2e-2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = K.Context(0)
+    yield c
+    c.close()
+
+
+def bf16_round(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
+
+
+def reference_params(seed):
+    """Initial parameters with W2..W4 rounded to BF16 (what the GPU multiplies with)."""
+    p = M.init_params(seed).astype(np.float32)
+    offs = np.cumsum([0] + [i * o + o for i, o in M.LAYERS])
+    for li in (1, 2, 3):
+        i, o = M.LAYERS[li]
+        p[offs[li]:offs[li] + i * o] = bf16_round(p[offs[li]:offs[li] + i * o])
+    return p
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_forward_matches_reference(ctx):
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(11)
+    rng = np.random.Generator(np.random.PCG64(2))
+    x = rng.uniform(-1, 1, size=(1000, 4)).astype(np.float32)  # not a multiple of 16: ragged tail
+    mlp = K.Mlp(ctx, max_batch=512)  # several chunks
+    mlp.set_params(p)
+    xd = torch.from_numpy(x).to(ctx.device)
+    y = mlp.forward(xd).cpu().numpy()
+    ref, _ = M.forward(p.astype(np.float64), x.astype(np.float64))
+    for j in range(5):
+        assert rel_fro(y[:, j], ref[:, j]) <= REL, (j, rel_fro(y[:, j], ref[:, j]))
+    # rows are independent: a prefix evaluated alone gives the same bits
+    y2 = mlp.forward(xd[:300].contiguous()).cpu().numpy()
+    assert np.array_equal(y2, y[:300])
+    assert np.array_equal(mlp.get_params(), p)
+    mlp.close()
+
+
+def test_gradients_match_reference(ctx):
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(5)
+    rng = np.random.Generator(np.random.PCG64(8))
+    n = 512
+    x = rng.uniform(-1, 1, size=(n + 100, 4)).astype(np.float32)
+    t = np.zeros((n + 100, 6), dtype=np.float32)
+    t[:, 0] = rng.integers(0, 2, n + 100)
+    t[:, 1:5] = rng.normal(size=(n + 100, 4))
+    t[:, 5] = rng.integers(0, 2, n + 100)
+    idx = rng.permutation(n + 100)[:n].astype(np.int32)  # gathered batch
+    mlp = K.Mlp(ctx, max_batch=1024)
+    mlp.set_params(p)
+    loss, g = mlp.loss_grads(torch.from_numpy(x).to(ctx.device), torch.from_numpy(t).to(ctx.device),
+                             torch.from_numpy(idx).to(ctx.device))
+    torch.cuda.synchronize()
+    lref, gref = M.loss_and_grads(p.astype(np.float64), x[idx].astype(np.float64), t[idx].astype(np.float64))
+    assert abs(float(loss) - lref) <= REL * abs(lref)
+    g = g.cpu().numpy()
+    k = 0
+    for li, (i, o) in enumerate(M.LAYERS):
+        for name, size in (("W", i * o), ("b", o)):
+            e = rel_fro(g[k:k + size], gref[k:k + size])
+            assert e <= REL, (li + 1, name, e)
+            k += size
+    mlp.close()
+
+
+def test_features_and_targets_kernels(ctx):
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    rays = scenes.label_rays(2000, seed=31)
+    rd = torch.from_numpy(rays).to(ctx.device)
+    f = K.surrogate_features(rd).cpu().numpy()
+    want = np.stack([rays[:, 0], np.cos(np.radians(rays[:, 1])), rays[:, 2] / 15, rays[:, 3] / 15], 1)
+    np.testing.assert_allclose(f, want.astype(np.float32), rtol=1e-6, atol=1e-7)
+    mod = K.Model(kind=K.MODEL_THIN_DISK)
+    out = K.alloc_outputs(len(rays), mod, 0, ctx.device)
+    ctx.trace_rays(rd, mod, [], K.Integrator(), out)
+    t = K.surrogate_targets(rd, out).cpu().numpy()
+    st = out["status"].cpu().numpy()
+    crossed = (st & K.CROSSED) != 0
+    rplus = 1 + np.sqrt(1 - rays[:, 0] ** 2)
+    np.testing.assert_array_equal(t[:, 0], ((st & K.CAPTURED) != 0).astype(np.float32))
+    np.testing.assert_array_equal(t[:, 5], crossed.astype(np.float32))
+    rc = out["r_cross"].cpu().numpy()
+    np.testing.assert_allclose(t[:, 1], np.log(np.where(crossed, rc, rplus)).astype(np.float32), rtol=1e-6)
+    np.testing.assert_allclose(t[crossed, 2], out["g"].cpu().numpy()[crossed].astype(np.float32), rtol=1e-6)
+    assert np.all(t[~crossed, 2] == 0)
+
+
+def test_training_reduces_loss(ctx):
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    rays = torch.from_numpy(scenes.label_rays(16384, seed=41)).to(ctx.device)
+    mod = K.Model(kind=K.MODEL_THIN_DISK)
+    out = K.alloc_outputs(rays.shape[0], mod, 0, ctx.device)
+    ctx.trace_rays(rays, mod, [], K.Integrator(), out)
+    x = K.surrogate_features(rays)
+    t = K.surrogate_targets(rays, out)
+    mlp = K.Mlp(ctx, max_batch=4096)
+    mlp.set_params(M.init_params(1))
+    loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    losses = []
+    for step in range(120):
+        idx = torch.randperm(rays.shape[0], generator=gen)[:4096].to(torch.int32).to(ctx.device)
+        mlp.train_step(x, t, idx, 4096, 1e-3, loss)
+        if step % 20 == 0 or step == 119:
+            losses.append(float(loss))
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.1 * losses[0], losses
+    mlp.close()
