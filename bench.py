@@ -104,7 +104,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="torus", choices=["torus", "thin_disk", "projection", "batch"])
+    ap.add_argument("--workload", default="torus",
+                    choices=["torus", "thin_disk", "projection", "batch", "train", "render"])
+    ap.add_argument("--train-rays", type=int, default=10_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--ckpt", default=os.path.join("gpurun_out", "surrogate.npz"))
+    ap.add_argument("--images", type=int, default=64, help="render: number of images")
+    ap.add_argument("--fallback", default="0.05,0.95,0.5,0.25,0",
+                    help="render: p_lo,p_hi,crit_band,edge_band,g_tol")
+    ap.add_argument("--lr", type=float, default=1e-3, help="train: peak learning rate")
     ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch shape first")
     ap.add_argument("--baselines", action="store_true", help="batch: also time per-image launches")
     ap.add_argument("--nfreq", type=int, default=1, help="calibration: number of frequencies (1 or 8)")
@@ -148,6 +156,12 @@ def main():
 
     if args.workload == "batch":
         bench_batch(ctx, args, dev)
+        return
+    if args.workload == "train":
+        bench_train(ctx, args, dev)
+        return
+    if args.workload == "render":
+        bench_render(ctx, args, dev)
         return
 
     w, desc = workload(args.workload, args.n)
@@ -276,6 +290,93 @@ def bench_batch(ctx, args, dev):
                            "batch_speedup": round(bms / ms, 3)}
         ctx.set_launch()
     plan.close()
+    print(json.dumps(line), flush=True)
+
+
+MLP_TRAIN_MFMA_FLOPS = 3 * 3 * 2 * 256 * 256  # per sample: forward, input- and weight-gradient of the 256x256 layers
+MLP_FWD_FLOPS = 397824  # per sample, all layers
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def bench_train(ctx, args, dev):
+    """Surrogate training: integrator-labelled rays, BF16-MFMA forward/backward, Adam, batch 65536."""
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import surrogate as S
+    rays, x, t, label_s = S.label_dataset(ctx, args.train_rays, 1604)
+    _, xv, tv, _ = S.label_dataset(ctx, 100_000, 1614)
+    mlp = K.Mlp(ctx, 65536)
+    mlp.set_params(S.init_params(7))
+    log = lambda r: print(json.dumps({"train_epoch": r}), file=sys.stderr, flush=True)
+    res = S.train(ctx, mlp, x, t, xv, tv, args.epochs, lr0=args.lr, log=log)
+    acc = S.accuracy(mlp, xv, tv)
+    os.makedirs(os.path.dirname(args.ckpt) or ".", exist_ok=True)
+    S.save_checkpoint(args.ckpt, mlp, {"train_rays": args.train_rays, "epochs": args.epochs, "lr": args.lr,
+                                       "val_loss": res["history"][-1]["val_loss"], **acc})
+    sps = res["samples_per_s"]
+    ach = sps * MLP_TRAIN_MFMA_FLOPS / 1e12
+    line = {"metric": "surrogate training samples/s", "value": round(sps, 1), "unit": "samples/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+            "config": {"workload": f"MLP 4-256x4-5 SiLU, batch 65536, Adam, {args.train_rays} integrator-labelled "
+                                   f"rays, {args.epochs} epochs"},
+            "label_rays_per_s": round(args.train_rays / label_s, 1), "train_seconds": round(res["train_seconds"], 3),
+            "val_loss": res["history"][-1]["val_loss"], "accuracy": acc,
+            "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": BF16_DENSE_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(ach / BF16_DENSE_PEAK_TFLOPS, 5), "traffic": None,
+                         "flops_per_sample": MLP_TRAIN_MFMA_FLOPS, "kernel": "256x256 layers (fwd+dgrad+wgrad)"}}
+    mlp.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_render(ctx, args, dev):
+    """Surrogate + fallback thin-disk images vs the full FP64 integrator on the same GPU."""
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    from paper_1601_02063_amd import surrogate as S
+    ws = scenes.render_scenes(1605, args.images, args.n or 2048)
+    cams = [K.Camera(**w["camera"]) for w in ws]
+    mod, integ = K.Model(**ws[0]["model"]), K.Integrator(**ws[0]["integ"])
+    mlp = K.Mlp(ctx, 1 << 20)
+    meta = S.load_checkpoint(args.ckpt, mlp)
+    if meta is None:
+        raise SystemExit(f"no surrogate checkpoint at {args.ckpt}: run --workload train first")
+    stream = torch.cuda.current_stream()
+    # reference: every ray through the integrator (one persistent plan, graph replay)
+    plan = K.Plan(ctx, cams, mod, [], integ)
+    ref = plan.alloc_outputs(("status", "intensity"))
+    plan.launch(ref, graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.launch(ref, graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_int = e0.elapsed_time(e1)
+    fb = tuple(float(v) for v in args.fallback.split(","))
+    out = K.surrogate_render(ctx, mlp, cams, mod, integ, fb)  # warm-up
+    torch.cuda.synchronize()
+    e0.record(stream)
+    out = K.surrogate_render(ctx, mlp, cams, mod, integ, fb)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_sur = e0.elapsed_time(e1)
+    err = S.render_errors(out["intensity"], ref["intensity"], plan.offsets)
+    nfb = int(out["fallback"].sum())
+    ok = err["flux_rel_err_max"] <= 1e-2
+    line = {"metric": METRIC, "value": round(len(cams) / (t_sur * 1e-3), 3), "unit": "images/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 surrogate + f64 fallback", "data": "synthetic",
+            "config": {"workload": f"{len(cams)} thin-disk images {cams[0].nx}x{cams[0].ny} over +-15 M, "
+                                   f"(a, incl) seeded 1605, disk ISCO-20 M", "fallback": fb,
+                       "checkpoint": meta},
+            "surrogate_ms": round(t_sur, 3), "integrator_ms": round(t_int, 3),
+            "integrator_images_per_s": round(len(cams) / (t_int * 1e-3), 3),
+            "speedup_vs_integrator": round(t_int / t_sur, 3), "flux_within_1pct": ok,
+            "fallback_fraction": round(nfb / plan.num_rays, 5), "errors": err}
+    plan.close()
+    mlp.close()
     print(json.dumps(line), flush=True)
 
 

@@ -249,6 +249,48 @@ int kgrt_surrogate_targets(const double* rays_dev, const int32_t* status_dev, co
                            const double* g_dev, const double* phi_cross_dev, int64_t n, float* targets_dev,
                            void* stream);
 
+/* Fallback policy of the surrogate render: a ray is re-integrated in FP64 when
+ * its predicted capture probability lies in [p_lo, p_hi], when it is within
+ * crit_band (M, radially in the image plane) of the image's Kerr critical curve,
+ * when its predicted crossing radius is within edge_band (M) of a disk edge
+ * (where the intensity jumps), or, if g_tol > 0, when the network's g output
+ * and the Keplerian g at its predicted radius differ by more than g_tol. */
+typedef struct kgrt_fallback {
+    float p_lo, p_hi, crit_band, edge_band;  /* defaults 0.05, 0.95, 0.5, 0.25 */
+    float g_tol;                             /* default 0 (no check) */
+} kgrt_fallback;
+
+/* The Kerr critical curve (section 4.2's shadow boundary) seen at infinity,
+ * as radius from the image centre on nbins = 1024 equal polar-angle bins
+ * starting at -pi (host array; the table the fallback band uses). */
+int kgrt_critical_curve(double a, double incl_deg, float* radius_host, int32_t nbins);
+
+/* Thin-disk images (section 4.3, j = r^-3, I = g^3 j) from the surrogate, with
+ * fallback rays (kgrt_fallback) re-integrated by the FP64 integrator on the
+ * same stream: features -> network -> decode and fallback test -> device-built
+ * ray list -> integrator -> composite -> per-image flux. The fallback rays of
+ * consecutive images with the same r_obs and phi_obs, up to 2^26 pixels, go to
+ * the integrator as one list (one launch). Outputs (device): intensity [total]
+ * (images concatenated, pixel j*nx+i), status [total] or NULL (KGRT_FALLBACK
+ * set on re-integrated rays; others carry the predicted capture/escape bit),
+ * flux [nimg] or NULL (sum of intensity per image), fallback_counts [nimg] or
+ * NULL. Everything, the critical-curve tables included (built on the device,
+ * the same as kgrt_critical_curve's), is asynchronous on `stream`; the host
+ * waits only when the workspace grows. Workspace grows on demand
+ * and is kept by the network object (about 60 bytes per pixel, at most 2^26
+ * pixels' worth, plus 36 bytes per pixel of at most 2^22). */
+int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* mlp, const kgrt_camera* cams, int32_t nimg,
+                          const kgrt_model* disk, const kgrt_integrator* integ, const kgrt_fallback* fb,
+                          double* intensity_dev, int32_t* status_dev, double* flux_dev,
+                          unsigned long long* fallback_counts_dev, void* stream);
+
+/* As kgrt_trace_rays, for lists built on the device: only the first *n_dev
+ * (device int64, read by the kernels) of at most n_max rays are traced. Outputs
+ * are laid out for n_max rays (torus planes [nfreq][n_max]). */
+int kgrt_trace_rays_dev(kgrt_ctx* ctx, const double* rays_dev, const int64_t* n_dev, int64_t n_max, double r_obs,
+                        double phi_obs_deg, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+                        const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
+
 /* Error strings. kgrt_last_error returns the context's last message ("" if none). */
 const char* kgrt_strerror(int code);
 const char* kgrt_last_error(const kgrt_ctx* ctx);

@@ -60,48 +60,9 @@ struct KParams {
     uint32_t flags;
     int32_t refill_min;
     int32_t naive;  // 1: one ray per thread, no queue (the paper's mapping, kept as a baseline)
+    const int64_t* count_dev;  // if set, only rays [0, *count_dev) exist (lists built on the device)
     Outputs out;
 };
-
-// ------------------------------------------------------------ ray start
-
-// Pixel -> start state, section 2.2: Eqs. (18)-(19) image plane -> Cartesian,
-// Eqs. (20)-(22) Cartesian -> Boyer-Lindquist, Eqs. (24)-(26) rates of a ray
-// along the line of sight, Eq. (7) energy (negative root, rates scaled so
-// E = -1), Eq. (8) L_z, Eqs. (4)-(5) covariant momenta. Returns false when
-// the start point is unusable (E^2 <= 0 or non-finite values).
-__device__ __forceinline__ bool start_ray(double a, double a2, double r_obs, double sqrt_ro2a2, double sin_i,
-                                          double cos_i, double sin_p, double cos_p, double phi_obs, double x,
-                                          double y, State& st, double& L) {
-    const double D = sqrt_ro2a2 * sin_i - y * cos_i;
-    const double xp = D * cos_p - x * sin_p;
-    const double yp = D * sin_p + x * cos_p;
-    const double zp = r_obs * cos_i + y * sin_i;
-    const double w = xp * xp + yp * yp + zp * zp - a2;
-    const double r = sqrt((w + sqrt(w * w + 4.0 * a2 * zp * zp)) / 2.0);
-    const double th = acos(zp / r);
-    const double ph = atan2(yp, xp);
-    const double R = sqrt(r * r + a2);
-    double sP, cP;
-    sincos_bounded(ph - phi_obs, &sP, &cP);
-    double sn, cs;
-    sincos_bounded(th, &sn, &cs);
-    const double Sigma = r * r + a2 * cs * cs;
-    double rdot = -(r * R * sn * sin_i * cP + R * R * cs * cos_i) / Sigma;
-    double thdot = (r * sn * cos_i - R * cs * sin_i * cP) / Sigma;
-    double phdot = sin_i * sP / (R * sn);
-    const double Delta = r * r - 2.0 * r + a2;
-    const double E2 = ((Sigma - 2.0 * r) / (Sigma * Delta)) * (Sigma * rdot * rdot + Sigma * Delta * thdot * thdot) +
-                      Delta * phdot * phdot * sn * sn;
-    bool ok = (E2 > 0.0) && isfinite(E2);
-    const double inv = 1.0 / sqrt(E2);
-    rdot *= inv;
-    thdot *= inv;
-    phdot *= inv;
-    L = (Sigma * Delta * phdot + 2.0 * a * r) * sn * sn / (Sigma - 2.0 * r);
-    st = State{r, th, ph, 0.0, Sigma * rdot / Delta, Sigma * thdot};
-    return ok && finite6(st) && isfinite(L);
-}
 
 // Ray id -> start state and the per-ray uniforms (spin, capture radius,
 // disk inner edge, observer distance).
@@ -159,6 +120,7 @@ __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
 // One thread per ray of the chunk [base, base + count): ray start (section 2.2).
 __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t base, int64_t count, double* rec,
                                                     int64_t cap) {
+    if (P.count_dev) count = std::max<int64_t>(0, std::min<int64_t>(count, *P.count_dev - base));
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
         State st;
         double a, a2, L, r_cap, r_in, r_obs;
@@ -193,6 +155,7 @@ __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WavesPerEU<MODEL>::value, WavesPerEU<MODEL>::value)))
 trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restrict__ rec, int64_t cap) {
     constexpr bool kDisk = (MODEL != KGRT_MODEL_TORUS);
+    if (P.count_dev) count = std::max<int64_t>(0, std::min<int64_t>(count, *P.count_dev - base));
     const int lane = __lane_id();
     const uint64_t lane_mask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool active = false, done = false, fresh = true;
@@ -745,9 +708,20 @@ int kgrt_trace(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, c
     return dispatch(ctx, P, (hipStream_t)stream);
 }
 
+int kgrt_trace_rays_dev(kgrt_ctx* ctx, const double* rays_dev, const int64_t* n_dev, int64_t n_max, double r_obs,
+                        double phi_obs_deg, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+                        const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
+
 int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_obs, double phi_obs_deg,
                     const kgrt_model* model, const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ,
                     const kgrt_outputs* out, void* stream) {
+    return kgrt_trace_rays_dev(ctx, rays_dev, nullptr, n, r_obs, phi_obs_deg, model, freqs_hz, nfreq, integ, out,
+                               stream);
+}
+
+int kgrt_trace_rays_dev(kgrt_ctx* ctx, const double* rays_dev, const int64_t* n_dev, int64_t n, double r_obs,
+                        double phi_obs_deg, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
+                        const kgrt_integrator* integ, const kgrt_outputs* out, void* stream) {
     if (!ctx) return KGRT_E_INVALID_ARG;
     if (n < 0) return fail(ctx, KGRT_E_INVALID_ARG, "n must be >= 0");
     if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "outputs is NULL");
@@ -766,6 +740,7 @@ int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_o
     P.list_mode = 1;
     P.rays4 = rays_dev;
     P.nrays = n;
+    P.count_dev = n_dev;
     const double pho = phi_obs_deg * 3.14159265358979323846 / 180.0;
     P.list_r_obs = r_obs;
     P.list_phi_obs = pho;

@@ -290,6 +290,46 @@ __device__ __host__ inline double isco_radius(double a) {
     return 3.0 + z2 - sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
 }
 
+// ------------------------------------------------------------ ray start
+
+// Pixel -> start state, section 2.2: Eqs. (18)-(19) image plane -> Cartesian,
+// Eqs. (20)-(22) Cartesian -> Boyer-Lindquist, Eqs. (24)-(26) rates of a ray
+// along the line of sight, Eq. (7) energy (negative root, rates scaled so
+// E = -1), Eq. (8) L_z, Eqs. (4)-(5) covariant momenta. Returns false when
+// the start point is unusable (E^2 <= 0 or non-finite values).
+__device__ __forceinline__ bool start_ray(double a, double a2, double r_obs, double sqrt_ro2a2, double sin_i,
+                                          double cos_i, double sin_p, double cos_p, double phi_obs, double x,
+                                          double y, State& st, double& L) {
+    const double D = sqrt_ro2a2 * sin_i - y * cos_i;
+    const double xp = D * cos_p - x * sin_p;
+    const double yp = D * sin_p + x * cos_p;
+    const double zp = r_obs * cos_i + y * sin_i;
+    const double w = xp * xp + yp * yp + zp * zp - a2;
+    const double r = sqrt((w + sqrt(w * w + 4.0 * a2 * zp * zp)) / 2.0);
+    const double th = acos(zp / r);
+    const double ph = atan2(yp, xp);
+    const double R = sqrt(r * r + a2);
+    double sP, cP;
+    sincos_bounded(ph - phi_obs, &sP, &cP);
+    double sn, cs;
+    sincos_bounded(th, &sn, &cs);
+    const double Sigma = r * r + a2 * cs * cs;
+    double rdot = -(r * R * sn * sin_i * cP + R * R * cs * cos_i) / Sigma;
+    double thdot = (r * sn * cos_i - R * cs * sin_i * cP) / Sigma;
+    double phdot = sin_i * sP / (R * sn);
+    const double Delta = r * r - 2.0 * r + a2;
+    const double E2 = ((Sigma - 2.0 * r) / (Sigma * Delta)) * (Sigma * rdot * rdot + Sigma * Delta * thdot * thdot) +
+                      Delta * phdot * phdot * sn * sn;
+    bool ok = (E2 > 0.0) && isfinite(E2);
+    const double inv = 1.0 / sqrt(E2);
+    rdot *= inv;
+    thdot *= inv;
+    phdot *= inv;
+    L = (Sigma * Delta * phdot + 2.0 * a * r) * sn * sn / (Sigma - 2.0 * r);
+    st = State{r, th, ph, 0.0, Sigma * rdot / Delta, Sigma * thdot};
+    return ok && finite6(st) && isfinite(L);
+}
+
 // Redshift g = nu_obs/nu_emit (Eq. (2)) of an emitter on a circular Keplerian
 // orbit, Omega = 1/(r^3/2 + a) in Boyer-Lindquist r at any theta, u^r = u^theta = 0,
 // seen by an observer at rest at infinity; the zero-angular-momentum

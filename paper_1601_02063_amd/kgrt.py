@@ -70,6 +70,11 @@ class CAdam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
+class CFallback(ctypes.Structure):
+    _fields_ = [("p_lo", ctypes.c_float), ("p_hi", ctypes.c_float), ("crit_band", ctypes.c_float),
+                ("edge_band", ctypes.c_float), ("g_tol", ctypes.c_float)]
+
+
 LAUNCH_PERSISTENT, LAUNCH_ONE_RAY_PER_THREAD = 0, 1
 PLAN_GRAPH = 1
 
@@ -174,6 +179,13 @@ def lib() -> ctypes.CDLL:
         L.kgrt_surrogate_features.argtypes, L.kgrt_surrogate_features.restype = [vp, i64, vp, vp], ctypes.c_int
         L.kgrt_surrogate_targets.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.kgrt_surrogate_targets.restype = ctypes.c_int
+        L.kgrt_surrogate_render.argtypes = [vp, vp, vp, i32, P(CModel), P(CIntegrator), P(CFallback), vp, vp, vp,
+                                            vp, vp]
+        L.kgrt_surrogate_render.restype = ctypes.c_int
+        L.kgrt_trace_rays_dev.argtypes = [vp, vp, vp, i64, d, d, P(CModel), P(d), i32, P(CIntegrator), P(COutputs),
+                                          vp]
+        L.kgrt_trace_rays_dev.restype = ctypes.c_int
+        L.kgrt_critical_curve.argtypes, L.kgrt_critical_curve.restype = [d, d, vp, i32], ctypes.c_int
         L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
         L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
@@ -456,3 +468,35 @@ def surrogate_targets(rays: torch.Tensor, outs: Dict[str, torch.Tensor], stream=
     if rc != OK:
         raise KgrtError(rc, "kgrt_surrogate_targets failed")
     return t
+
+
+def surrogate_render(ctx: Context, mlp: Mlp, cameras: Sequence[Camera], model: Model, integ: Integrator,
+                     fallback=(0.05, 0.95, 0.5, 0.25, 0.0), stream=None):
+    """kgrt_surrogate_render: thin-disk images from the network with FP64 fallback.
+
+    Returns dict(intensity [total] f64, status [total] i32, flux [nimg] f64, fallback [nimg] i64)."""
+    cams = (CCamera * len(cameras))(*[c.c() for c in cameras])
+    total = sum(c.nx * c.ny for c in cameras)
+    dev = ctx.device
+    out = {"intensity": torch.empty(total, dtype=torch.float64, device=dev),
+           "status": torch.empty(total, dtype=torch.int32, device=dev),
+           "flux": torch.empty(len(cameras), dtype=torch.float64, device=dev),
+           "fallback": torch.empty(len(cameras), dtype=torch.int64, device=dev)}
+    fb = CFallback(*(tuple(fallback) + (0.0,) * (5 - len(fallback))))
+    rc = lib().kgrt_surrogate_render(ctx._h, mlp._h, cams, len(cameras), ctypes.byref(model.c()),
+                                     ctypes.byref(integ.c()), ctypes.byref(fb), out["intensity"].data_ptr(),
+                                     out["status"].data_ptr(), out["flux"].data_ptr(), out["fallback"].data_ptr(),
+                                     _stream_handle(stream))
+    if rc != OK:
+        raise KgrtError(rc, lib().kgrt_mlp_last_error(mlp._h).decode())
+    return out
+
+
+def critical_curve(a: float, incl_deg: float):
+    """Radius of the critical curve on 1024 polar-angle bins starting at -pi (host, no GPU needed)."""
+    import numpy as np
+    R = np.zeros(1024, dtype=np.float32)
+    rc = lib().kgrt_critical_curve(a, incl_deg, R.ctypes.data, 1024)
+    if rc != OK:
+        raise KgrtError(rc, "kgrt_critical_curve failed")
+    return R

@@ -81,3 +81,15 @@ def sample_pixels(nx: int, ny: int, k: int, seed: int) -> np.ndarray:
     """k distinct pixel indices (j*nx + i) drawn without replacement."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.sort(rng.choice(nx * ny, size=min(k, nx * ny), replace=False))
+
+
+def render_scenes(seed: int = 1605, nimg: int = 64, n: int = 2048) -> list:
+    """Thin-disk images for the surrogate render: (a, incl) drawn per image as for the
+    training rays (a ~ U[0, 0.998], incl ~ U[1, 89] deg), n x n pixels over +-15 M."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(nimg):
+        a = float(rng.uniform(0.0, 0.998))
+        inc = float(rng.uniform(1.0, 89.0))
+        out.append(thin_disk_image(n, a, inc, 15.0))
+    return out

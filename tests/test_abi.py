@@ -44,10 +44,10 @@ def test_struct_layout_matches_header(K):
 #define P(T) printf(#T " %zu\n", sizeof(T));
 #define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
-  P(kgrt_camera) P(kgrt_model) P(kgrt_integrator) P(kgrt_outputs) P(kgrt_launch)
+  P(kgrt_camera) P(kgrt_model) P(kgrt_integrator) P(kgrt_outputs) P(kgrt_launch) P(kgrt_adam) P(kgrt_fallback)
   F(kgrt_camera, nx) F(kgrt_camera, x_min) F(kgrt_camera, y_max)
   F(kgrt_model, r_in) F(kgrt_model, r_emit_max) F(kgrt_integrator, max_steps) F(kgrt_integrator, flags)
-  F(kgrt_outputs, tau) F(kgrt_launch, refill_min)
+  F(kgrt_outputs, tau) F(kgrt_launch, refill_min) F(kgrt_adam, eps) F(kgrt_fallback, g_tol)
   return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
@@ -59,13 +59,15 @@ int main(void) {
     want = {
         "kgrt_camera": ctypes.sizeof(K.CCamera), "kgrt_model": ctypes.sizeof(K.CModel),
         "kgrt_integrator": ctypes.sizeof(K.CIntegrator), "kgrt_outputs": ctypes.sizeof(K.COutputs),
-        "kgrt_launch": ctypes.sizeof(K.CLaunch),
+        "kgrt_launch": ctypes.sizeof(K.CLaunch), "kgrt_adam": ctypes.sizeof(K.CAdam),
+        "kgrt_fallback": ctypes.sizeof(K.CFallback),
         "kgrt_camera.nx": K.CCamera.nx.offset, "kgrt_camera.x_min": K.CCamera.x_min.offset,
         "kgrt_camera.y_max": K.CCamera.y_max.offset, "kgrt_model.r_in": K.CModel.r_in.offset,
         "kgrt_model.r_emit_max": K.CModel.r_emit_max.offset,
         "kgrt_integrator.max_steps": K.CIntegrator.max_steps.offset,
         "kgrt_integrator.flags": K.CIntegrator.flags.offset, "kgrt_outputs.tau": K.COutputs.tau.offset,
-        "kgrt_launch.refill_min": K.CLaunch.refill_min.offset,
+        "kgrt_launch.refill_min": K.CLaunch.refill_min.offset, "kgrt_adam.eps": K.CAdam.eps.offset,
+        "kgrt_fallback.g_tol": K.CFallback.g_tol.offset,
     }
     for k, v in want.items():
         assert int(got[k]) == v, k
@@ -129,3 +131,22 @@ def test_context_without_gpu_reports_no_device(K):
     with pytest.raises(K.KgrtError) as e:
         K.Context(0)
     assert e.value.code == K.E_NO_DEVICE
+
+
+@pytest.mark.parametrize("a,inc", [(0.0, 60.0), (0.9, 60.0), (0.998, 89.0), (0.5, 5.0), (0.3, 30.0)])
+def test_critical_curve_table_matches_parametrisation(K, a, inc):
+    """The fallback band's table agrees with the spherical-photon-orbit curve computed
+    independently in the tests (sky-plane distance of curve points to the table)."""
+    import numpy as np
+    from tests.helpers import critical_curve_distance
+    R = K.critical_curve(a, inc)
+    psi = -np.pi + (np.arange(1024) + 0.5) * 2 * np.pi / 1024
+    x, y = R * np.cos(psi), R * np.sin(psi)
+    # table points lie on the curve: convert (x, y) -> (xi, eta) of a ray at infinity and measure
+    th = np.radians(inc)
+    xi = -x * np.sin(th)
+    eta = y ** 2 - a * a * np.cos(th) ** 2 + xi ** 2 / np.tan(th) ** 2
+    d = critical_curve_distance(a, inc, xi, eta)
+    # bins hold the largest radius in their angular range: ~dR/dpsi x half a bin (< 0.01 M),
+    # against a fallback band of 0.5 M
+    assert np.median(d) < 1e-2 and d.max() < 2e-2, (np.median(d), d.max())
