@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus",
-                    choices=["torus", "thin_disk", "projection", "batch", "train", "render"])
+                    choices=["torus", "thin_disk", "projection", "batch", "train", "infer", "render"])
     ap.add_argument("--train-rays", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--ckpt", default=os.path.join("gpurun_out", "surrogate.npz"))
@@ -159,6 +159,9 @@ def main():
         return
     if args.workload == "train":
         bench_train(ctx, args, dev)
+        return
+    if args.workload == "infer":
+        bench_infer(ctx, args, dev)
         return
     if args.workload == "render":
         bench_render(ctx, args, dev)
@@ -329,6 +332,50 @@ def bench_train(ctx, args, dev):
     print(json.dumps(line), flush=True)
 
 
+MLP_INFER_MFMA_FLOPS = 3 * 2 * 256 * 256  # per sample: the three 256x256 layers
+
+
+def bench_infer(ctx, args, dev):
+    """Surrogate inference alone (kgrt_mlp_forward, the fused kernel): 2^24 samples per step,
+    features drawn as the training rays' (seeded), initial weights (the cost does not depend
+    on their values)."""
+    import numpy as np
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    from paper_1601_02063_amd import surrogate as S
+    n = 1 << 24
+    rays = scenes.label_rays(n, 1617)
+    feat = np.stack([rays[:, 0], np.cos(np.radians(rays[:, 1])), rays[:, 2] / 15, rays[:, 3] / 15], 1)
+    x = torch.from_numpy(feat.astype(np.float32)).to(dev)
+    y = torch.empty((n, 5), dtype=torch.float32, device=dev)
+    mlp = K.Mlp(ctx, 65536)
+    mlp.set_params(S.init_params(7))
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, args.warmup)):
+        mlp.forward(x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        mlp.forward(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    sps = n / (ms * 1e-3)
+    ach = sps * MLP_INFER_MFMA_FLOPS / 1e12
+    line = {"metric": "surrogate inference samples/s", "value": round(sps, 1), "unit": "samples/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+            "config": {"workload": f"MLP 4-256x4-5 SiLU forward, {n} samples per step"},
+            "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": BF16_DENSE_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(ach / BF16_DENSE_PEAK_TFLOPS, 5), "traffic": None,
+                         "flops_per_sample": MLP_INFER_MFMA_FLOPS, "kernel": "mlp_infer_fused"}}
+    mlp.close()
+    print(json.dumps(line), flush=True)
+
+
 def bench_render(ctx, args, dev):
     """Surrogate + fallback thin-disk images vs the full FP64 integrator on the same GPU."""
     import torch
@@ -365,6 +412,12 @@ def bench_render(ctx, args, dev):
     t_sur = e0.elapsed_time(e1)
     err = S.render_errors(out["intensity"], ref["intensity"], plan.offsets)
     nfb = int(out["fallback"].sum())
+    for k, c in enumerate(cams):
+        a, b = plan.offsets[k], plan.offsets[k + 1]
+        fr = float(ref["intensity"][a:b].sum())
+        print(json.dumps({"image": k, "a": c.a, "incl_deg": c.incl_deg,
+                          "flux_rel_err": (float(out["intensity"][a:b].sum()) - fr) / fr if fr > 0 else None,
+                          "fallback_fraction": int(out["fallback"][k]) / (b - a)}), file=sys.stderr, flush=True)
     ok = err["flux_rel_err_max"] <= 1e-2
     line = {"metric": METRIC, "value": round(len(cams) / (t_sur * 1e-3), 3), "unit": "images/s",
             "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 surrogate + f64 fallback", "data": "synthetic",

@@ -38,9 +38,16 @@ constexpr int64_t kW3 = kB2 + kH, kB3 = kW3 + kH * kH;
 constexpr int64_t kW4 = kB3 + kH, kB4 = kW4 + kH * kH;
 constexpr int64_t kW5 = kB4 + kH, kB5 = kW5 + kOut * kH;
 constexpr int64_t kNumParams = kB5 + kOut;  // 199941
+// the packed BF16 weights Wf: W2..W4 [3][out][in], then W5 split into hi and lo parts [2][16][256]
+constexpr int64_t kW5Split = 3 * kH * kH, kW5Rows = 16;
+constexpr int64_t kWfSize = kW5Split + 2 * kW5Rows * kH;
 constexpr float kWCap = 1.0f, kWLogR = 10.0f, kWG = 10.0f, kWPhi = 1.0f;
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// sigmoid with the hardware base-2 exponential and reciprocal (about 1 ulp
+// each): plenty for BF16 activations, and no IEEE division sequence.
+__device__ __forceinline__ float sigmoidf_(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
 __device__ __forceinline__ float silu_(float z) { return z * sigmoidf_(z); }
 __device__ __forceinline__ float silu_grad_(float z) {
     const float s = sigmoidf_(z);
@@ -174,104 +181,158 @@ __global__ void __launch_bounds__(256) gemm_bt(const GemmArgs g) {
 
 
 // ----------------------------------------------------- fused inference
-// Inference of the whole network for a tile of 128 samples per block (8 waves):
-// activations stay in LDS (two 128 x 256 BF16 buffers, rows padded by 8
-// elements against bank conflicts), weights stream from L2. Wave w computes
-// rows 64 (w / 4) .. +63 and units 64 (w % 4) .. +63 of a hidden layer: 4 x 4
-// MFMA tiles, so each weight fragment is used by four row tiles.
-constexpr int kTileRows = 128, kLdsStride = kH + 8;
+// Inference of the whole network for tiles of 64 samples, one tile at a time
+// per block: the activations stay in one LDS buffer (64 x 256 BF16, rows
+// padded by 8 elements against bank conflicts) that each layer overwrites in
+// place, the weights stream from L2. The output head runs on MFMA too, with
+// W5 split into BF16 hi + lo parts (about 16 significant bits) and FP32
+// accumulation. A wave computes 16 RI rows x 16 UJ units of a hidden layer
+// (RI x UJ MFMA tiles, so each weight fragment serves RI row tiles); the
+// block has (4 / RI) x (16 / UJ) waves. Blocks use 39 KB of LDS, so several
+// share a compute unit and overlap one block's SiLU epilogue with another's
+// matrix products.
+constexpr int kTileRows = 64, kLdsStride = kH + 8;
+#ifndef KGRT_MLP_RI
+#define KGRT_MLP_RI 4
+#endif
+#ifndef KGRT_MLP_UJ
+#define KGRT_MLP_UJ 2
+#endif
+constexpr int kInferRI = KGRT_MLP_RI, kInferUJ = KGRT_MLP_UJ;
+constexpr int kInferThreads = 64 * (4 / kInferRI) * (16 / kInferUJ);
 
-__global__ void __launch_bounds__(512) mlp_infer_fused(const float* __restrict__ x, int64_t n,
-                                                       const float* __restrict__ P, const __bf16* __restrict__ Wf,
-                                                       float* __restrict__ y) {
-    extern __shared__ __bf16 lds[];
-    __bf16* const buf0 = lds;
-    __bf16* const buf1 = lds + kTileRows * kLdsStride;
+template <int RI, int UJ>
+__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
+mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict__ P, const __bf16* __restrict__ Wf,
+                float* __restrict__ y) {
+    constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
+    static_assert(kTileRows % (16 * RI) == 0 && kH % (16 * UJ) == 0, "tile shape");
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
+    __shared__ float xs[kTileRows * kIn];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WU, wu = wave % WU;
     const int lr = lane & 15, lg = lane >> 4;
-    const int rg = wave >> 2, ng = wave & 3;
+    // Input layer on MFMA with W1 and x split into BF16 hi + lo parts along k:
+    // k 0..3 W1hi.xhi, 4..7 W1hi.xlo, 8..11 W1lo.xhi (about 2^-16 relative), the rest zero.
+    auto split = [](float v, __bf16& hi, __bf16& lo) {
+        hi = (__bf16)v;
+        lo = (__bf16)(v - (float)hi);
+    };
+    const __bf16 z16 = (__bf16)0.0f;
+    bf16x8 w1f[UJ];
+#pragma unroll
+    for (int j = 0; j < UJ; ++j) {
+        const float* w = P + kW1 + (16 * (UJ * wu + j) + lr) * kIn;
+        bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
+        __bf16 hi[kIn], lo[kIn];
+#pragma unroll
+        for (int c = 0; c < kIn; ++c) split(w[c], hi[c], lo[c]);
+#pragma unroll
+        for (int c = 0; c < kIn; ++c) {
+            if (lg == 0) {
+                f[c] = hi[c];
+                f[4 + c] = hi[c];
+            } else if (lg == 1) {
+                f[c] = lo[c];
+            }
+        }
+        w1f[j] = f;
+    }
+    // SiLU(acc + bias) of one layer into the activation buffer; accumulator e of
+    // (i, j) is row 16 (RI wr + i) + lr, unit 16 (UJ wu + j) + 4 lg + e
+    auto store = [&](const f32x4 (&acc)[RI][UJ], const float* __restrict__ bias) {
+#pragma unroll
+        for (int j = 0; j < UJ; ++j) {
+            const int u = 16 * (UJ * wu + j) + 4 * lg;
+            const float bb0 = bias[u], bb1 = bias[u + 1], bb2 = bias[u + 2], bb3 = bias[u + 3];
+#pragma unroll
+            for (int i = 0; i < RI; ++i) {
+                const bf16x4 v = {(__bf16)silu_(acc[i][j][0] + bb0), (__bf16)silu_(acc[i][j][1] + bb1),
+                                  (__bf16)silu_(acc[i][j][2] + bb2), (__bf16)silu_(acc[i][j][3] + bb3)};
+                *reinterpret_cast<bf16x4*>(act + (16 * (RI * wr + i) + lr) * kLdsStride + u) = v;
+            }
+        }
+    };
     const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * kTileRows;
-        // input layer (FP32): unit u = tid % 256, rows (tid / 256) * 64 .. +63
+        __syncthreads();  // the previous tile's head has read the buffer
+        for (int i = tid; i < kTileRows * kIn; i += NT) xs[i] = (row0 + i / kIn < n) ? x[row0 * kIn + i] : 0.0f;
+        __syncthreads();
+        // input layer (rows past n compute on zeros and are never written out)
         {
-            const int u = tid & 255;
-            const float w0 = P[kW1 + u * kIn + 0], w1 = P[kW1 + u * kIn + 1], w2 = P[kW1 + u * kIn + 2],
-                        w3 = P[kW1 + u * kIn + 3], bb = P[kB1 + u];
-            for (int r = (tid >> 8) * 64; r < (tid >> 8) * 64 + 64; ++r) {
-                const int64_t b = row0 + r;
-                float a = 0.0f;
-                if (b < n) {
-                    const float* xr = x + b * kIn;
-                    a = silu_(bb + w0 * xr[0] + w1 * xr[1] + w2 * xr[2] + w3 * xr[3]);
+            f32x4 acc[RI][UJ];
+#pragma unroll
+            for (int i = 0; i < RI; ++i) {
+                const float* xr = xs + (16 * (RI * wr + i) + lr) * kIn;
+                bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
+                __bf16 hi[kIn], lo[kIn];
+#pragma unroll
+                for (int c = 0; c < kIn; ++c) split(xr[c], hi[c], lo[c]);
+#pragma unroll
+                for (int c = 0; c < kIn; ++c) {
+                    if (lg <= 1) f[c] = hi[c];
+                    if (lg == 0) f[4 + c] = lo[c];
                 }
-                buf0[r * kLdsStride + u] = (__bf16)a;
+#pragma unroll
+                for (int j = 0; j < UJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
             }
+            store(acc, P + kB1);
         }
         __syncthreads();
-        // hidden layers 2..4 on MFMA
+        // hidden layers 2..4 on MFMA, in place
         for (int l = 0; l < 3; ++l) {
-            const __bf16* in = (l & 1) ? buf1 : buf0;
-            __bf16* out = (l & 1) ? buf0 : buf1;
-            const __bf16* W = Wf + (int64_t)l * kH * kH;
+            const __bf16* W = Wf + (int64_t)l * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
+            const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
             const float* bias = P + (l == 0 ? kB2 : (l == 1 ? kB3 : kB4));
-            f32x4 acc[4][4];
+            f32x4 acc[RI][UJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+                for (int j = 0; j < UJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
             for (int s = 0; s < kH / 32; ++s) {
                 const int k = 32 * s + 8 * lg;
-                bf16x8 af[4], bfg[4];
+                bf16x8 af[UJ], bfg[RI];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    af[j] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(ng * 64 + 16 * j + lr) * kH + k);
+                for (int j = 0; j < UJ; ++j) af[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + k);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    bfg[i] = *reinterpret_cast<const bf16x8*>(in + (rg * 64 + 16 * i + lr) * kLdsStride + k);
+                for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < RI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < UJ; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
             }
-            // accumulator e of (i, j): row rg*64 + 16 i + lr, unit ng*64 + 16 j + 4 lg + e
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = rg * 64 + 16 * i + lr;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int u = ng * 64 + 16 * j + 4 * lg;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) out[r * kLdsStride + u + e] = (__bf16)silu_(acc[i][j][e] + bias[u + e]);
-                }
-            }
+            __syncthreads();  // every wave has read this layer's input
+            store(acc, bias);
             __syncthreads();
         }
-        // output head (FP32): row tid / 4, quarter q = tid % 4 of the 256 inputs, quads combined by shuffles
-        {
-            const __bf16* h4 = buf1;
-            const int r = tid >> 2, q = tid & 3;
-            float o[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int k = q * 64; k < q * 64 + 64; ++k) {
-                const float hv = (float)h4[r * kLdsStride + k];
-#pragma unroll
-                for (int j = 0; j < kOut; ++j) o[j] += P[kW5 + j * kH + k] * hv;
+        // output head: row tile rt, outputs 0..15 (5 used), hi and lo parts of W5
+        for (int rt = wave; rt < kTileRows / 16; rt += NT / 64) {
+            const __bf16* Wh = Wf + kW5Split + lr * kH;
+            const __bf16* A = act + (16 * rt + lr) * kLdsStride;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+            for (int s = 0; s < kH / 32; ++s) {
+                const int k = 32 * s + 8 * lg;
+                const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + k);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + k), hv, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + kW5Rows * kH + k), hv,
+                                                              acc, 0, 0, 0);
             }
+            // accumulator e: output 4 lg + e of row 16 rt + lr
+            const int64_t b = row0 + 16 * rt + lr;
+            if (b < n && lg == 0) {
 #pragma unroll
-            for (int j = 0; j < kOut; ++j) {
-                o[j] += __shfl_xor(o[j], 1);
-                o[j] += __shfl_xor(o[j], 2);
-            }
-            const int64_t b = row0 + r;
-            if (q == 0 && b < n) {
-#pragma unroll
-                for (int j = 0; j < kOut; ++j) y[b * kOut + j] = o[j] + P[kB5 + j];
+                for (int e = 0; e < 4; ++e) y[b * kOut + e] = acc[e] + P[kB5 + e];
+            } else if (b < n && lg == 1) {
+                y[b * kOut + 4] = acc[0] + P[kB5 + 4];
             }
         }
-        __syncthreads();
     }
 }
 
@@ -417,10 +478,22 @@ __global__ void __launch_bounds__(256) adam(float* __restrict__ P, float* __rest
     }
 }
 
-// BF16 copies of W2..W4: Wf[l][out][in] (forward) and Wb[l][in][out] (input gradients).
+// BF16 copies of W2..W4: Wf[l][out][in] (forward) and Wb[l][in][out] (input
+// gradients); after them in Wf, W5 as two BF16 parts hi + lo of 16 x 256
+// (outputs 5..15 zero) for the inference kernel's output head.
 __global__ void __launch_bounds__(256) pack_weights(const float* __restrict__ P, __bf16* __restrict__ Wf,
                                                     __bf16* __restrict__ Wb) {
-    const int l = blockIdx.y;  // 0..2 -> W2..W4
+    const int l = blockIdx.y;  // 0..2 -> W2..W4, 3 -> W5 split
+    if (l == 3) {
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kW5Rows * kH; i += gridDim.x * blockDim.x) {
+            const int o = i / kH;
+            const float w = (o < kOut) ? P[kW5 + i] : 0.0f;
+            const __bf16 hi = (__bf16)w;
+            Wf[kW5Split + i] = hi;
+            Wf[kW5Split + kW5Rows * kH + i] = (__bf16)(w - (float)hi);
+        }
+        return;
+    }
     const float* W = P + (l == 0 ? kW2 : (l == 1 ? kW3 : kW4));
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kH * kH; i += gridDim.x * blockDim.x) {
         const int o = i / kH, k = i % kH;
@@ -825,7 +898,7 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
     const size_t hb = (size_t)max_batch * kH * sizeof(__bf16);
     bool ok = hipMalloc(&m->P, kNumParams * 4) == hipSuccess && hipMalloc(&m->M, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->V, kNumParams * 4) == hipSuccess && hipMalloc(&m->G, kNumParams * 4) == hipSuccess &&
-              hipMalloc(&m->Wf, 3 * kH * kH * sizeof(__bf16)) == hipSuccess &&
+              hipMalloc(&m->Wf, kWfSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Wb, 3 * kH * kH * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess;
     for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess && hipMalloc(&m->z[l], hb) == hipSuccess;
@@ -850,7 +923,7 @@ int kgrt_mlp_set_params(kgrt_mlp* m, const float* params, int64_t n) {
         return mlp_fail(m, KGRT_E_HIP, "hipMemcpy failed");
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->M, kNumParams, 0.0f);
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->V, kNumParams, 0.0f);
-    hipLaunchKernelGGL(pack_weights, dim3(64, 3), dim3(256), 0, 0, m->P, m->Wf, m->Wb);
+    hipLaunchKernelGGL(pack_weights, dim3(64, 4), dim3(256), 0, 0, m->P, m->Wf, m->Wb);
     m->step = 0;
     if (hipDeviceSynchronize() != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "set_params failed");
     return KGRT_OK;
@@ -872,15 +945,15 @@ int kgrt_mlp_forward(kgrt_mlp* m, const float* x, float* y, int64_t n, void* str
     if (!x || !y) return mlp_fail(m, KGRT_E_INVALID_ARG, "x and y must be device pointers");
     DevGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
-    // one block per compute unit (135 KB of LDS each), looping over 128-sample tiles
-    int dev = 0, ncu = 256;
+    // a persistent grid: as many resident blocks as fit, looping over 64-sample tiles
+    int dev = 0, ncu = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const size_t lds = 2 * kTileRows * kLdsStride * sizeof(__bf16);
-    if (hipFuncSetAttribute((const void*)mlp_infer_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return mlp_fail(m, KGRT_E_HIP, "cannot reserve LDS for the fused inference kernel");
+    auto kern = mlp_infer_fused<kInferRI, kInferUJ>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kInferThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
     const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, ncu));
-    hipLaunchKernelGGL(mlp_infer_fused, dim3(grid), dim3(512), lds, st, x, n, m->P, m->Wf, y);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)ncu * per_cu));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kInferThreads), 0, st, x, n, m->P, m->Wf, y);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
@@ -964,7 +1037,7 @@ int kgrt_mlp_train_step(kgrt_mlp* m, const float* x, const float* t, const int32
     const float c1 = 1.0f - powf(opt->beta1, (float)m->step), c2 = 1.0f - powf(opt->beta2, (float)m->step);
     hipLaunchKernelGGL(adam, dim3(256), dim3(256), 0, st, m->P, m->M, m->V, m->G, kNumParams, opt->lr, opt->beta1,
                        opt->beta2, opt->eps, c1, c2);
-    hipLaunchKernelGGL(pack_weights, dim3(64, 3), dim3(256), 0, st, m->P, m->Wf, m->Wb);
+    hipLaunchKernelGGL(pack_weights, dim3(64, 4), dim3(256), 0, st, m->P, m->Wf, m->Wb);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
