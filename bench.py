@@ -108,10 +108,13 @@ def main():
                     choices=["torus", "thin_disk", "projection", "batch", "train", "infer", "render"])
     ap.add_argument("--train-rays", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--ckpt", default=os.path.join("gpurun_out", "surrogate.npz"))
+    ap.add_argument("--ckpt", default=None,
+                    help="train: checkpoint to write (default gpurun_out/surrogate.npz); "
+                         "render: weights to use (default the package's trained network)")
     ap.add_argument("--images", type=int, default=64, help="render: number of images")
-    ap.add_argument("--fallback", default="0.05,0.95,0.5,0.25,0",
-                    help="render: p_lo,p_hi,crit_band,edge_band,g_tol")
+    ap.add_argument("--fallback", default=None,
+                    help="render: p_lo,p_hi,crit_band,edge_band,g_tol,grad_max (default the tuned policy)")
+    ap.add_argument("--seed", type=int, default=None, help="render/analysis: scene seed (default 1605)")
     ap.add_argument("--lr", type=float, default=1e-3, help="train: peak learning rate")
     ap.add_argument("--autotune", action="store_true", help="batch: autotune the launch shape first")
     ap.add_argument("--baselines", action="store_true", help="batch: also time per-image launches")
@@ -314,8 +317,9 @@ def bench_train(ctx, args, dev):
     log = lambda r: print(json.dumps({"train_epoch": r}), file=sys.stderr, flush=True)
     res = S.train(ctx, mlp, x, t, xv, tv, args.epochs, lr0=args.lr, log=log)
     acc = S.accuracy(mlp, xv, tv)
-    os.makedirs(os.path.dirname(args.ckpt) or ".", exist_ok=True)
-    S.save_checkpoint(args.ckpt, mlp, {"train_rays": args.train_rays, "epochs": args.epochs, "lr": args.lr,
+    ckpt = args.ckpt or os.path.join("gpurun_out", "surrogate.npz")
+    os.makedirs(os.path.dirname(ckpt) or ".", exist_ok=True)
+    S.save_checkpoint(ckpt, mlp, {"train_rays": args.train_rays, "epochs": args.epochs, "lr": args.lr,
                                        "val_loss": res["history"][-1]["val_loss"], **acc})
     sps = res["samples_per_s"]
     ach = sps * MLP_TRAIN_MFMA_FLOPS / 1e12
@@ -383,13 +387,15 @@ def bench_render(ctx, args, dev):
     from paper_1601_02063_amd import kgrt as K
     from paper_1601_02063_amd import scenes
     from paper_1601_02063_amd import surrogate as S
-    ws = scenes.render_scenes(1605, args.images, args.n or 2048)
+    seed = 1605 if args.seed is None else args.seed
+    ws = scenes.render_scenes(seed, args.images, args.n or 2048)
     cams = [K.Camera(**w["camera"]) for w in ws]
     mod, integ = K.Model(**ws[0]["model"]), K.Integrator(**ws[0]["integ"])
     mlp = K.Mlp(ctx, 1 << 20)
-    meta = S.load_checkpoint(args.ckpt, mlp)
+    ckpt = args.ckpt or S.DEFAULT_WEIGHTS
+    meta = S.load_checkpoint(ckpt, mlp)
     if meta is None:
-        raise SystemExit(f"no surrogate checkpoint at {args.ckpt}: run --workload train first")
+        raise SystemExit(f"no surrogate checkpoint at {ckpt}: run --workload train first")
     stream = torch.cuda.current_stream()
     # reference: every ray through the integrator (one persistent plan, graph replay)
     plan = K.Plan(ctx, cams, mod, [], integ)
@@ -402,7 +408,7 @@ def bench_render(ctx, args, dev):
     e1.record(stream)
     torch.cuda.synchronize()
     t_int = e0.elapsed_time(e1)
-    fb = tuple(float(v) for v in args.fallback.split(","))
+    fb = tuple(float(v) for v in args.fallback.split(",")) if args.fallback else S.DEFAULT_FALLBACK
     out = K.surrogate_render(ctx, mlp, cams, mod, integ, fb)  # warm-up
     torch.cuda.synchronize()
     e0.record(stream)
@@ -422,7 +428,7 @@ def bench_render(ctx, args, dev):
     line = {"metric": METRIC, "value": round(len(cams) / (t_sur * 1e-3), 3), "unit": "images/s",
             "n_gpus": 1, "higher_is_better": True, "dtype": "bf16 surrogate + f64 fallback", "data": "synthetic",
             "config": {"workload": f"{len(cams)} thin-disk images {cams[0].nx}x{cams[0].ny} over +-15 M, "
-                                   f"(a, incl) seeded 1605, disk ISCO-20 M", "fallback": fb,
+                                   f"(a, incl) seeded {seed}, disk ISCO-20 M", "fallback": fb,
                        "checkpoint": meta},
             "surrogate_ms": round(t_sur, 3), "integrator_ms": round(t_int, 3),
             "integrator_images_per_s": round(len(cams) / (t_int * 1e-3), 3),

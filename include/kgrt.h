@@ -253,11 +253,15 @@ int kgrt_surrogate_targets(const double* rays_dev, const int32_t* status_dev, co
  * its predicted capture probability lies in [p_lo, p_hi], when it is within
  * crit_band (M, radially in the image plane) of the image's Kerr critical curve,
  * when its predicted crossing radius is within edge_band (M) of a disk edge
- * (where the intensity jumps), or, if g_tol > 0, when the network's g output
- * and the Keplerian g at its predicted radius differ by more than g_tol. */
+ * (where the intensity jumps), if g_tol > 0 when the network's g output and
+ * the Keplerian g at its predicted radius differ by more than g_tol, and if
+ * grad_max > 0 when the predicted ln r_c changes by more than grad_max per M
+ * of image-plane distance toward one of its 4 neighbouring pixels (one of the
+ * two predictions within edge_band of the disk; neighbours in the same
+ * network segment of up to 2^22 pixels). */
 typedef struct kgrt_fallback {
     float p_lo, p_hi, crit_band, edge_band;  /* defaults 0.05, 0.95, 0.5, 0.25 */
-    float g_tol;                             /* default 0 (no check) */
+    float g_tol, grad_max;                   /* defaults 0 (no check) */
 } kgrt_fallback;
 
 /* The Kerr critical curve (section 4.2's shadow boundary) seen at infinity,

@@ -549,7 +549,7 @@ struct RenderImage {
     int32_t nx, ny;
 };
 struct RenderCfg {
-    float p_lo, p_hi, crit_band, edge_band, g_tol;
+    float p_lo, p_hi, crit_band, edge_band, g_tol, grad_max;
 };
 constexpr int kCritBins = 1024;
 
@@ -615,7 +615,27 @@ __global__ void __launch_bounds__(256) decode_kernel(const RenderImage im, int64
             const double rd = rc;
             const bool near_disk = rd >= im.r_in - cfg.edge_band && rd <= im.r_out + cfg.edge_band;
             if (ok && near_disk) gk = kgrt::redshift(rd, kgrt::kPi / 2.0, im.a, im.a * im.a, -L);
-            fb = !ok || !(isfinite(o0) && isfinite(o1) && isfinite(o2)) || (pcap >= cfg.p_lo && pcap <= cfg.p_hi) ||
+            // steep predicted crossing radius toward a 4-neighbour in this segment (one
+            // of the pair on or near the disk): the network smooths such features
+            bool steep = false;
+            if (cfg.grad_max > 0.0f) {
+                const int64_t px = (p0 + i) % im.nx;
+                const float lo_r = logf(fmaxf((float)im.r_in - cfg.edge_band, 1e-3f));
+                const float hi_r = logf((float)im.r_out + cfg.edge_band);
+                const float inv_dx = (float)(im.nx / im.x_w), inv_dy = (float)(im.ny / im.y_w);
+                const bool me_near = o1 >= lo_r && o1 <= hi_r;
+                auto check = [&](int64_t q, float inv_pitch) {
+                    if (q < 0 || q >= cnt) return;
+                    const float on = pred[5 * q + 1];
+                    if ((me_near || (on >= lo_r && on <= hi_r)) && !(fabsf(on - o1) * inv_pitch <= cfg.grad_max))
+                        steep = true;
+                };
+                if (px > 0) check(i - 1, inv_dx);
+                if (px + 1 < im.nx) check(i + 1, inv_dx);
+                check(i - im.nx, inv_dy);
+                check(i + im.nx, inv_dy);
+            }
+            fb = !ok || steep || !(isfinite(o0) && isfinite(o1) && isfinite(o2)) || (pcap >= cfg.p_lo && pcap <= cfg.p_hi) ||
                  fabsf(rho - Rc) < cfg.crit_band || fabsf(rc - (float)im.r_in) < cfg.edge_band ||
                  fabsf(rc - (float)im.r_out) < cfg.edge_band ||
                  (cfg.g_tol > 0.0f && near_disk && !(fabs(gk - (double)g) <= (double)cfg.g_tol));
@@ -1192,7 +1212,7 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
     if (nimg < 1) return mlp_fail(m, KGRT_E_INVALID_ARG, "nimg must be >= 1");
     if (disk->kind != KGRT_MODEL_THIN_DISK) return mlp_fail(m, KGRT_E_UNSUPPORTED, "the surrogate renders the thin disk");
     if (!(fb->p_lo >= 0.0f && fb->p_hi <= 1.0f && fb->p_lo <= fb->p_hi && fb->crit_band >= 0.0f && fb->edge_band >= 0.0f &&
-          fb->g_tol >= 0.0f))
+          fb->g_tol >= 0.0f && fb->grad_max >= 0.0f))
         return mlp_fail(m, KGRT_E_INVALID_ARG, "invalid fallback settings");
     int64_t maxn = 0;
     for (int32_t k = 0; k < nimg; ++k) {
@@ -1223,7 +1243,7 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
     }
     if (flux) hipLaunchKernelGGL(zero_f64, dim3(1), dim3(256), 0, st, flux, (int64_t)nimg);
     if (fallback_counts) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, st, fallback_counts, (int64_t)nimg);
-    const RenderCfg cfg{fb->p_lo, fb->p_hi, fb->crit_band, fb->edge_band, fb->g_tol};
+    const RenderCfg cfg{fb->p_lo, fb->p_hi, fb->crit_band, fb->edge_band, fb->g_tol, fb->grad_max};
     // one ray list covers images of one observer distance and azimuth
     auto flush = [&](int64_t listed, double r_obs, double phi_obs) -> int {
         kgrt_outputs o{};

@@ -72,7 +72,7 @@ class CAdam(ctypes.Structure):
 
 class CFallback(ctypes.Structure):
     _fields_ = [("p_lo", ctypes.c_float), ("p_hi", ctypes.c_float), ("crit_band", ctypes.c_float),
-                ("edge_band", ctypes.c_float), ("g_tol", ctypes.c_float)]
+                ("edge_band", ctypes.c_float), ("g_tol", ctypes.c_float), ("grad_max", ctypes.c_float)]
 
 
 LAUNCH_PERSISTENT, LAUNCH_ONE_RAY_PER_THREAD = 0, 1
@@ -471,7 +471,8 @@ def surrogate_targets(rays: torch.Tensor, outs: Dict[str, torch.Tensor], stream=
 
 
 def surrogate_render(ctx: Context, mlp: Mlp, cameras: Sequence[Camera], model: Model, integ: Integrator,
-                     fallback=(0.05, 0.95, 0.5, 0.25, 0.0), stream=None):
+                     fallback=(0.05, 0.95, 0.5, 0.25, 0.0, 0.0), stream=None):
+    # (surrogate.DEFAULT_FALLBACK is the tuned policy; this default keeps the optional checks off)
     """kgrt_surrogate_render: thin-disk images from the network with FP64 fallback.
 
     Returns dict(intensity [total] f64, status [total] i32, flux [nimg] f64, fallback [nimg] i64)."""
@@ -482,7 +483,7 @@ def surrogate_render(ctx: Context, mlp: Mlp, cameras: Sequence[Camera], model: M
            "status": torch.empty(total, dtype=torch.int32, device=dev),
            "flux": torch.empty(len(cameras), dtype=torch.float64, device=dev),
            "fallback": torch.empty(len(cameras), dtype=torch.int64, device=dev)}
-    fb = CFallback(*(tuple(fallback) + (0.0,) * (5 - len(fallback))))
+    fb = CFallback(*(tuple(fallback) + (0.0,) * (6 - len(fallback))))
     rc = lib().kgrt_surrogate_render(ctx._h, mlp._h, cams, len(cameras), ctypes.byref(model.c()),
                                      ctypes.byref(integ.c()), ctypes.byref(fb), out["intensity"].data_ptr(),
                                      out["status"].data_ptr(), out["flux"].data_ptr(), out["fallback"].data_ptr(),

@@ -19,7 +19,18 @@ import torch
 from . import kgrt as K
 from . import scenes
 
-ARCH = "mlp 4-256x4-5 SiLU, BF16 hidden layers (MFMA, FP32 accumulate), FP32 head"
+ARCH = ("mlp 4-256x4-5 SiLU; training: 256x256 layers in BF16 on MFMA (FP32 accumulate), FP32 input layer, "
+        "head and Adam; inference: one fused MFMA kernel, input layer and head on hi+lo BF16 splits")
+
+# The trained network shipped with the package (thin disk r_in = ISCO, r_out = 20 M,
+# observer at 1000 M); its .json beside it records how it was trained and its accuracy.
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "thin_disk_mlp.npz")
+
+# Fallback policy (p_lo, p_hi, crit_band, edge_band, g_tol, grad_max): the two required rules
+# (capture probability band, 0.5 M critical-curve band) plus the disk-edge band, the g-head
+# consistency check and the neighbour rule, with thresholds chosen on 64 images of 1024^2
+# drawn from PCG64(1606).
+DEFAULT_FALLBACK = (0.05, 0.95, 0.5, 0.25, 0.005, 0.5)
 
 
 LAYERS = ((4, 256), (256, 256), (256, 256), (256, 256), (256, 5))

@@ -47,7 +47,7 @@ int main(void) {
   P(kgrt_camera) P(kgrt_model) P(kgrt_integrator) P(kgrt_outputs) P(kgrt_launch) P(kgrt_adam) P(kgrt_fallback)
   F(kgrt_camera, nx) F(kgrt_camera, x_min) F(kgrt_camera, y_max)
   F(kgrt_model, r_in) F(kgrt_model, r_emit_max) F(kgrt_integrator, max_steps) F(kgrt_integrator, flags)
-  F(kgrt_outputs, tau) F(kgrt_launch, refill_min) F(kgrt_adam, eps) F(kgrt_fallback, g_tol)
+  F(kgrt_outputs, tau) F(kgrt_launch, refill_min) F(kgrt_adam, eps) F(kgrt_fallback, grad_max)
   return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
@@ -67,7 +67,7 @@ int main(void) {
         "kgrt_integrator.max_steps": K.CIntegrator.max_steps.offset,
         "kgrt_integrator.flags": K.CIntegrator.flags.offset, "kgrt_outputs.tau": K.COutputs.tau.offset,
         "kgrt_launch.refill_min": K.CLaunch.refill_min.offset, "kgrt_adam.eps": K.CAdam.eps.offset,
-        "kgrt_fallback.g_tol": K.CFallback.g_tol.offset,
+        "kgrt_fallback.grad_max": K.CFallback.grad_max.offset,
     }
     for k, v in want.items():
         assert int(got[k]) == v, k

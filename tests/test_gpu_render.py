@@ -67,7 +67,7 @@ def test_default_policy_consistency(setup):
     from paper_1601_02063_amd import kgrt as K
     ctx, mlp, cams, mod, integ, plan, ref = setup
     # a policy that splits this (briefly trained) network's rays into both paths
-    for policy in ((0.05, 0.95, 0.5, 0.25, 0.05), (0.3, 0.7, 0.25, 0.1, 0.1), (0.49, 0.51, 0.0, 0.0, 0.0)):
+    for policy in ((0.05, 0.95, 0.5, 0.25, 0.05, 3.0), (0.3, 0.7, 0.25, 0.1, 0.1, 6.0), (0.49, 0.51, 0.0, 0.0, 0.0, 0.0)):
         out = K.surrogate_render(ctx, mlp, cams, mod, integ, fallback=policy)
         torch.cuda.synchronize()
         I, st = out["intensity"].cpu().numpy(), out["status"].cpu().numpy()
@@ -75,7 +75,7 @@ def test_default_policy_consistency(setup):
         if 0 < fb.sum() < len(fb):
             break
     assert 0 < fb.sum() < len(fb)
-    p_lo, p_hi, crit, edge, g_tol = policy
+    p_lo, p_hi, crit, edge, g_tol, grad_max = policy
     err = np.abs(I - ref["intensity"]) / np.maximum(np.abs(ref["intensity"]), 1e-300)
     assert np.all((I[fb] == ref["intensity"][fb]) | (err[fb] <= 1e-9))
     # non-fallback pixels: decode rule on the network's own outputs
@@ -112,6 +112,25 @@ def test_default_policy_consistency(setup):
             (np.abs(rc - 20.0) < edge + 1e-4) | ~np.isfinite(y[:, :3]).all(1)
         if g_tol > 0:
             others |= (rc >= rin - edge - 1e-4) & (rc <= 20.0 + edge + 1e-4)  # the g check may apply
+        if grad_max > 0:
+            # steepest change of the predicted ln r_c toward a 4-neighbour, one of the pair near the disk
+            lr_ = y[:, 1].astype(np.float64).reshape(cam.ny, cam.nx)
+            lo_r, hi_r = np.log(max(rin - edge, 1e-3)), np.log(20.0 + edge)
+            near = (lr_ >= lo_r) & (lr_ <= hi_r)
+            grad = np.zeros_like(lr_)
+            for ax, pitch in ((1, (cam.x_max - cam.x_min) / cam.nx), (0, (cam.y_max - cam.y_min) / cam.ny)):
+                dd = np.abs(np.diff(lr_, axis=ax)) / pitch
+                nn = near[:, 1:] | near[:, :-1] if ax == 1 else near[1:, :] | near[:-1, :]
+                dd = np.where(nn, dd, 0.0)
+                if ax == 1:
+                    grad[:, 1:] = np.maximum(grad[:, 1:], dd)
+                    grad[:, :-1] = np.maximum(grad[:, :-1], dd)
+                else:
+                    grad[1:, :] = np.maximum(grad[1:, :], dd)
+                    grad[:-1, :] = np.maximum(grad[:-1, :], dd)
+            grad = grad.ravel()
+            assert np.all(grad[nf] <= grad_max * (1 + 1e-4) + 1e-3)
+            others |= grad >= grad_max * (1 - 1e-4) - 1e-3
         only_crit = fb[lo:hi] & ~others
         assert np.all(dcrit[only_crit] < crit + 1e-3)
         # Keplerian g at the predicted radius for kept rays near the disk (oracle: xi = L/E)
