@@ -35,14 +35,14 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # divergence-free run (every lane traces the same ray), see
 # profiles/torus_flop_calibration.md. "formula": operation count of the
 # source with every divide, root and transcendental counted once.
-FLOPS_PER_ATTEMPT = {"torus": (2180.0, "calibrated"), "thin_disk": (620.0, "formula"),
+FLOPS_PER_ATTEMPT = {"torus": (1668.0, "calibrated"), "thin_disk": (620.0, "formula"),
                      "projection": (620.0, "formula")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
 # profiles/torus_1024_hbm_traffic.md. Valid only for the kernel sources they
 # were taken on (md5 of csrc/kgrt.hip + csrc/kgrt_device.hpp); null otherwise.
-TRAFFIC = {"torus": {"bytes": 3002214321, "source_md5": "575b399cfc72a7f596b8b9e11d0b57eb"}}
+TRAFFIC = {"torus": {"bytes": 8847787490, "source_md5": "0475c7061e6beeb7f7c0dece5688f53b"}}
 
 
 def kernel_source_md5() -> str:

@@ -52,6 +52,7 @@ struct KParams {
     // model
     int32_t model, nf;
     double freqs[16];
+    double inv_freqs[16];
     double r_in_cfg, r_out;
     TorusParams torus;
     // integrator
@@ -213,12 +214,14 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                             active = true;
                             if (MODEL == KGRT_MODEL_TORUS) {
                                 const double g0 = redshift(y.r, y.th, a, a2, -L);
+                                const double ig0 = fm::rcp(g0);
                                 const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
 #pragma unroll
                                 for (int f = 0; f < NF; ++f) {
                                     tau[f] = 0.0;
                                     Iacc[f] = 0.0;
-                                    if (f < nf) torus_coeffs(q, P.torus, g0, P.freqs[f], ap[f], ep[f]);
+                                    if (f < nf)
+                                        torus_coeffs(q, P.torus, g0, ig0, P.freqs[f], P.inv_freqs[f], ap[f], ep[f]);
                                 }
                             }
                         } else {
@@ -331,14 +334,15 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
                         // each accepted endpoint, exponential-trapezoid increment
                         const double g1 = redshift(y.r, y.th, a, a2, -L);
+                        const double ig1 = fm::rcp(g1);
                         const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
 #pragma unroll
                         for (int f = 0; f < NF; ++f) {
                             if (f < nf) {
                                 double a1, e1;
-                                torus_coeffs(q, P.torus, g1, P.freqs[f], a1, e1);
+                                torus_coeffs(q, P.torus, g1, ig1, P.freqs[f], P.inv_freqs[f], a1, e1);
                                 const double dtau = hdone * (ap[f] + a1) / 2.0;
-                                const double phi = (dtau > 0.0) ? -fm::expm1(-dtau) / dtau : 1.0;
+                                const double phi = (dtau > 0.0) ? -fm::expm1(-dtau) * fm::rcp(dtau) : 1.0;
                                 Iacc[f] += fm::exp(-tau[f]) * hdone * (ep[f] + e1) / 2.0 * phi;
                                 tau[f] += dtau;
                                 ap[f] = a1;
@@ -521,6 +525,13 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     T.eps_B = m->eps_B;
     T.rg = kGMsun * m->mbh_msun / (kC * kC);
     T.r_emit_max = m->r_emit_max;
+    T.cB = 8.0 * kPi * T.eps_B * kMp * kC * kC / 6.0;
+    T.cTheta = kKb * T.T0 / (kMe * kC * kC);
+    T.cNu = 3.0 * kQe / (4.0 * kPi * kMe * kC);
+    T.cJ = kQe * kQe / (1.7320508075688772 * kC);
+    T.cH = (T.T0 > 0.0) ? kH / (kKb * T.T0) : 0.0;
+    T.cBnu = kC * kC / (2.0 * kH);
+    for (int f = 0; f < 16; ++f) P.inv_freqs[f] = (f < P.nf && freqs[f] > 0.0) ? 1.0 / freqs[f] : 0.0;
     P.rtol = in->rtol;
     P.hmax_frac = in->hmax_frac;
     P.horizon_delta = in->horizon_delta;

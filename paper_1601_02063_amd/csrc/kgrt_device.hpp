@@ -340,63 +340,97 @@ __device__ __forceinline__ double redshift(double r, double th, double a, double
     s = clamp_sin(s);
     const double s2 = s * s;
     const double Sigma = r * r + a2 * c * c;
-    const double iS = 1.0 / Sigma;
+    const double iS = fm::rcp(Sigma);
     const double gtt = -(1.0 - 2.0 * r * iS);
     const double gtp = -2.0 * a * r * s2 * iS;
     const double gpp = (r * r + a2 + 2.0 * a2 * r * s2 * iS) * s2;
-    double Om = 1.0 / (r * sqrt(r) + a);
+    double Om = fm::rcp(r * sqrt(r) + a);
     double arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
     if (!(arg > 0.0)) {
-        Om = -gtp / gpp;
+        Om = -gtp * fm::rcp(gpp);
         arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
     }
     // 1/(u^t (1 - xi Omega)) with u^t = arg^-1/2
-    return sqrt(arg) / (1.0 - xi * Om);
+    return sqrt(arg) * fm::rcp(1.0 - xi * Om);
 }
 
 // Modified Bessel function K_2(x), x > 0, to ~1e-15 relative.
 //  x <= 2: the ascending series of Abramowitz & Stegun 9.6.11 for n = 2,
-//     K_2 = 2/x^2 - 1/2 + (x^2/4) sum_k t_k [ (H_k + H_{k+2})/2 - gamma - ln(x/2) ],
-//     t_k = (x^2/4)^k / (k! (k+2)!), H_k the harmonic numbers;
-//  x > 2: the trapezoidal rule on K_2(x) = int_0^inf exp(-x cosh u) cosh(2u) du
-//     (A&S 9.6.24), step min(0.2, 0.6/sqrt(x)), which converges geometrically
-//     for this entire, doubly-exponentially decaying integrand; cosh(k h) - 1
-//     and cosh(2 k h) come from a Chebyshev-type recurrence.
-__device__ inline double bessel_k2(double x) {
+//     K_2 = 2/x^2 - 1/2 + q sum_k c_k q^k [B_k - gamma - ln(x/2)],  q = x^2/4,
+//     c_k = 1/(k! (k+2)!), B_k = (H_k + H_{k+2})/2 (H the harmonic numbers),
+//     summed as two polynomials in q (13 terms: c_12 q^12 < 1e-20 for q <= 1);
+//  x > 2: K_2 = f(t) e^-x / sqrt(x) with f(t) = sqrt(x) e^x K_2(x), t = 2/x,
+//     a smooth function on (0, 1] evaluated from its Chebyshev expansion in
+//     s = 2t - 1 (Clenshaw's recurrence; coefficients by csrc/gen_k2_cheb.py).
+// Kept out of line: inlined into the integrator it raised the torus kernel's
+// spills from 124 to 284 bytes per lane and made it 45% slower (measured).
+namespace k2 {
+constexpr double harm(int n) { return n == 0 ? 0.0 : harm(n - 1) + 1.0 / n; }
+template <int K> struct C { static constexpr double value = 1.0 / (trig::fact(K) * trig::fact(K + 2)); };
+template <int K> struct CB {
+    static constexpr double value = C<K>::value * 0.5 * (harm(K) + harm(K + 2));
+};
+// max relative error of the expansion on t in (0, 1]: 3.53e-17
+constexpr double kCheb[23] = {
+    1.9262890227982927,
+    6.9995586038264909e-1,
+    2.6170713479740811e-2,
+    -7.5018244642171226e-4,
+    5.3674324702843297e-5,
+    -5.5565569992929136e-6,
+    7.1755728106304028e-7,
+    -1.0803493404324407e-7,
+    1.8257625536999556e-8,
+    -3.3812091171936075e-9,
+    6.7503021694118435e-10,
+    -1.4356710508630012e-10,
+    3.2240349844618053e-11,
+    -7.5919911324572731e-12,
+    1.8643740164153105e-12,
+    -4.7532395845036968e-13,
+    1.2534874890086944e-13,
+    -3.4086052776469779e-14,
+    9.5326307419863909e-15,
+    -2.735364562022107e-15,
+    8.03195174582688e-16,
+    -2.3917930684419428e-16,
+    6.6717415083862169e-17,
+};
+}  // namespace k2
+
+__device__ __noinline__ double bessel_k2(double x) {
     if (x <= 2.0) {
         const double q = 0.25 * x * x;
         const double lg = fm::log(0.5 * x) + kEulerGamma;
-        double t = 0.5, hk = 0.0, hk2 = 1.5;
-        double sum = t * (0.5 * (hk + hk2) - lg);
+        double pb = k2::CB<12>::value, pc = k2::C<12>::value;
+#define KGRT_K2_TERM(K)                      \
+    pb = fma(pb, q, k2::CB<K>::value);       \
+    pc = fma(pc, q, k2::C<K>::value);
+        KGRT_K2_TERM(11) KGRT_K2_TERM(10) KGRT_K2_TERM(9) KGRT_K2_TERM(8) KGRT_K2_TERM(7) KGRT_K2_TERM(6)
+        KGRT_K2_TERM(5) KGRT_K2_TERM(4) KGRT_K2_TERM(3) KGRT_K2_TERM(2) KGRT_K2_TERM(1) KGRT_K2_TERM(0)
+#undef KGRT_K2_TERM
+        return fma(q, fma(-lg, pc, pb), fma(0.5, fm::rcp(q), -0.5));
+    }
+    const double s = fma(4.0, fm::rcp(x), -1.0);
+    const double s2 = 2.0 * s;
+    double b1 = 0.0, b2 = 0.0;
 #pragma unroll
-        for (int k = 1; k < 16; ++k) {
-            t *= q / (k * (k + 2.0));
-            hk += 1.0 / k;
-            hk2 += 1.0 / (k + 2.0);
-            sum += t * (0.5 * (hk + hk2) - lg);
-        }
-        return 2.0 / (x * x) - 0.5 + q * sum;
+    for (int j = 22; j >= 1; --j) {
+        const double b0 = fma(s2, b1, k2::kCheb[j] - b2);
+        b2 = b1;
+        b1 = b0;
     }
-    const double h = fmin(0.2, 0.6 / sqrt(x));
-    const double u = 0.5 * h, u2 = u * u;  // sinh(u), u <= 0.1, Taylor through u^9
-    const double sh = u + u * u2 * (1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (1.0 / 5040.0 + u2 / 362880.0)));
-    const double e1 = 2.0 * sh * sh;  // cosh(h) - 1
-    const double c1 = 1.0 + e1;
-    double em1 = 0.0, e = e1, sum = 0.5;
-    for (int k = 1; k < 64; ++k) {
-        const double term = fm::exp(-x * e) * (1.0 + 4.0 * e + 2.0 * e * e);
-        sum += term;
-        if (term < 1e-18 * sum) break;
-        const double en = 2.0 * c1 * e - em1 + 2.0 * e1;
-        em1 = e;
-        e = en;
-    }
-    return h * fm::exp(-x) * sum;
+    const double f = fma(s, b1, k2::kCheb[0] - b2);
+    return f * fm::exp(-x) * fm::inv_root<2>(x);
 }
 
 // Torus and emission parameters in the form the kernels use.
 struct TorusParams {
     double n0, inv_rnorm, n_index, inv_2h2, T0, T_index, eps_B, rg, r_emit_max;
+    // products of constants, set on the host: B^2 = cB n_e / r, Theta_e = cTheta T_e/T0,
+    // nu_c = cNu B Theta_e^2, j prefactor = cJ n_e / K_2(1/Theta_e), h/(k T_e) = cH T0/T_e,
+    // 1/B_nu = cBnu expm1(h nu/(k T_e)) / nu^3
+    double cB, cTheta, cNu, cJ, cH, cBnu;
 };
 
 // Emission and absorption per unit affine parameter at (r, theta), redshift g,
@@ -406,7 +440,7 @@ struct TorusParams {
 // (Kirchhoff's law, section 4.5). Frequency-independent plasma quantities are
 // computed once per point by torus_plasma().
 struct Plasma {
-    double ne, Te, nu_c, jpref, hkT;  // jpref = n e^2/(sqrt(3) c K_2(1/Theta_e)), hkT = h/(k T_e)
+    double ne, Te, inv_nu_c, jpref, hkT;  // jpref = n e^2/(sqrt(3) c K_2(1/Theta_e)), hkT = h/(k T_e)
     bool emits;
 };
 
@@ -414,32 +448,34 @@ __device__ inline Plasma torus_plasma(const TorusParams& P, double r, double th,
     Plasma q;
     q.emits = (r > r_cap) && !(r > P.r_emit_max);
     if (!q.emits) {
-        q.ne = q.Te = q.nu_c = q.jpref = q.hkT = 0.0;
+        q.ne = q.Te = q.inv_nu_c = q.jpref = q.hkT = 0.0;
         return q;
     }
     double sth, cth;
     sincos_bounded(th, &sth, &cth);
-    const double z = r * cth;
     const double lx = fm::log(r * P.inv_rnorm);
-    q.ne = P.n0 * fm::exp(-P.n_index * lx - z * z * P.inv_2h2 / (r * r));
-    q.Te = P.T0 * fm::exp(-P.T_index * lx);
-    const double B = sqrt(8.0 * kPi * P.eps_B * q.ne * kMp * kC * kC / (6.0 * r));
-    const double theta_e = kKb * q.Te / (kMe * kC * kC);
-    q.nu_c = 3.0 * kQe * B / (4.0 * kPi * kMe * kC) * theta_e * theta_e;
-    q.jpref = q.ne * kQe * kQe / (1.7320508075688772 * kC * bessel_k2(1.0 / theta_e));
-    q.hkT = kH / (kKb * q.Te);
+    q.ne = P.n0 * fm::exp(-P.n_index * lx - cth * cth * P.inv_2h2);  // z^2/r^2 = cos^2(theta)
+    const double eT = fm::exp(-P.T_index * lx);                       // T_e/T0
+    const double ieT = fm::rcp(eT);
+    q.Te = P.T0 * eT;
+    const double B = sqrt(P.cB * q.ne * fm::rcp(r));
+    const double theta_e = P.cTheta * eT;
+    q.inv_nu_c = fm::rcp(P.cNu * B * theta_e * theta_e);
+    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT / P.cTheta));
+    q.hkT = P.cH * ieT;
     return q;
 }
 
-__device__ inline void torus_coeffs(const Plasma& q, const TorusParams& P, double g, double nu, double& a_lam,
-                                    double& e_lam) {
+// ig = 1/g; inv_nu = 1/nu.
+__device__ inline void torus_coeffs(const Plasma& q, const TorusParams& P, double g, double ig, double nu,
+                                    double inv_nu, double& a_lam, double& e_lam) {
     if (!q.emits) {
         a_lam = 0.0;
         e_lam = 0.0;
         return;
     }
-    const double nu0 = nu / g;
-    const double xm = nu0 / q.nu_c;
+    const double nu0 = nu * ig;
+    const double xm = nu0 * q.inv_nu_c;
     double j = 0.0;
     if (xm < 1e9) {  // beyond, exp(-1.8899 x^1/3) underflows to zero
         // w = x^(-1/12): x^(-1/6) = w^2, x^(-1/4) = w^3, x^(-1/2) = w^6, x^(1/3) = x w^8
@@ -450,10 +486,10 @@ __device__ inline void torus_coeffs(const Plasma& q, const TorusParams& P, doubl
     }
     double alpha = 0.0;
     if (j > 0.0) {
-        const double bnu = 2.0 * kH * nu0 * nu0 * nu0 / (kC * kC) / fm::expm1(nu0 * q.hkT);
-        alpha = j / bnu;
+        const double inv_nu0 = g * inv_nu;
+        alpha = j * fm::expm1(nu0 * q.hkT) * P.cBnu * (inv_nu0 * inv_nu0 * inv_nu0);  // j / B_nu(T_e)
     }
-    a_lam = P.rg * alpha / g;
+    a_lam = P.rg * alpha * ig;
     e_lam = P.rg * g * g * j;
 }
 
