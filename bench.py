@@ -35,14 +35,14 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # divergence-free run (every lane traces the same ray), see
 # profiles/torus_flop_calibration.md. "formula": operation count of the
 # source with every divide, root and transcendental counted once.
-FLOPS_PER_ATTEMPT = {"torus": (1668.0, "calibrated"), "thin_disk": (620.0, "formula"),
+FLOPS_PER_ATTEMPT = {"torus": (1601.0, "calibrated"), "thin_disk": (620.0, "formula"),
                      "projection": (620.0, "formula")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
 # profiles/torus_1024_hbm_traffic.md. Valid only for the kernel sources they
 # were taken on (md5 of csrc/kgrt.hip + csrc/kgrt_device.hpp); null otherwise.
-TRAFFIC = {"torus": {"bytes": 8847787490, "source_md5": "0475c7061e6beeb7f7c0dece5688f53b"}}
+TRAFFIC = {"torus": {"bytes": 547238593, "source_md5": "0e9a89230347053981259304e4ff0ec9"}}
 
 
 def kernel_source_md5() -> str:

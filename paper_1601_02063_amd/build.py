@@ -28,7 +28,7 @@ def hipcc() -> str:
 def build(force: bool = True, verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Compile the library in-tree (always, unless force=False and it is up to date).
 
-    defines: extra preprocessor settings, e.g. ("KGRT_WAVES_PER_EU=3",) for launch-shape experiments.
+    defines: extra preprocessor settings, e.g. ("KGRT_WAVES_TORUS=3",) for launch-shape experiments.
     """
     if not force and os.path.exists(out):
         newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)

@@ -139,21 +139,32 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
     }
 }
 
-// Waves per SIMD the register allocation targets, per model (measured on
-// MI355X: the crossing-tracking kernel is fastest with one wave and the
-// whole register file, the transfer kernel with three).
-#ifdef KGRT_WAVES_PER_EU
-template <int MODEL> struct WavesPerEU { static constexpr int value = KGRT_WAVES_PER_EU; };
-#else
-template <int MODEL> struct WavesPerEU { static constexpr int value = (MODEL == KGRT_MODEL_TORUS) ? 3 : 1; };
+// Waves per SIMD the register allocation targets, per model and number of
+// frequencies carried (measured on MI355X; fewer waves give each one more of
+// the register file, which these FP64 kernels need more than extra waves to
+// hide latency: at three waves the one-frequency transfer kernel spilled
+// 144 B per lane and ran 14% slower, the eight-frequency one 2.8x slower; one
+// wave is 35% slower for eight frequencies and 11% slower for the thin disk).
+#ifndef KGRT_WAVES_DISK
+#define KGRT_WAVES_DISK 2
 #endif
+#ifndef KGRT_WAVES_TORUS
+#define KGRT_WAVES_TORUS 2
+#endif
+#ifndef KGRT_WAVES_TORUS_MULTI
+#define KGRT_WAVES_TORUS_MULTI 2
+#endif
+template <int MODEL, int NF> struct WavesPerEU {
+    static constexpr int value =
+        (MODEL != KGRT_MODEL_TORUS) ? KGRT_WAVES_DISK : (NF == 1 ? KGRT_WAVES_TORUS : KGRT_WAVES_TORUS_MULTI);
+};
 
 // Persistent integrator over the rays of one chunk. MODEL selects the
 // crossing-tracking models (geodesic, thin disk) or the transfer model
 // (torus); NF bounds the number of frequencies carried in registers.
 template <int MODEL, int NF>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(WavesPerEU<MODEL>::value, WavesPerEU<MODEL>::value)))
+__attribute__((amdgpu_waves_per_eu(WavesPerEU<MODEL, NF>::value, WavesPerEU<MODEL, NF>::value)))
 trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restrict__ rec, int64_t cap) {
     constexpr bool kDisk = (MODEL != KGRT_MODEL_TORUS);
     if (P.count_dev) count = std::max<int64_t>(0, std::min<int64_t>(count, *P.count_dev - base));
@@ -163,6 +174,10 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
     int64_t rid = 0;
     State y{};
     double h = 0.0, a = 0.0, a2 = 0.0, L = 0.0, r_cap = 0.0, r_in = 0.0, r_obs = 0.0;
+    // sin(theta) (clamped, section 2.1) and cos(theta) of y, computed once per
+    // point and shared by the first RHS stage, the redshift, the plasma and the
+    // crossing test; for the crossing-tracking models also those of y_k
+    double sy = 0.0, cy = 0.0, syk = 0.0, cyk = 0.0;
     int32_t steps = 0, attempts = 0, status = 0;
     // crossing refinement (thin disk / geodesic): Newton iteration on the
     // step size from y_k, run in lockstep with the other lanes' attempts
@@ -210,12 +225,14 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         h = P.hmax_frac * r_obs;
                         steps = attempts = status = 0;
                         crossed = refine = false;
+                        sincos_bounded(y.th, &sy, &cy);
+                        sy = clamp_sin(sy);
                         if (isfinite(y.r)) {
                             active = true;
                             if (MODEL == KGRT_MODEL_TORUS) {
-                                const double g0 = redshift(y.r, y.th, a, a2, -L);
+                                const double g0 = redshift_sc(y.r, sy, cy, a, a2, -L);
                                 const double ig0 = fm::rcp(g0);
-                                const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
+                                const Plasma q = torus_plasma(P.torus, y.r, cy, r_cap);
 #pragma unroll
                                 for (int f = 0; f < NF; ++f) {
                                     tau[f] = 0.0;
@@ -257,7 +274,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
         bool terminate = false;
         const State yb = (kDisk && refine) ? yk : y;
         const double hb = (kDisk && refine) ? hs : h;
-        const State k1 = rhs(yb, a, a2, L);
+        const State k1 = rhs_sc(yb, (kDisk && refine) ? syk : sy, (kDisk && refine) ? cyk : cy, a, a2, L);
         State yn, ye;
         cash_karp(yb, k1, hb, a, a2, L, yn, ye);
         bool check_end = false;
@@ -302,7 +319,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                 const double tol = P.rtol;
 #define KGRT_ERR(f)                                                                      \
     {                                                                                    \
-        const double e = fabs(ye.f) / (tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12));      \
+        const double e = fabs(ye.f) * fm::rcp(tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12)); \
         if (e > errmax) errmax = e;                                                      \
     }
                 KGRT_ERR(r) KGRT_ERR(th) KGRT_ERR(ph) KGRT_ERR(t) KGRT_ERR(pr) KGRT_ERR(pth)
@@ -323,9 +340,15 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                 const double hdone = h;
                 double hnext = (errmax > 1.89e-4) ? h * (0.9 * fm::pow_m02(errmax)) : h * 5.0;
                 ++steps;
-                if (kDisk) yk = y;
-                const double thk = y.th;
+                if (kDisk) {
+                    yk = y;
+                    syk = sy;
+                    cyk = cy;
+                }
+                const double c0 = cy;  // cos(theta) at y_k
                 y = yn;
+                sincos_bounded(y.th, &sy, &cy);
+                sy = clamp_sin(sy);
                 if (!finite6(y)) {
                     status |= ST_NONFINITE;
                     terminate = true;
@@ -333,9 +356,9 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     if (MODEL == KGRT_MODEL_TORUS) {
                         // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
                         // each accepted endpoint, exponential-trapezoid increment
-                        const double g1 = redshift(y.r, y.th, a, a2, -L);
+                        const double g1 = redshift_sc(y.r, sy, cy, a, a2, -L);
                         const double ig1 = fm::rcp(g1);
-                        const Plasma q = torus_plasma(P.torus, y.r, y.th, r_cap);
+                        const Plasma q = torus_plasma(P.torus, y.r, cy, r_cap);
 #pragma unroll
                         for (int f = 0; f < NF; ++f) {
                             if (f < nf) {
@@ -351,9 +374,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         }
                         check_end = true;
                     } else {
-                        double c0, c1, sdum;
-                        sincos_bounded(thk, &sdum, &c0);
-                        sincos_bounded(y.th, &sdum, &c1);
+                        const double c1 = cy;
                         if (!crossed && ((c0 > 0.0 && c1 <= 0.0) || (c0 < 0.0 && c1 >= 0.0))) {
                             // first equatorial crossing inside this step: refine it over the
                             // next evaluations, starting from linear interpolation of cos(theta)

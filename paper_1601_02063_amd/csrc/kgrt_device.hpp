@@ -212,10 +212,8 @@ __device__ __forceinline__ double pow_m02(double x) { return inv_root<5>(x); }
 //   p_r' = [2 r E W / Delta - (r - 1)(W^2/Delta^2 + p_r^2)] / Sigma,  W = (r^2+a^2)E - aL,
 // equal to the printed form on the null cone; it keeps 2 Sigma H conserved,
 // which the printed form does not on ingoing rays.
-__device__ __forceinline__ State rhs(const State& y, double a, double a2, double L) {
-    double s, c;
-    sincos_bounded(y.th, &s, &c);
-    s = clamp_sin(s);
+// With sin(theta) (clamped) and cos(theta) of y given.
+__device__ __forceinline__ State rhs_sc(const State& y, double s, double c, double a, double a2, double L) {
     const double r = y.r;
     const double r2a2 = r * r + a2;
     const double Sigma = r * r + a2 * c * c;
@@ -234,6 +232,12 @@ __device__ __forceinline__ State rhs(const State& y, double a, double a2, double
     d.pr = (-2.0 * r * WiD - (r - 1.0) * (WiD * WiD + y.pr * y.pr)) * iS;
     d.pth = s * c * iS * (L * L * is2 * is2 - a2);
     return d;
+}
+
+__device__ __forceinline__ State rhs(const State& y, double a, double a2, double L) {
+    double s, c;
+    sincos_bounded(y.th, &s, &c);
+    return rhs_sc(y, clamp_sin(s), c, a, a2, L);
 }
 
 __device__ __forceinline__ State axpy(const State& y, double h, const State& k) {
@@ -334,10 +338,8 @@ __device__ __forceinline__ bool start_ray(double a, double a2, double r_obs, dou
 // orbit, Omega = 1/(r^3/2 + a) in Boyer-Lindquist r at any theta, u^r = u^theta = 0,
 // seen by an observer at rest at infinity; the zero-angular-momentum
 // observer replaces it where u.u = -1 has no solution. xi = L_z/E.
-__device__ __forceinline__ double redshift(double r, double th, double a, double a2, double xi) {
-    double s, c;
-    sincos_bounded(th, &s, &c);
-    s = clamp_sin(s);
+// With sin(theta) (clamped) and cos(theta) given.
+__device__ __forceinline__ double redshift_sc(double r, double s, double c, double a, double a2, double xi) {
     const double s2 = s * s;
     const double Sigma = r * r + a2 * c * c;
     const double iS = fm::rcp(Sigma);
@@ -352,6 +354,12 @@ __device__ __forceinline__ double redshift(double r, double th, double a, double
     }
     // 1/(u^t (1 - xi Omega)) with u^t = arg^-1/2
     return sqrt(arg) * fm::rcp(1.0 - xi * Om);
+}
+
+__device__ __forceinline__ double redshift(double r, double th, double a, double a2, double xi) {
+    double s, c;
+    sincos_bounded(th, &s, &c);
+    return redshift_sc(r, clamp_sin(s), c, a, a2, xi);
 }
 
 // Modified Bessel function K_2(x), x > 0, to ~1e-15 relative.
@@ -444,15 +452,14 @@ struct Plasma {
     bool emits;
 };
 
-__device__ inline Plasma torus_plasma(const TorusParams& P, double r, double th, double r_cap) {
+// cth = cos(theta).
+__device__ inline Plasma torus_plasma(const TorusParams& P, double r, double cth, double r_cap) {
     Plasma q;
     q.emits = (r > r_cap) && !(r > P.r_emit_max);
     if (!q.emits) {
         q.ne = q.Te = q.inv_nu_c = q.jpref = q.hkT = 0.0;
         return q;
     }
-    double sth, cth;
-    sincos_bounded(th, &sth, &cth);
     const double lx = fm::log(r * P.inv_rnorm);
     q.ne = P.n0 * fm::exp(-P.n_index * lx - cth * cth * P.inv_2h2);  // z^2/r^2 = cos^2(theta)
     const double eT = fm::exp(-P.T_index * lx);                       // T_e/T0

@@ -41,6 +41,13 @@ constexpr int64_t kNumParams = kB5 + kOut;  // 199941
 // the packed BF16 weights Wf: W2..W4 [3][out][in], then W5 split into hi and lo parts [2][16][256]
 constexpr int64_t kW5Split = 3 * kH * kH, kW5Rows = 16;
 constexpr int64_t kWfSize = kW5Split + 2 * kW5Rows * kH;
+// Inference folds the base-2 exponential's scale c = log2(e) into the weights:
+// with W1, b1..b4 scaled by -c and W5 by -1/c, every hidden layer computes
+// ht = -c SiLU(z) directly from zt = -c z as zt / (1 + 2^zt) (W2..W4 are
+// unchanged, since -c cancels between consecutive layers). The scaled FP32 W1
+// [256][4] and biases [4][256] live in a small buffer Pi.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr int64_t kPiW1 = 0, kPiB = kH * kIn, kPiSize = kPiB + 4 * kH;
 constexpr float kWCap = 1.0f, kWLogR = 10.0f, kWG = 10.0f, kWPhi = 1.0f;
 
 // sigmoid with the hardware base-2 exponential and reciprocal (about 1 ulp
@@ -204,7 +211,7 @@ constexpr int kInferThreads = 64 * (4 / kInferRI) * (16 / kInferUJ);
 template <int RI, int UJ>
 __global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
 mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict__ P, const __bf16* __restrict__ Wf,
-                float* __restrict__ y) {
+                const float* __restrict__ Pi, float* __restrict__ y) {
     constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
     static_assert(kTileRows % (16 * RI) == 0 && kH % (16 * UJ) == 0, "tile shape");
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
@@ -224,7 +231,7 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
     bf16x8 w1f[UJ];
 #pragma unroll
     for (int j = 0; j < UJ; ++j) {
-        const float* w = P + kW1 + (16 * (UJ * wu + j) + lr) * kIn;
+        const float* w = Pi + kPiW1 + (16 * (UJ * wu + j) + lr) * kIn;
         bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
         __bf16 hi[kIn], lo[kIn];
 #pragma unroll
@@ -240,17 +247,29 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
         }
         w1f[j] = f;
     }
-    // SiLU(acc + bias) of one layer into the activation buffer; accumulator e of
-    // (i, j) is row 16 (RI wr + i) + lr, unit 16 (UJ wu + j) + 4 lg + e
-    auto store = [&](const f32x4 (&acc)[RI][UJ], const float* __restrict__ bias) {
+    // Accumulators start at the layer's scaled bias; accumulator e of (i, j) is
+    // row 16 (RI wr + i) + lr, unit 16 (UJ wu + j) + 4 lg + e.
+    auto init = [&](f32x4 (&acc)[RI][UJ], int layer) {
+#pragma unroll
+        for (int j = 0; j < UJ; ++j) {
+            const f32x4 b = *reinterpret_cast<const f32x4*>(Pi + kPiB + layer * kH + 16 * (UJ * wu + j) + 4 * lg);
+#pragma unroll
+            for (int i = 0; i < RI; ++i) acc[i][j] = b;
+        }
+    };
+    // ht = zt / (1 + 2^zt) of one layer into the activation buffer
+    auto store = [&](const f32x4 (&acc)[RI][UJ]) {
 #pragma unroll
         for (int j = 0; j < UJ; ++j) {
             const int u = 16 * (UJ * wu + j) + 4 * lg;
-            const float bb0 = bias[u], bb1 = bias[u + 1], bb2 = bias[u + 2], bb3 = bias[u + 3];
 #pragma unroll
             for (int i = 0; i < RI; ++i) {
-                const bf16x4 v = {(__bf16)silu_(acc[i][j][0] + bb0), (__bf16)silu_(acc[i][j][1] + bb1),
-                                  (__bf16)silu_(acc[i][j][2] + bb2), (__bf16)silu_(acc[i][j][3] + bb3)};
+                bf16x4 v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float zt = acc[i][j][e];
+                    v[e] = (__bf16)(zt * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(zt)));
+                }
                 *reinterpret_cast<bf16x4*>(act + (16 * (RI * wr + i) + lr) * kLdsStride + u) = v;
             }
         }
@@ -264,6 +283,7 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
         // input layer (rows past n compute on zeros and are never written out)
         {
             f32x4 acc[RI][UJ];
+            init(acc, 0);
 #pragma unroll
             for (int i = 0; i < RI; ++i) {
                 const float* xr = xs + (16 * (RI * wr + i) + lr) * kIn;
@@ -278,21 +298,17 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
                 }
 #pragma unroll
                 for (int j = 0; j < UJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, acc[i][j], 0, 0, 0);
             }
-            store(acc, P + kB1);
+            store(acc);
         }
         __syncthreads();
         // hidden layers 2..4 on MFMA, in place
         for (int l = 0; l < 3; ++l) {
             const __bf16* W = Wf + (int64_t)l * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
             const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
-            const float* bias = P + (l == 0 ? kB2 : (l == 1 ? kB3 : kB4));
             f32x4 acc[RI][UJ];
-#pragma unroll
-            for (int i = 0; i < RI; ++i)
-#pragma unroll
-                for (int j = 0; j < UJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            init(acc, l + 1);
 #pragma unroll 1
             for (int s = 0; s < kH / 32; ++s) {
                 const int k = 32 * s + 8 * lg;
@@ -308,7 +324,7 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
             }
             __syncthreads();  // every wave has read this layer's input
-            store(acc, bias);
+            store(acc);
             __syncthreads();
         }
         // output head: row tile rt, outputs 0..15 (5 used), hi and lo parts of W5
@@ -482,12 +498,24 @@ __global__ void __launch_bounds__(256) adam(float* __restrict__ P, float* __rest
 // gradients); after them in Wf, W5 as two BF16 parts hi + lo of 16 x 256
 // (outputs 5..15 zero) for the inference kernel's output head.
 __global__ void __launch_bounds__(256) pack_weights(const float* __restrict__ P, __bf16* __restrict__ Wf,
-                                                    __bf16* __restrict__ Wb) {
-    const int l = blockIdx.y;  // 0..2 -> W2..W4, 3 -> W5 split
+                                                    __bf16* __restrict__ Wb, float* __restrict__ Pi) {
+    const int l = blockIdx.y;  // 0..2 -> W2..W4, 3 -> W5 split, 4 -> scaled W1 and biases
+    if (l == 4) {
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kPiSize; i += gridDim.x * blockDim.x) {
+            if (i < kPiB) {
+                Pi[i] = -kLog2e * P[kW1 + i];
+            } else {
+                const int layer = (i - kPiB) / kH, u = (i - kPiB) % kH;
+                const int64_t off = layer == 0 ? kB1 : (layer == 1 ? kB2 : (layer == 2 ? kB3 : kB4));
+                Pi[i] = -kLog2e * P[off + u];
+            }
+        }
+        return;
+    }
     if (l == 3) {
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kW5Rows * kH; i += gridDim.x * blockDim.x) {
             const int o = i / kH;
-            const float w = (o < kOut) ? P[kW5 + i] : 0.0f;
+            const float w = (o < kOut) ? -P[kW5 + i] / kLog2e : 0.0f;
             const __bf16 hi = (__bf16)w;
             Wf[kW5Split + i] = hi;
             Wf[kW5Split + kW5Rows * kH + i] = (__bf16)(w - (float)hi);
@@ -823,6 +851,7 @@ struct kgrt_mlp {
     int64_t max_batch = 0;
     float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr;
     __bf16 *Wf = nullptr, *Wb = nullptr;
+    float* Pi = nullptr;  // scaled W1 and biases for inference
     // activations / gradients, batch-major [B][256] unless named T (feature-major [256][B])
     __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr, *dz2 = nullptr, *dzT = nullptr;
     float* dout = nullptr;
@@ -895,7 +924,7 @@ int64_t kgrt_mlp_num_params(void) { return kNumParams; }
 int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
-    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->dz, m->dz2, m->dzT, m->dout, m->r_feat, m->r_pred,
+    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Pi, m->dz, m->dz2, m->dzT, m->dout, m->r_feat, m->r_pred,
                     m->r_tab, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
                     m->h[1], m->h[2], m->h[3], m->h[4], m->z[1], m->z[2], m->z[3], m->z[4],
                     m->hT[1], m->hT[2], m->hT[3]};
@@ -919,6 +948,7 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
     bool ok = hipMalloc(&m->P, kNumParams * 4) == hipSuccess && hipMalloc(&m->M, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->V, kNumParams * 4) == hipSuccess && hipMalloc(&m->G, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->Wf, kWfSize * sizeof(__bf16)) == hipSuccess &&
+              hipMalloc(&m->Pi, kPiSize * sizeof(float)) == hipSuccess &&
               hipMalloc(&m->Wb, 3 * kH * kH * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess;
     for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess && hipMalloc(&m->z[l], hb) == hipSuccess;
@@ -943,7 +973,7 @@ int kgrt_mlp_set_params(kgrt_mlp* m, const float* params, int64_t n) {
         return mlp_fail(m, KGRT_E_HIP, "hipMemcpy failed");
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->M, kNumParams, 0.0f);
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->V, kNumParams, 0.0f);
-    hipLaunchKernelGGL(pack_weights, dim3(64, 4), dim3(256), 0, 0, m->P, m->Wf, m->Wb);
+    hipLaunchKernelGGL(pack_weights, dim3(64, 5), dim3(256), 0, 0, m->P, m->Wf, m->Wb, m->Pi);
     m->step = 0;
     if (hipDeviceSynchronize() != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "set_params failed");
     return KGRT_OK;
@@ -973,7 +1003,7 @@ int kgrt_mlp_forward(kgrt_mlp* m, const float* x, float* y, int64_t n, void* str
         per_cu = 1;
     const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)ncu * per_cu));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kInferThreads), 0, st, x, n, m->P, m->Wf, y);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kInferThreads), 0, st, x, n, m->P, m->Wf, m->Pi, y);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
@@ -1057,7 +1087,7 @@ int kgrt_mlp_train_step(kgrt_mlp* m, const float* x, const float* t, const int32
     const float c1 = 1.0f - powf(opt->beta1, (float)m->step), c2 = 1.0f - powf(opt->beta2, (float)m->step);
     hipLaunchKernelGGL(adam, dim3(256), dim3(256), 0, st, m->P, m->M, m->V, m->G, kNumParams, opt->lr, opt->beta1,
                        opt->beta2, opt->eps, c1, c2);
-    hipLaunchKernelGGL(pack_weights, dim3(64, 4), dim3(256), 0, st, m->P, m->Wf, m->Wb);
+    hipLaunchKernelGGL(pack_weights, dim3(64, 5), dim3(256), 0, st, m->P, m->Wf, m->Wb, m->Pi);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
