@@ -38,9 +38,11 @@ constexpr int64_t kW3 = kB2 + kH, kB3 = kW3 + kH * kH;
 constexpr int64_t kW4 = kB3 + kH, kB4 = kW4 + kH * kH;
 constexpr int64_t kW5 = kB4 + kH, kB5 = kW5 + kOut * kH;
 constexpr int64_t kNumParams = kB5 + kOut;  // 199941
-// the packed BF16 weights Wf: W2..W4 [3][out][in], then W5 split into hi and lo parts [2][16][256]
+// the packed BF16 weights Wf: W2..W4 [3][out][in], then W5 split into hi and lo
+// parts [2][16][256] twice: scaled for inference (see below) and unscaled for training
 constexpr int64_t kW5Split = 3 * kH * kH, kW5Rows = 16;
-constexpr int64_t kWfSize = kW5Split + 2 * kW5Rows * kH;
+constexpr int64_t kW5SplitU = kW5Split + 2 * kW5Rows * kH;
+constexpr int64_t kWfSize = kW5SplitU + 2 * kW5Rows * kH;
 // Inference folds the base-2 exponential's scale c = log2(e) into the weights:
 // with W1, b1..b4 scaled by -c and W5 by -1/c, every hidden layer computes
 // ht = -c SiLU(z) directly from zt = -c z as zt / (1 + 2^zt) (W2..W4 are
@@ -55,137 +57,6 @@ constexpr float kWCap = 1.0f, kWLogR = 10.0f, kWG = 10.0f, kWPhi = 1.0f;
 __device__ __forceinline__ float sigmoidf_(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
-__device__ __forceinline__ float silu_(float z) { return z * sigmoidf_(z); }
-__device__ __forceinline__ float silu_grad_(float z) {
-    const float s = sigmoidf_(z);
-    return s * (1.0f + z * (1.0f - s));
-}
-
-// ------------------------------------------------------------ input layer
-// h1 = SiLU(x W1^T + b1), x gathered through idx (or identity). One block of
-// 256 threads (thread = hidden unit) handles 16 samples.
-__global__ void __launch_bounds__(256) in_layer(const float* __restrict__ x, const int32_t* __restrict__ idx,
-                                                int64_t n, const float* __restrict__ P, __bf16* __restrict__ h,
-                                                __bf16* __restrict__ z_out, __bf16* __restrict__ hT, int64_t ldT) {
-    const int o = threadIdx.x;
-    const float w0 = P[kW1 + o * kIn + 0], w1 = P[kW1 + o * kIn + 1], w2 = P[kW1 + o * kIn + 2],
-                w3 = P[kW1 + o * kIn + 3], bb = P[kB1 + o];
-    const int64_t b0 = (int64_t)blockIdx.x * 16;
-    for (int s = 0; s < 16; ++s) {
-        const int64_t b = b0 + s;
-        if (b >= n) break;
-        const int64_t src = idx ? idx[b] : b;
-        const float* xr = x + src * kIn;
-        const float z = bb + w0 * xr[0] + w1 * xr[1] + w2 * xr[2] + w3 * xr[3];
-        const float a = silu_(z);
-        h[b * kH + o] = (__bf16)a;
-        if (z_out) z_out[b * kH + o] = (__bf16)z;
-        if (hT) hT[o * ldT + b] = (__bf16)a;
-    }
-}
-
-// --------------------------------------------------------- MFMA product
-// out[b][n] = sum_k A[b][k] * Bt[n][k], A: [rows][lda] BF16, Bt: [256][ldb] BF16,
-// k in [k0, k0 + klen). One wave computes 16 rows x 64 columns; a block of
-// four waves covers 16 rows x 256 columns. Grid: (row tiles, k chunks).
-enum Epi { EPI_FWD = 0, EPI_BWD = 1, EPI_ATOMIC = 2 };
-
-struct GemmArgs {
-    const __bf16* A;
-    int64_t lda;
-    const __bf16* Bt;
-    int64_t ldb;
-    int64_t rows;   // multiple of 16 handled with bounds checks on the row side
-    int64_t klen;   // reduction length per block (multiple of 32)
-    int64_t kend;   // reduction stops at kend (multiple of 32)
-    // epilogue
-    const float* bias;       // EPI_FWD: [256]
-    __bf16* h;               // EPI_FWD: activation out [rows][256]
-    __bf16* zsave;           // EPI_FWD: pre-activation out (may be null)
-    const __bf16* zin;       // EPI_BWD: pre-activation of this layer [rows][256]
-    __bf16* dz;              // EPI_BWD: dL/dz out [rows][256]
-    __bf16* outT;            // EPI_FWD / EPI_BWD: feature-major copy [256][ldT] (may be null)
-    int64_t ldT;
-    float* acc_out;          // EPI_ATOMIC: [rows][256] FP32, accumulated with atomics
-};
-
-template <int EPI>
-__global__ void __launch_bounds__(256) gemm_bt(const GemmArgs g) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * 16;  // b rows of this tile
-    const int64_t kbase = (int64_t)blockIdx.y * g.klen;
-    const int n0 = wave * 64;
-    f32x4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = lane & 15, lg = lane >> 4;  // MFMA lane coordinates
-    const int64_t arow = r0 + lr;
-    const bool arow_ok = arow < g.rows;
-    const int64_t kstop = std::min<int64_t>(kbase + g.klen, g.kend);
-    for (int64_t kk = kbase; kk < kstop; kk += 32) {
-        const int64_t k = kk + 8 * lg;
-        bf16x8 bfrag;  // MFMA B operand: column b = lr, rows k..k+7
-        if (arow_ok) {
-            bfrag = *reinterpret_cast<const bf16x8*>(g.A + arow * g.lda + k);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bfrag[e] = (__bf16)0.0f;
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int n = n0 + 16 * t + lr;  // MFMA A operand: row n, k..k+7
-            const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(g.Bt + (int64_t)n * g.ldb + k);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[t], 0, 0, 0);
-        }
-    }
-    // accumulator e of tile t holds out[b = r0 + lr][n = n0 + 16 t + 4 lg + e]
-    const int64_t b = r0 + lr;
-    if (b >= g.rows) return;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int nb = n0 + 16 * t + 4 * lg;
-        if (EPI == EPI_ATOMIC) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) atomicAdd(&g.acc_out[b * kH + nb + e], acc[t][e]);
-        } else if (EPI == EPI_FWD) {
-            __bf16 hv[4], zv[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float z = acc[t][e] + g.bias[nb + e];
-                zv[e] = (__bf16)z;
-                hv[e] = (__bf16)silu_(z);
-            }
-            __bf16* hp = g.h + b * kH + nb;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) hp[e] = hv[e];
-            if (g.zsave) {
-                __bf16* zp = g.zsave + b * kH + nb;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) zp[e] = zv[e];
-            }
-            if (g.outT) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) g.outT[(int64_t)(nb + e) * g.ldT + b] = hv[e];
-            }
-        } else {  // EPI_BWD: dz = (dL/dh) * SiLU'(z)
-            __bf16 dv[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float z = (float)g.zin[b * kH + nb + e];
-                dv[e] = (__bf16)(acc[t][e] * silu_grad_(z));
-            }
-            __bf16* dp = g.dz + b * kH + nb;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) dp[e] = dv[e];
-            if (g.outT) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) g.outT[(int64_t)(nb + e) * g.ldT + b] = dv[e];
-            }
-        }
-    }
-}
-
 
 // ----------------------------------------------------- fused inference
 // Inference of the whole network for tiles of 64 samples, one tile at a time
@@ -352,130 +223,383 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
     }
 }
 
-// ------------------------------------------------------------ output head
-// o = h4 W5^T + b5 in FP32 (one thread per sample). Training: also the loss
-// (block-reduced, one atomic per block) and dL/do.
-__global__ void __launch_bounds__(256) out_layer(const __bf16* __restrict__ h4, int64_t n, const float* __restrict__ P,
-                                                 float* __restrict__ y, const float* __restrict__ t,
-                                                 const int32_t* __restrict__ idx, float* __restrict__ dout,
-                                                 float* __restrict__ loss, float inv_n) {
-    __shared__ float red[256];
-    __shared__ float w5[kOut * kH];
-    for (int i = threadIdx.x; i < kOut * kH; i += blockDim.x) w5[i] = P[kW5 + i];
-    __syncthreads();
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float l = 0.0f;
-    if (b < n) {
-        float o[kOut];
+
+// ------------------------------------------------------- fused training
+// One training step in four kernels over 64-sample tiles of the batch
+// (gathered through idx):
+//  train_fwd: the inference kernel's structure in unscaled form; stores each
+//    layer's SiLU'(z) and activation h (layers 1..4) feature-major [256][ld]
+//    in BF16, dL/do [B][5] (FP32) and the loss;
+//  train_bwd: dz4 = (dL/do W5) SiLU'(z4), then dh_{l-1} = dz_l W_l on MFMA
+//    (with W_l^T) and dz_{l-1} = dh_{l-1} SiLU'(z_{l-1}) in a column pass that
+//    also stores dz feature-major and sums the gradients of b1..b4, W1, W5, b5
+//    (per block, one atomic per value at the end);
+//  train_dw: dW_l = sum_b dz_l[b] h_{l-1}[b]^T (l = 2..4) on MFMA as partial
+//    sums over row chunks, added up by train_dw_reduce.
+constexpr int kDwChunks = 64;
+
+struct TrainBufs {
+    __bf16* sT[4];   // SiLU'(z) of layers 1..4, feature-major
+    __bf16* hT[4];   // h of layers 1..4, feature-major
+    __bf16* dzT[4];  // dL/dz of layers 1..4, feature-major (layers 2..4 used)
+    int64_t ld;      // leading dimension of the feature-major arrays
+    float* dout;     // dL/do [B][5]
+    float* loss;
+    float inv_n;
+};
+
+template <int RI, int UJ>
+__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(3, 3)))
+train_fwd(const float* __restrict__ x, const int32_t* __restrict__ idx, const float* __restrict__ t, int64_t n,
+          const float* __restrict__ P, const __bf16* __restrict__ Wf, const TrainBufs B) {
+    constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
+    __shared__ float xs[kTileRows * kIn];
+    __shared__ float os[kTileRows * 8];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WU, wu = wave % WU;
+    const int lr = lane & 15, lg = lane >> 4;
+    auto split = [](float v, __bf16& hi, __bf16& lo) {
+        hi = (__bf16)v;
+        lo = (__bf16)(v - (float)hi);
+    };
+    const __bf16 z16 = (__bf16)0.0f;
+    bf16x8 w1f[UJ];
 #pragma unroll
-        for (int j = 0; j < kOut; ++j) o[j] = P[kB5 + j];
-        const bf16x8* hr = reinterpret_cast<const bf16x8*>(h4 + b * kH);
-        for (int c = 0; c < kH / 8; ++c) {
-            const bf16x8 v = hr[c];
+    for (int j = 0; j < UJ; ++j) {
+        const float* w = P + kW1 + (16 * (UJ * wu + j) + lr) * kIn;
+        bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
+        __bf16 hi[kIn], lo[kIn];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float hv = (float)v[e];
+        for (int c = 0; c < kIn; ++c) split(w[c], hi[c], lo[c]);
 #pragma unroll
-                for (int j = 0; j < kOut; ++j) o[j] += w5[j * kH + 8 * c + e] * hv;
+        for (int c = 0; c < kIn; ++c) {
+            if (lg == 0) {
+                f[c] = hi[c];
+                f[4 + c] = hi[c];
+            } else if (lg == 1) {
+                f[c] = lo[c];
             }
         }
-        if (y) {
-#pragma unroll
-            for (int j = 0; j < kOut; ++j) y[b * kOut + j] = o[j];
-        }
-        if (t) {
-            const float* tr = t + (idx ? (int64_t)idx[b] : b) * 6;
-            const float cap = tr[0], m = tr[5];
-            const float sp = (o[0] > 0.0f) ? o[0] + log1pf(__expf(-o[0])) : log1pf(__expf(o[0]));
-            const float e1 = o[1] - tr[1], e2 = o[2] - tr[2], e3 = o[3] - tr[3], e4 = o[4] - tr[4];
-            l = kWCap * (sp - cap * o[0]) + kWLogR * e1 * e1 + kWG * e2 * e2 + kWPhi * m * (e3 * e3 + e4 * e4);
-            float* d = dout + b * kOut;
-            d[0] = kWCap * (sigmoidf_(o[0]) - cap) * inv_n;
-            d[1] = 2.0f * kWLogR * e1 * inv_n;
-            d[2] = 2.0f * kWG * e2 * inv_n;
-            d[3] = 2.0f * kWPhi * m * e3 * inv_n;
-            d[4] = 2.0f * kWPhi * m * e4 * inv_n;
-        }
+        w1f[j] = f;
     }
-    if (t && loss) {
-        red[threadIdx.x] = l;
+    auto init = [&](f32x4 (&acc)[RI][UJ], int64_t boff) {
+#pragma unroll
+        for (int j = 0; j < UJ; ++j) {
+            const f32x4 b = *reinterpret_cast<const f32x4*>(P + boff + 16 * (UJ * wu + j) + 4 * lg);
+#pragma unroll
+            for (int i = 0; i < RI; ++i) acc[i][j] = b;
+        }
+    };
+    // h = SiLU(z) into the activation buffer; SiLU'(z) and h to global
+    auto store = [&](const f32x4 (&acc)[RI][UJ], int layer, int64_t row0) {
+#pragma unroll
+        for (int j = 0; j < UJ; ++j) {
+            const int u = 16 * (UJ * wu + j) + 4 * lg;
+#pragma unroll
+            for (int i = 0; i < RI; ++i) {
+                const int r = 16 * (RI * wr + i) + lr;
+                const int64_t b = row0 + r;
+                bf16x4 v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float z = acc[i][j][e];
+                    const float sg = sigmoidf_(z);
+                    const float h = z * sg;
+                    v[e] = (__bf16)h;
+                    if (b < n) {
+                        B.sT[layer][(int64_t)(u + e) * B.ld + b] = (__bf16)(sg * (1.0f + z * (1.0f - sg)));
+                        B.hT[layer][(int64_t)(u + e) * B.ld + b] = (__bf16)h;
+                    }
+                }
+                *reinterpret_cast<bf16x4*>(act + r * kLdsStride + u) = v;
+            }
+        }
+    };
+    float lacc = 0.0f;
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * kTileRows;
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        for (int i = tid; i < kTileRows * kIn; i += NT) {
+            const int64_t b = row0 + i / kIn;
+            xs[i] = (b < n) ? x[(idx ? (int64_t)idx[b] : b) * kIn + i % kIn] : 0.0f;
+        }
+        __syncthreads();
+        {
+            f32x4 acc[RI][UJ];
+            init(acc, kB1);
+#pragma unroll
+            for (int i = 0; i < RI; ++i) {
+                const float* xr = xs + (16 * (RI * wr + i) + lr) * kIn;
+                bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
+                __bf16 hi[kIn], lo[kIn];
+#pragma unroll
+                for (int c = 0; c < kIn; ++c) split(xr[c], hi[c], lo[c]);
+#pragma unroll
+                for (int c = 0; c < kIn; ++c) {
+                    if (lg <= 1) f[c] = hi[c];
+                    if (lg == 0) f[4 + c] = lo[c];
+                }
+#pragma unroll
+                for (int j = 0; j < UJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, acc[i][j], 0, 0, 0);
+            }
+            store(acc, 0, row0);
+        }
+        __syncthreads();
+        for (int l = 0; l < 3; ++l) {
+            const __bf16* W = Wf + (int64_t)l * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
+            const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
+            f32x4 acc[RI][UJ];
+            init(acc, l == 0 ? kB2 : (l == 1 ? kB3 : kB4));
+#pragma unroll 1
+            for (int s = 0; s < kH / 32; ++s) {
+                const int k = 32 * s + 8 * lg;
+                bf16x8 af[UJ], bfg[RI];
+#pragma unroll
+                for (int j = 0; j < UJ; ++j) af[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + k);
+#pragma unroll
+                for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
+#pragma unroll
+                for (int i = 0; i < RI; ++i)
+#pragma unroll
+                    for (int j = 0; j < UJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
+            }
+            __syncthreads();
+            store(acc, l + 1, row0);
             __syncthreads();
         }
-        if (threadIdx.x == 0) atomicAdd(loss, red[0] * inv_n);
-    }
-}
-
-// Backward through the head: dz4 = (dout W5) * SiLU'(z4), plus dW5 += dout^T h4
-// and db5 += sum dout. Block of 256 threads (thread = hidden unit) over a
-// chunk of `per` samples.
-__global__ void __launch_bounds__(256) head_back(const float* __restrict__ dout, const __bf16* __restrict__ h4,
-                                                 const __bf16* __restrict__ z4, int64_t n, int per,
-                                                 const float* __restrict__ P, __bf16* __restrict__ dz4,
-                                                 __bf16* __restrict__ dz4T, int64_t ldT, float* __restrict__ G) {
-    const int u = threadIdx.x;
-    float w[kOut];
+        // output head (W5 as hi + lo BF16 parts) into os[row][0..4]
+        for (int rt = wave; rt < kTileRows / 16; rt += NT / 64) {
+            const __bf16* Wh = Wf + kW5SplitU + lr * kH;
+            const __bf16* A = act + (16 * rt + lr) * kLdsStride;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+            for (int s = 0; s < kH / 32; ++s) {
+                const int k = 32 * s + 8 * lg;
+                const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + k);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + k), hv, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + kW5Rows * kH + k), hv,
+                                                              acc, 0, 0, 0);
+            }
+            const int r = 16 * rt + lr;
+            if (lg == 0) {
 #pragma unroll
-    for (int j = 0; j < kOut; ++j) w[j] = P[kW5 + j * kH + u];
-    float gw[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    const int64_t b0 = (int64_t)blockIdx.x * per;
-    const int64_t b1 = std::min<int64_t>(n, b0 + per);
-    for (int64_t b = b0; b < b1; ++b) {
-        const float* d = dout + b * kOut;
-        float dh = 0.0f;
-        const float hv = (float)h4[b * kH + u];
-#pragma unroll
-        for (int j = 0; j < kOut; ++j) {
-            dh += d[j] * w[j];
-            gw[j] += d[j] * hv;
-            gb[j] += d[j];
+                for (int e = 0; e < 4; ++e) os[r * 8 + e] = acc[e] + P[kB5 + e];
+            } else if (lg == 1) {
+                os[r * 8 + 4] = acc[0] + P[kB5 + 4];
+            }
         }
-        const __bf16 dzv = (__bf16)(dh * silu_grad_((float)z4[b * kH + u]));
-        dz4[b * kH + u] = dzv;
-        dz4T[(int64_t)u * ldT + b] = dzv;
-    }
-#pragma unroll
-    for (int j = 0; j < kOut; ++j) atomicAdd(&G[kW5 + j * kH + u], gw[j]);
-    if (u == 0) {
-#pragma unroll
-        for (int j = 0; j < kOut; ++j) atomicAdd(&G[kB5 + j], gb[j]);
-    }
-}
-
-// Bias gradient of a hidden layer: db[u] = sum_b dz[u][b] over the feature-major copy.
-__global__ void __launch_bounds__(256) bias_grad(const __bf16* __restrict__ dzT, int64_t ldT, int64_t n,
-                                                 float* __restrict__ gb) {
-    __shared__ float red[256];
-    const int u = blockIdx.x;
-    float s = 0.0f;
-    for (int64_t b = threadIdx.x; b < n; b += 256) s += (float)dzT[(int64_t)u * ldT + b];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
+        // loss and dL/do, one thread per row
+        if (tid < kTileRows) {
+            const int64_t b = row0 + tid;
+            if (b < n) {
+                const float* o = os + tid * 8;
+                const float* tr = t + (idx ? (int64_t)idx[b] : b) * 6;
+                const float cap = tr[0], m = tr[5];
+                const float sp = (o[0] > 0.0f) ? o[0] + log1pf(__expf(-o[0])) : log1pf(__expf(o[0]));
+                const float e1 = o[1] - tr[1], e2 = o[2] - tr[2], e3 = o[3] - tr[3], e4 = o[4] - tr[4];
+                lacc += kWCap * (sp - cap * o[0]) + kWLogR * e1 * e1 + kWG * e2 * e2 + kWPhi * m * (e3 * e3 + e4 * e4);
+                float* d = B.dout + b * kOut;
+                d[0] = kWCap * (sigmoidf_(o[0]) - cap) * B.inv_n;
+                d[1] = 2.0f * kWLogR * e1 * B.inv_n;
+                d[2] = 2.0f * kWG * e2 * B.inv_n;
+                d[3] = 2.0f * kWPhi * m * e3 * B.inv_n;
+                d[4] = 2.0f * kWPhi * m * e4 * B.inv_n;
+            }
+        }
     }
-    if (threadIdx.x == 0) gb[u] = red[0];
+    if (tid < 64) {
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) lacc += __shfl_xor(lacc, d);
+        if (tid == 0) atomicAdd(B.loss, lacc * B.inv_n);
+    }
 }
 
-// dW1[u][c] = sum_b dz1[b][u] x[b][c] (inputs gathered through idx).
-__global__ void __launch_bounds__(256) in_layer_back(const __bf16* __restrict__ dz1, const float* __restrict__ x,
-                                                     const int32_t* __restrict__ idx, int64_t n, int per,
-                                                     float* __restrict__ G) {
-    const int u = threadIdx.x;
-    float g[kIn] = {0.f, 0.f, 0.f, 0.f};
-    const int64_t b0 = (int64_t)blockIdx.x * per;
-    const int64_t b1 = std::min<int64_t>(n, b0 + per);
-    for (int64_t b = b0; b < b1; ++b) {
-        const float d = (float)dz1[b * kH + u];
-        const float* xr = x + (idx ? (int64_t)idx[b] : b) * kIn;
+template <int RI, int UJ>
+__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
+train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t n, const float* __restrict__ P,
+          const __bf16* __restrict__ Wb, const TrainBufs B, float* __restrict__ G) {
+    constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
+    constexpr int PH = NT / kH, RPT = kTileRows / PH;  // column pass: row phases, rows per thread
+    static_assert(NT % kH == 0 && RPT % 8 == 0, "column pass shape");
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
+    __shared__ float xs[kTileRows * kIn];
+    __shared__ float ds[kTileRows * kOut];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WU, wu = wave % WU;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int cu = tid % kH, ch = tid / kH;  // column pass: unit, row phase
+    float w5[kOut], gw5[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb5[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < kIn; ++c) g[c] += d * xr[c];
+    for (int j = 0; j < kOut; ++j) w5[j] = P[kW5 + j * kH + cu];
+    float gb[4] = {0.f, 0.f, 0.f, 0.f}, gw1[kIn] = {0.f, 0.f, 0.f, 0.f};
+    // dz of layer L (1..4) for this thread's unit and rows: dh from the head
+    // (L = 4) or from the activation buffer, times SiLU'(z_L) saved by the
+    // forward kernel; stored to the buffer (for the next product) and, for
+    // L >= 2, feature-major to global
+    auto column = [&](int L, int64_t row0) {
+        const int rbeg = ch * RPT;
+        for (int q = 0; q < RPT / 8; ++q) {
+            const int r8 = rbeg + 8 * q;
+            const int64_t b8 = row0 + r8;
+            if (b8 >= n) break;  // n is a multiple of 32: groups of 8 rows are whole
+            const bf16x8 sv = *reinterpret_cast<const bf16x8*>(B.sT[L - 1] + (int64_t)cu * B.ld + b8);
+            bf16x8 hv{};
+            if (L == 4) hv = *reinterpret_cast<const bf16x8*>(B.hT[3] + (int64_t)cu * B.ld + b8);
+            bf16x8 out;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = r8 + e;
+                float dh;
+                if (L == 4) {
+                    dh = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < kOut; ++j) dh += ds[r * kOut + j] * w5[j];
+                } else {
+                    dh = (float)act[r * kLdsStride + cu];
+                }
+                const float dz = dh * (float)sv[e];
+                if (L == 4) {
+                    const float h = (float)hv[e];
+#pragma unroll
+                    for (int j = 0; j < kOut; ++j) {
+                        gw5[j] += ds[r * kOut + j] * h;
+                        gb5[j] += ds[r * kOut + j];
+                    }
+                }
+                gb[L - 1] += dz;
+                if (L == 1) {
+#pragma unroll
+                    for (int c = 0; c < kIn; ++c) gw1[c] += dz * xs[r * kIn + c];
+                }
+                const __bf16 dzb = (__bf16)dz;
+                out[e] = dzb;
+                act[r * kLdsStride + cu] = dzb;
+            }
+            if (L >= 2) *reinterpret_cast<bf16x8*>(B.dzT[L - 1] + (int64_t)cu * B.ld + b8) = out;
+        }
+    };
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * kTileRows;
+        __syncthreads();
+        for (int i = tid; i < kTileRows * kIn; i += NT) {
+            const int64_t b = row0 + i / kIn;
+            xs[i] = (b < n) ? x[(idx ? (int64_t)idx[b] : b) * kIn + i % kIn] : 0.0f;
+        }
+        for (int i = tid; i < kTileRows * kOut; i += NT) ds[i] = (row0 + i / kOut < n) ? B.dout[row0 * kOut + i] : 0.0f;
+        __syncthreads();
+        column(4, row0);
+        __syncthreads();
+        for (int l = 4; l >= 2; --l) {
+            // dh_{l-1}[row][i] = sum_o dz_l[row][o] W_l[o][i], A = W_l^T rows (Wb[i][o])
+            const __bf16* W = Wb + (int64_t)(l - 2) * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
+            const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
+            f32x4 acc[RI][UJ];
+#pragma unroll
+            for (int i = 0; i < RI; ++i)
+#pragma unroll
+                for (int j = 0; j < UJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+            for (int s = 0; s < kH / 32; ++s) {
+                const int k = 32 * s + 8 * lg;
+                bf16x8 af[UJ], bfg[RI];
+#pragma unroll
+                for (int j = 0; j < UJ; ++j) af[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + k);
+#pragma unroll
+                for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
+#pragma unroll
+                for (int i = 0; i < RI; ++i)
+#pragma unroll
+                    for (int j = 0; j < UJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < UJ; ++j) {
+                const int u = 16 * (UJ * wu + j) + 4 * lg;
+#pragma unroll
+                for (int i = 0; i < RI; ++i) {
+                    const bf16x4 v = {(__bf16)acc[i][j][0], (__bf16)acc[i][j][1], (__bf16)acc[i][j][2],
+                                      (__bf16)acc[i][j][3]};
+                    *reinterpret_cast<bf16x4*>(act + (16 * (RI * wr + i) + lr) * kLdsStride + u) = v;
+                }
+            }
+            __syncthreads();
+            column(l - 1, row0);
+            __syncthreads();
+        }
     }
+    const int64_t boff[4] = {kB1, kB2, kB3, kB4};
 #pragma unroll
-    for (int c = 0; c < kIn; ++c) atomicAdd(&G[kW1 + u * kIn + c], g[c]);
+    for (int L = 0; L < 4; ++L) atomicAdd(&G[boff[L] + cu], gb[L]);
+#pragma unroll
+    for (int c = 0; c < kIn; ++c) atomicAdd(&G[kW1 + cu * kIn + c], gw1[c]);
+#pragma unroll
+    for (int j = 0; j < kOut; ++j) atomicAdd(&G[kW5 + j * kH + cu], gw5[j]);
+    if (cu == 0) {
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) atomicAdd(&G[kB5 + j], gb5[j]);
+    }
+}
+
+// Partial dW_L over one row chunk: block (column group cg of 64 input units,
+// chunk, layer L - 2), 4 waves of 64 output units x 64 input units each.
+__global__ void __launch_bounds__(256) train_dw(const TrainBufs B, int64_t n, float* __restrict__ part) {
+    const int li = blockIdx.z, chunk = blockIdx.y, cg = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int64_t per = (((n + kDwChunks - 1) / kDwChunks) + 31) / 32 * 32;
+    const int64_t b0 = chunk * per, b1 = std::min<int64_t>(n, b0 + per);
+    const __bf16* dz = B.dzT[li + 1];  // dL/dz of layer li + 2
+    const __bf16* h = B.hT[li];        // h of layer li + 1
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t b = b0; b < b1; b += 32) {
+        const int64_t kk = b + 8 * lg;
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+            af[mi] = *reinterpret_cast<const bf16x8*>(dz + (int64_t)(16 * (4 * wave + mi) + lr) * B.ld + kk);
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+            bfr[ni] = *reinterpret_cast<const bf16x8*>(h + (int64_t)(64 * cg + 16 * ni + lr) * B.ld + kk);
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mi], bfr[ni], acc[mi][ni], 0, 0, 0);
+    }
+    // accumulator e of (mi, ni): output unit 16 (4 wave + mi) + 4 lg + e, input unit 64 cg + 16 ni + lr
+    float* out = part + (int64_t)(li * kDwChunks + chunk) * kH * kH;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                out[(int64_t)(16 * (4 * wave + mi) + 4 * lg + e) * kH + 64 * cg + 16 * ni + lr] = acc[mi][ni][e];
+}
+
+__global__ void __launch_bounds__(256) train_dw_reduce(const float* __restrict__ part, float* __restrict__ G) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * kH * kH; i += (int64_t)gridDim.x * blockDim.x) {
+        const int li = (int)(i / (kH * kH));
+        const int64_t e = i % (kH * kH);
+        float s = 0.0f;
+        for (int c = 0; c < kDwChunks; ++c) s += part[(int64_t)(li * kDwChunks + c) * kH * kH + e];
+        G[(li == 0 ? kW2 : (li == 1 ? kW3 : kW4)) + e] = s;
+    }
 }
 
 // ------------------------------------------------------------------ Adam
@@ -519,6 +643,10 @@ __global__ void __launch_bounds__(256) pack_weights(const float* __restrict__ P,
             const __bf16 hi = (__bf16)w;
             Wf[kW5Split + i] = hi;
             Wf[kW5Split + kW5Rows * kH + i] = (__bf16)(w - (float)hi);
+            const float wu = (o < kOut) ? P[kW5 + i] : 0.0f;
+            const __bf16 hu = (__bf16)wu;
+            Wf[kW5SplitU + i] = hu;
+            Wf[kW5SplitU + kW5Rows * kH + i] = (__bf16)(wu - (float)hu);
         }
         return;
     }
@@ -852,9 +980,11 @@ struct kgrt_mlp {
     float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr;
     __bf16 *Wf = nullptr, *Wb = nullptr;
     float* Pi = nullptr;  // scaled W1 and biases for inference
-    // activations / gradients, batch-major [B][256] unless named T (feature-major [256][B])
-    __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr, *dz2 = nullptr, *dzT = nullptr;
+    // training arrays, feature-major [256][max_batch] BF16: z[l] holds SiLU'(z_l),
+    // hT[l] and dz the activations h_l (l = 1..3) and h_4, h[l] the gradients dL/dz_l
+    __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr;
     float* dout = nullptr;
+    float* part = nullptr;  // weight-gradient partial sums [3][kDwChunks][256][256]
     int64_t step = 0;
     // render workspace (grown on demand): features, outputs, fallback list and its integration
     float *r_feat = nullptr, *r_pred = nullptr, *r_tab = nullptr;
@@ -884,36 +1014,6 @@ struct DevGuard {
     }
 };
 
-void launch_gemm(int epi, const GemmArgs& a, int64_t rows, int64_t ksplit, hipStream_t st) {
-    const dim3 grid((unsigned)((rows + 15) / 16), (unsigned)ksplit);
-    if (epi == EPI_FWD) hipLaunchKernelGGL(gemm_bt<EPI_FWD>, grid, dim3(256), 0, st, a);
-    else if (epi == EPI_BWD) hipLaunchKernelGGL(gemm_bt<EPI_BWD>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(gemm_bt<EPI_ATOMIC>, grid, dim3(256), 0, st, a);
-}
-
-// Forward pass over n <= max_batch samples. Training keeps pre-activations
-// and feature-major copies of the hidden layer inputs.
-void forward(kgrt_mlp* m, const float* x, const int32_t* idx, int64_t n, bool train, hipStream_t st) {
-    const int64_t ldT = m->max_batch;
-    hipLaunchKernelGGL(in_layer, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, x, idx, n, m->P, m->h[1],
-                       train ? m->z[1] : nullptr, train ? m->hT[1] : nullptr, ldT);
-    for (int l = 2; l <= 4; ++l) {
-        GemmArgs a{};
-        a.A = m->h[l - 1];
-        a.lda = kH;
-        a.Bt = m->Wf + (int64_t)(l - 2) * kH * kH;
-        a.ldb = kH;
-        a.rows = n;
-        a.klen = kH;
-        a.kend = kH;
-        a.bias = m->P + (l == 2 ? kB2 : (l == 3 ? kB3 : kB4));
-        a.h = m->h[l];
-        a.zsave = train ? m->z[l] : nullptr;
-        a.outT = (train && l < 4) ? m->hT[l] : nullptr;
-        a.ldT = ldT;
-        launch_gemm(EPI_FWD, a, n, 1, st);
-    }
-}
 
 }  // namespace
 
@@ -924,7 +1024,7 @@ int64_t kgrt_mlp_num_params(void) { return kNumParams; }
 int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
-    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Pi, m->dz, m->dz2, m->dzT, m->dout, m->r_feat, m->r_pred,
+    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Pi, m->part, m->dz, m->dout, m->r_feat, m->r_pred,
                     m->r_tab, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
                     m->h[1], m->h[2], m->h[3], m->h[4], m->z[1], m->z[2], m->z[3], m->z[4],
                     m->hT[1], m->hT[2], m->hT[3]};
@@ -950,11 +1050,11 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
               hipMalloc(&m->Wf, kWfSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Pi, kPiSize * sizeof(float)) == hipSuccess &&
               hipMalloc(&m->Wb, 3 * kH * kH * sizeof(__bf16)) == hipSuccess &&
-              hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess;
+              hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess &&
+              hipMalloc(&m->part, (size_t)3 * kDwChunks * kH * kH * 4) == hipSuccess;
     for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess && hipMalloc(&m->z[l], hb) == hipSuccess;
     for (int l = 1; ok && l <= 3; ++l) ok = hipMalloc(&m->hT[l], hb) == hipSuccess;
-    ok = ok && hipMalloc(&m->dz, hb) == hipSuccess && hipMalloc(&m->dz2, hb) == hipSuccess &&
-         hipMalloc(&m->dzT, hb) == hipSuccess;
+    ok = ok && hipMalloc(&m->dz, hb) == hipSuccess;
     if (!ok) {
         kgrt_mlp_destroy(m);
         return KGRT_E_NOMEM;
@@ -1021,53 +1121,30 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     const int64_t ldT = m->max_batch;
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, st, m->G, kNumParams, 0.0f);
     hipLaunchKernelGGL(fill_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1, 0.0f);
-    forward(m, x, idx, n, true, st);
-    hipLaunchKernelGGL(out_layer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m->h[4], n, m->P, nullptr, t,
-                       idx, m->dout, loss, 1.0f / (float)n);
-    // head: dz4 (batch-major in dz, feature-major in dzT), dW5, db5
-    const int per = 256;
-    hipLaunchKernelGGL(head_back, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, st, m->dout, m->h[4], m->z[4],
-                       n, per, m->P, m->dz, m->dzT, ldT, m->G);
-    __bf16* dzc = m->dz;   // dL/dz of the current layer, batch-major
-    __bf16* dzn = m->dz2;  // next (lower) layer's
-    for (int l = 4; l >= 2; --l) {
-        // dW_l[out][in] += sum_b dz_l[b][out] h_{l-1}[b][in]:  rows = out, A = dz_l^T, Bt = h_{l-1}^T
-        const int64_t kchunk = 4096;
-        const int64_t kpad = n;  // n is a multiple of 32
-        {
-            GemmArgs a{};
-            a.A = m->dzT;
-            a.lda = ldT;
-            a.Bt = m->hT[l - 1];
-            a.ldb = ldT;
-            a.rows = kH;
-            a.klen = std::min<int64_t>(kchunk, kpad);
-            a.kend = n;
-            a.acc_out = m->G + (l == 2 ? kW2 : (l == 3 ? kW3 : kW4));
-            launch_gemm(EPI_ATOMIC, a, kH, (kpad + a.klen - 1) / a.klen, st);
-        }
-        hipLaunchKernelGGL(bias_grad, dim3(kH), dim3(256), 0, st, m->dzT, ldT, n,
-                           m->G + (l == 2 ? kB2 : (l == 3 ? kB3 : kB4)));
-        // dL/dz_{l-1} = (dz_l W_l) * SiLU'(z_{l-1}):  rows = b, A = dz_l, Bt = W_l^T ([in][out])
-        GemmArgs a{};
-        a.A = dzc;
-        a.lda = kH;
-        a.Bt = m->Wb + (int64_t)(l - 2) * kH * kH;
-        a.ldb = kH;
-        a.rows = n;
-        a.klen = kH;
-        a.kend = kH;
-        a.zin = m->z[l - 1];
-        a.dz = dzn;
-        a.outT = m->dzT;  // overwritten after its last use above (stream order)
-        a.ldT = ldT;
-        launch_gemm(EPI_BWD, a, n, 1, st);
-        std::swap(dzc, dzn);
+    TrainBufs tb{};
+    for (int l = 0; l < 4; ++l) {
+        tb.sT[l] = m->z[l + 1];
+        tb.dzT[l] = m->h[l + 1];
     }
-    // input layer: dW1, db1
-    hipLaunchKernelGGL(in_layer_back, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, st, dzc, x, idx, n, per,
-                       m->G);
-    hipLaunchKernelGGL(bias_grad, dim3(kH), dim3(256), 0, st, m->dzT, ldT, n, m->G + kB1);
+    for (int l = 0; l < 3; ++l) tb.hT[l] = m->hT[l + 1];
+    tb.hT[3] = m->dz;
+    tb.ld = ldT;
+    tb.dout = m->dout;
+    tb.loss = loss;
+    tb.inv_n = 1.0f / (float)n;
+    int dev = 0, ncu = 256, pf = 1, pb = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    auto kf = train_fwd<kInferRI, kInferUJ>;
+    auto kb = train_bwd<kInferRI, kInferUJ>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pf, kf, kInferThreads, 0) != hipSuccess || pf < 1) pf = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pb, kb, kInferThreads, 0) != hipSuccess || pb < 1) pb = 1;
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    hipLaunchKernelGGL(kf, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pf)), dim3(kInferThreads), 0, st, x,
+                       idx, t, n, m->P, m->Wf, tb);
+    hipLaunchKernelGGL(kb, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pb)), dim3(kInferThreads), 0, st, x,
+                       idx, n, m->P, m->Wb, tb, m->G);
+    hipLaunchKernelGGL(train_dw, dim3(kH / 64, kDwChunks, 3), dim3(256), 0, st, tb, n, m->part);
+    hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
     if (grads && hipMemcpyAsync(grads, m->G, kNumParams * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return mlp_fail(m, KGRT_E_HIP, "gradient copy failed");
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
