@@ -238,11 +238,15 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
 //    sums over row chunks, added up by train_dw_reduce.
 constexpr int kDwChunks = 64;
 
+// Per-sample arrays of the training step are stored tile-major,
+// [B/64][256 units][64 rows] BF16: a tile's values for one unit are 128
+// contiguous bytes, and the whole tile is one 32 KB block.
+__device__ __forceinline__ int64_t tm_index(int u, int64_t b) { return (b >> 6) * (kH * 64) + u * 64 + (b & 63); }
+
 struct TrainBufs {
-    __bf16* sT[4];   // SiLU'(z) of layers 1..4, feature-major
-    __bf16* hT[4];   // h of layers 1..4, feature-major
-    __bf16* dzT[4];  // dL/dz of layers 1..4, feature-major (layers 2..4 used)
-    int64_t ld;      // leading dimension of the feature-major arrays
+    __bf16* sT[4];   // SiLU'(z) of layers 1..4
+    __bf16* hT[4];   // h of layers 1..4
+    __bf16* dzT[4];  // dL/dz of layers 1..4 (layers 2..4 used)
     float* dout;     // dL/do [B][5]
     float* loss;
     float inv_n;
@@ -310,8 +314,8 @@ train_fwd(const float* __restrict__ x, const int32_t* __restrict__ idx, const fl
                     const float h = z * sg;
                     v[e] = (__bf16)h;
                     if (b < n) {
-                        B.sT[layer][(int64_t)(u + e) * B.ld + b] = (__bf16)(sg * (1.0f + z * (1.0f - sg)));
-                        B.hT[layer][(int64_t)(u + e) * B.ld + b] = (__bf16)h;
+                        B.sT[layer][tm_index(u + e, b)] = (__bf16)(sg * (1.0f + z * (1.0f - sg)));
+                        B.hT[layer][tm_index(u + e, b)] = (__bf16)h;
                     }
                 }
                 *reinterpret_cast<bf16x4*>(act + r * kLdsStride + u) = v;
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdg
 train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t n, const float* __restrict__ P,
           const __bf16* __restrict__ Wb, const TrainBufs B, float* __restrict__ G) {
     constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
-    constexpr int PH = NT / kH, RPT = kTileRows / PH;  // column pass: row phases, rows per thread
+    constexpr int PH = NT / kH, RPT = kTileRows / PH;  // column pass: threads per unit, rows per thread
     static_assert(NT % kH == 0 && RPT % 8 == 0, "column pass shape");
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
     __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
@@ -436,7 +440,9 @@ train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t 
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WU, wu = wave % WU;
     const int lr = lane & 15, lg = lane >> 4;
-    const int cu = tid % kH, ch = tid / kH;  // column pass: unit, row phase
+    // column pass: lanes take adjacent units (adjacent LDS words; 128-byte rows of
+    // the tile-major arrays), the PH row blocks go to different waves
+    const int cu = tid % kH, ch = tid / kH;
     float w5[kOut], gw5[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb5[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < kOut; ++j) w5[j] = P[kW5 + j * kH + cu];
@@ -451,9 +457,9 @@ train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t 
             const int r8 = rbeg + 8 * q;
             const int64_t b8 = row0 + r8;
             if (b8 >= n) break;  // n is a multiple of 32: groups of 8 rows are whole
-            const bf16x8 sv = *reinterpret_cast<const bf16x8*>(B.sT[L - 1] + (int64_t)cu * B.ld + b8);
+            const bf16x8 sv = *reinterpret_cast<const bf16x8*>(B.sT[L - 1] + tm_index(cu, b8));
             bf16x8 hv{};
-            if (L == 4) hv = *reinterpret_cast<const bf16x8*>(B.hT[3] + (int64_t)cu * B.ld + b8);
+            if (L == 4) hv = *reinterpret_cast<const bf16x8*>(B.hT[3] + tm_index(cu, b8));
             bf16x8 out;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -484,7 +490,7 @@ train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t 
                 out[e] = dzb;
                 act[r * kLdsStride + cu] = dzb;
             }
-            if (L >= 2) *reinterpret_cast<bf16x8*>(B.dzT[L - 1] + (int64_t)cu * B.ld + b8) = out;
+            if (L >= 2) *reinterpret_cast<bf16x8*>(B.dzT[L - 1] + tm_index(cu, b8)) = out;
         }
     };
     const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
@@ -570,11 +576,9 @@ __global__ void __launch_bounds__(256) train_dw(const TrainBufs B, int64_t n, fl
         const int64_t kk = b + 8 * lg;
         bf16x8 af[4], bfr[4];
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
-            af[mi] = *reinterpret_cast<const bf16x8*>(dz + (int64_t)(16 * (4 * wave + mi) + lr) * B.ld + kk);
+        for (int mi = 0; mi < 4; ++mi) af[mi] = *reinterpret_cast<const bf16x8*>(dz + tm_index(16 * (4 * wave + mi) + lr, kk));
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
-            bfr[ni] = *reinterpret_cast<const bf16x8*>(h + (int64_t)(64 * cg + 16 * ni + lr) * B.ld + kk);
+        for (int ni = 0; ni < 4; ++ni) bfr[ni] = *reinterpret_cast<const bf16x8*>(h + tm_index(64 * cg + 16 * ni + lr, kk));
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -1044,7 +1048,7 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
     if (!m) return KGRT_E_NOMEM;
     m->device = dev;
     m->max_batch = max_batch;
-    const size_t hb = (size_t)max_batch * kH * sizeof(__bf16);
+    const size_t hb = (size_t)((max_batch + 63) / 64 * 64) * kH * sizeof(__bf16);  // whole 64-row tiles
     bool ok = hipMalloc(&m->P, kNumParams * 4) == hipSuccess && hipMalloc(&m->M, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->V, kNumParams * 4) == hipSuccess && hipMalloc(&m->G, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->Wf, kWfSize * sizeof(__bf16)) == hipSuccess &&
@@ -1118,7 +1122,6 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     if (!x || !t || !loss) return mlp_fail(m, KGRT_E_INVALID_ARG, "x, t and loss must be device pointers");
     DevGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
-    const int64_t ldT = m->max_batch;
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, st, m->G, kNumParams, 0.0f);
     hipLaunchKernelGGL(fill_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1, 0.0f);
     TrainBufs tb{};
@@ -1128,7 +1131,6 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     }
     for (int l = 0; l < 3; ++l) tb.hT[l] = m->hT[l + 1];
     tb.hT[3] = m->dz;
-    tb.ld = ldT;
     tb.dout = m->dout;
     tb.loss = loss;
     tb.inv_n = 1.0f / (float)n;
