@@ -2,8 +2,10 @@
 from __future__ import annotations
 
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -13,11 +15,18 @@ SOURCES = [os.path.join(CSRC, "kgrt.hip"), os.path.join(CSRC, "kgrt_mlp.hip")]
 HEADERS = [os.path.join(CSRC, "kgrt_device.hpp"), os.path.join(ROOT, "include", "kgrt.h")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
+
+# Per-source flags. The integrator keeps no loop-invariant values hoisted by
+# the machine-level LICM pass: in the persistent loop it hoisted 32-bit halves
+# of the FP64 polynomial constants into SGPRs, which then spilled to VGPR
+# lanes and came back through v_readlane on every step (measured on gfx950:
+# 591 -> 251 readlanes, 205 -> 134 VGPRs for the torus kernel).
+SOURCE_FLAGS = {"kgrt.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def hipcc() -> str:
@@ -34,12 +43,25 @@ def build(force: bool = True, verbose: bool = False, out: str = LIB, defines=())
         newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)
         if os.path.getmtime(out) >= newest:
             return out
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-D" + d for d in defines] + ["-o", tmp] + SOURCES
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    subprocess.check_call(cmd)
-    os.replace(tmp, out)
+    tmpdir = tempfile.mkdtemp(prefix="kgrt_build_")
+    try:
+        objs = []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            cmd = ([hipcc()] + HIPCC_FLAGS + SOURCE_FLAGS.get(os.path.basename(src), []) +
+                   ["-D" + d for d in defines] + ["-c", "-o", obj, src])
+            if verbose:
+                print(" ".join(cmd), file=sys.stderr)
+            subprocess.check_call(cmd)
+            objs.append(obj)
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        subprocess.check_call(cmd)
+        os.replace(tmp, out)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return out
 
 

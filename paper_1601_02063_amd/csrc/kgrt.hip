@@ -140,16 +140,16 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 }
 
 // Waves per SIMD the register allocation targets, per model and number of
-// frequencies carried (measured on MI355X; fewer waves give each one more of
-// the register file, which these FP64 kernels need more than extra waves to
-// hide latency: at three waves the one-frequency transfer kernel spilled
-// 144 B per lane and ran 14% slower, the eight-frequency one 2.8x slower; one
-// wave is 35% slower for eight frequencies and 11% slower for the thin disk).
+// frequencies carried (measured on MI355X, with the build's machine-LICM
+// setting for this file): the one-frequency transfer kernel (133 VGPRs) and the
+// thin disk (161) run fastest at three waves without spills; the
+// eight-frequency kernel (192 VGPRs) at two (three would spill, one wave is
+// 35% slower).
 #ifndef KGRT_WAVES_DISK
-#define KGRT_WAVES_DISK 2
+#define KGRT_WAVES_DISK 3
 #endif
 #ifndef KGRT_WAVES_TORUS
-#define KGRT_WAVES_TORUS 2
+#define KGRT_WAVES_TORUS 3
 #endif
 #ifndef KGRT_WAVES_TORUS_MULTI
 #define KGRT_WAVES_TORUS_MULTI 2
