@@ -33,10 +33,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # the accepted steps included. "calibrated": 64 x (ADD + MUL + TRANS + 2 FMA)
 # FP64 VALU instructions per attempt from rocprofv3 counters on a
 # divergence-free run (every lane traces the same ray), see
-# profiles/torus_flop_calibration.md. "formula": operation count of the
-# source with every divide, root and transcendental counted once.
-FLOPS_PER_ATTEMPT = {"torus": (1601.0, "calibrated"), "thin_disk": (620.0, "formula"),
-                     "projection": (620.0, "formula")}
+# profiles/trace_kernel_flop_calibration.md (the thin-disk figure, from three disk
+# rays, also serves the projection workload, which runs the same kernel).
+FLOPS_PER_ATTEMPT = {"torus": (1601.0, "calibrated"), "thin_disk": (995.0, "calibrated"),
+                     "projection": (995.0, "calibrated")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
@@ -58,6 +58,10 @@ CALIBRATION_RAYS = {
     "captured": (0.94, 17.0, 1.5, 2.0),
     "escaping": (0.94, 17.0, 7.0, -5.0),
     "far": (0.94, 17.0, 18.0, 15.0),
+    # thin disk (a = 0.9, incl 60 deg, as the 64x64 disk image): a disk hit, a far ray, a captured ray
+    "disk_hit": (0.9, 60.0, 6.0, 3.0),
+    "disk_far": (0.9, 60.0, 14.0, 12.0),
+    "disk_captured": (0.9, 60.0, 0.5, 0.5),
 }
 
 
@@ -447,17 +451,22 @@ def calibrate(ctx, which: str, dev, nfreq: int = 1):
 
     from paper_1601_02063_amd import kgrt as K
     from paper_1601_02063_amd import scenes
-    w = scenes.torus_image(16, freqs=(230e9,) if nfreq == 1 else scenes.batch_frequencies())
+    if which.startswith("disk_"):
+        w = scenes.thin_disk_image(16)
+    else:
+        w = scenes.torus_image(16, freqs=(230e9,) if nfreq == 1 else scenes.batch_frequencies())
     mod, freqs, integ = K.Model(**w["model"]), list(w["freqs"]), K.Integrator(**w["integ"])
     nrays = 256 * 1024
     ray = torch.tensor(CALIBRATION_RAYS[which], dtype=torch.float64, device=dev)
     rays = ray.repeat(nrays, 1).contiguous()
-    out = K.alloc_outputs(nrays, mod, len(freqs), dev, names=("status", "steps", "attempts", "intensity", "tau"))
+    out = K.alloc_outputs(nrays, mod, len(freqs), dev, names=("status", "steps", "attempts", "intensity", "tau",
+                                                              "r_cross", "g"))
     ctx.trace_rays(rays, mod, freqs, integ, out)
     torch.cuda.synchronize()
     att = out["attempts"]
     assert int(att.min()) == int(att.max()), "copies of one ray must take identical step sequences"
     print(json.dumps({"calibration_ray": which, "nfreq": len(freqs), "ray": CALIBRATION_RAYS[which], "rays": nrays,
+                      "status": int(out["status"][0]),
                       "attempts_per_ray": int(att[0]), "steps_per_ray": int(out["steps"][0]),
                       "total_attempts": int(att.to(torch.int64).sum())}), flush=True)
 
