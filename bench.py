@@ -10,9 +10,17 @@ outputs resident in HBM.
 Metric: ns per photon per accepted RK step = kernel time / sum of accepted
 steps over the image (the paper's Table 1 quantity T/S).
 
-Prints ONE JSON line. Extra modes:
+Prints ONE JSON line. Other workloads (--workload):
+  thin_disk, projection   the 64x64 thin-disk image; the first-crossing projection
+  batch                   256 uneven torus images, 8 frequencies, one graph-replayed plan
+  train                   surrogate training on integrator-labelled rays (writes a checkpoint)
+  infer                   the fused surrogate network alone, 2^24 samples
+  render                  64 surrogate+fallback thin-disk images of 2048^2 vs the integrator
+  table1                  the paper's Table 1 sweep (projection, N = 2 ... 2048)
+Extra modes:
   --calibrate RAY   trace copies of one ray (no divergence) so a rocprofv3
                     --pmc run can count FP64 VALU instructions per step.
+  --copy-probe      one plain 1 GiB device copy (scales HBM byte counters).
 """
 from __future__ import annotations
 
@@ -42,6 +50,11 @@ FLOPS_PER_ATTEMPT = {"torus": (1601.0, "calibrated"), "thin_disk": (995.0, "cali
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
 # profiles/torus_1024_hbm_traffic.md. Valid only for the kernel sources they
 # were taken on (md5 of csrc/kgrt.hip + csrc/kgrt_device.hpp); null otherwise.
+# VALU lane utilisation of the dominant kernel on the 1024^2 torus image (useful
+# FP64 FLOPs / FP64 lane slots issued, rocprofv3 counters), valid for the sources it
+# was taken on; see profiles/trace_kernel_flop_calibration.md.
+LANE_UTILISATION = {"torus": {"value": 0.870, "source_md5": "c359a774629592a72747cf2a76cb81a3"}}
+
 TRAFFIC = {"torus": {"bytes": 503210105, "source_md5": "c359a774629592a72747cf2a76cb81a3"}}
 
 
@@ -98,9 +111,17 @@ def cpu_baseline(w, nsample: int, seed: int = 2024):
     res = O.trace_points(sc, xy, threads)
     dt = time.perf_counter() - t0
     steps = int(res["steps"].astype(np.int64).sum())
+    # one thread on every threads-th pixel of the same sample
+    sub = xy[::max(threads, 1)]
+    t1 = time.perf_counter()
+    res1 = O.trace_points(sc, sub, 1)
+    dt1 = time.perf_counter() - t1
+    steps1 = int(res1["steps"].astype(np.int64).sum())
     return {"value": dt / steps * 1e9, "unit": "ns/photon/RK step", "cores": threads, "kind": "oracle",
+            "single_thread_value": dt1 / steps1 * 1e9,
             "sample": f"{len(idx)} seeded pixels (seed {seed}) of the same image, {steps} accepted steps, "
-                      f"{dt:.2f} s wall on {threads} threads ({platform.processor() or platform.machine()})"}
+                      f"{dt:.2f} s wall on {threads} threads ({platform.processor() or platform.machine()}); "
+                      f"single thread: every {max(threads, 1)}th of them, {steps1} steps, {dt1:.2f} s"}
 
 
 def main():
@@ -109,7 +130,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus",
-                    choices=["torus", "thin_disk", "projection", "batch", "train", "infer", "render"])
+                    choices=["torus", "thin_disk", "projection", "batch", "train", "infer", "render", "table1"])
     ap.add_argument("--train-rays", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--ckpt", default=None,
@@ -124,7 +145,8 @@ def main():
     ap.add_argument("--baselines", action="store_true", help="batch: also time per-image launches")
     ap.add_argument("--nfreq", type=int, default=1, help="calibration: number of frequencies (1 or 8)")
     ap.add_argument("--n", type=int, default=None, help="image side (default per workload)")
-    ap.add_argument("--cpu-sample", type=int, default=40000, help="pixels in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=400000,
+                    help="pixels in the CPU-oracle sample (0 = skip); about 10 s of oracle work on 16 cores")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)
@@ -170,6 +192,9 @@ def main():
     if args.workload == "infer":
         bench_infer(ctx, args, dev)
         return
+    if args.workload == "table1":
+        bench_table1(ctx, args, dev)
+        return
     if args.workload == "render":
         bench_render(ctx, args, dev)
         return
@@ -205,6 +230,9 @@ def main():
     achieved = fpa * attempts / (ms_mean * 1e-3) / 1e12
     tr = TRAFFIC.get(args.workload)
     traffic = tr["bytes"] if (tr and args.n in (None, 1024) and tr["source_md5"] == kernel_source_md5()) else None
+    lu = LANE_UTILISATION.get(args.workload)
+    lane_util = lu["value"] if (lu and args.n in (None, 1024) and lu["source_md5"] == kernel_source_md5()) else None
+    kinfo = ctx.kernel_info(mod.kind, max(len(freqs), 1), args.block or 256)
     line = {
         "metric": METRIC,
         "value": round(ns_per_step, 6),
@@ -228,7 +256,10 @@ def main():
         "accepted_steps": steps,
         "attempted_steps": attempts,
         "steps_per_ray": round(steps / n, 2),
+        "ns_per_attempted_step": round(ms_mean * 1e6 / attempts, 6),
+        "ns_per_rhs_eval": round(ms_mean * 1e6 / (6 * attempts), 6),
         "captured_frac": round(float(((st & 1) != 0).float().mean()), 5),
+        "kernel": dict(kinfo, lane_utilisation=lane_util),
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": traffic,
                      "flops_per_attempt": fpa, "flops_basis": basis,
@@ -338,6 +369,41 @@ def bench_train(ctx, args, dev):
                          "flops_per_sample": MLP_TRAIN_MFMA_FLOPS, "kernel": "256x256 layers (fwd+dgrad+wgrad)"}}
     mlp.close()
     print(json.dumps(line), flush=True)
+
+
+def bench_table1(ctx, args, dev):
+    """The paper's Table 1 measurement on MI355X: first-crossing projection images (a = 0.95,
+    incl 60 deg, observer 1000 M, +-15 M, rtol 1e-8) of N x N pixels, N = 2 ... 2048; run time T of
+    one launch (after a warm-up, median of args.steps), total accepted RK steps S, and T/S."""
+    import torch
+
+    from paper_1601_02063_amd import kgrt as K
+    from paper_1601_02063_amd import scenes
+    stream = torch.cuda.current_stream()
+    rows = []
+    for p in range(1, 12):
+        N = 2 ** p
+        w = scenes.projection_image(N)
+        cam, mod, integ = K.Camera(**w["camera"]), K.Model(**w["model"]), K.Integrator(**w["integ"])
+        out = K.alloc_outputs(N * N, mod, 0, dev, names=("status", "steps", "attempts", "r_cross", "g"))
+        ctx.trace(cam, mod, [], integ, out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(3, args.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.trace(cam, mod, [], integ, out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        T = sorted(ts)[len(ts) // 2]
+        S = int(out["steps"].to(torch.int64).sum())
+        rows.append({"N": N, "T_ms": round(T, 4), "S": S, "steps_per_photon": round(S / (N * N), 1),
+                     "ns_per_photon_step": round(T * 1e6 / S, 5), "photon_steps_per_s": round(S / (T * 1e-3), 1)})
+        print(json.dumps({"table1_row": rows[-1]}), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "Table 1 analogue: ns per photon per RK step (T/S), projection a=0.95 incl 60",
+                      "unit": "ns/photon/RK step", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+                      "data": "synthetic", "rows": rows}), flush=True)
 
 
 MLP_INFER_MFMA_FLOPS = 3 * 2 * 256 * 256  # per sample: the three 256x256 layers

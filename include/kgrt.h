@@ -144,6 +144,16 @@ int kgrt_ctx_set_launch(kgrt_ctx* ctx, const kgrt_launch* launch);
 /* Number of compute units of the context's device. */
 int kgrt_ctx_num_cus(const kgrt_ctx* ctx);
 
+/* Launch facts of the integrator kernel the library would run for `model`
+ * and `nfreq` (torus: 1..16; others: ignored) at `block` threads per block
+ * (64, 128 or 256; 0 = 256), as the runtime reports them for the compiled
+ * code: VGPRs per lane, scratch (spill) bytes per lane, resident blocks per
+ * compute unit and the resulting waves per SIMD. */
+typedef struct kgrt_kernel_info {
+    int32_t vgprs, scratch_bytes, blocks_per_cu, waves_per_simd;
+} kgrt_kernel_info;
+int kgrt_kernel_info_get(kgrt_ctx* ctx, int32_t model, int32_t nfreq, int32_t block, kgrt_kernel_info* out);
+
 /* Validates a request without touching a GPU (the trace calls run the same
  * checks first). cam may be NULL (ray-list mode), freqs_hz is a host array. */
 int kgrt_check_args(const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,

@@ -634,6 +634,20 @@ int dispatch(kgrt_ctx* ctx, const KParams& P, hipStream_t st) {
     return dispatch_env(ctx, env, P, st);
 }
 
+template <int MODEL, int NF>
+int kernel_info(int block, kgrt_kernel_info* out) {
+    auto kern = trace_kernel<MODEL, NF>;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void*)kern) != hipSuccess) return KGRT_E_HIP;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess) return KGRT_E_HIP;
+    out->vgprs = fa.numRegs;
+    out->scratch_bytes = (int32_t)fa.localSizeBytes;
+    out->blocks_per_cu = per_cu;
+    out->waves_per_simd = per_cu * (block / 64) / 4;  // four SIMDs per compute unit
+    return KGRT_OK;
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -665,6 +679,24 @@ const char* kgrt_strerror(int code) {
 }
 
 const char* kgrt_last_error(const kgrt_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int kgrt_kernel_info_get(kgrt_ctx* ctx, int32_t model, int32_t nfreq, int32_t block, kgrt_kernel_info* out) {
+    if (!ctx || !out) return KGRT_E_INVALID_ARG;
+    if (block == 0) block = 256;
+    if (block != 64 && block != 128 && block != 256) return fail(ctx, KGRT_E_INVALID_ARG, "block must be 64, 128 or 256");
+    if (model < KGRT_MODEL_GEODESIC || model > KGRT_MODEL_TORUS) return fail(ctx, KGRT_E_INVALID_ARG, "unknown model");
+    if (model == KGRT_MODEL_TORUS && (nfreq < 1 || nfreq > 16)) return fail(ctx, KGRT_E_INVALID_ARG, "nfreq must be 1..16");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    int rc;
+    if (model != KGRT_MODEL_TORUS) rc = kernel_info<KGRT_MODEL_THIN_DISK, 1>(block, out);
+    else if (nfreq <= 1) rc = kernel_info<KGRT_MODEL_TORUS, 1>(block, out);
+    else if (nfreq <= 2) rc = kernel_info<KGRT_MODEL_TORUS, 2>(block, out);
+    else if (nfreq <= 4) rc = kernel_info<KGRT_MODEL_TORUS, 4>(block, out);
+    else if (nfreq <= 8) rc = kernel_info<KGRT_MODEL_TORUS, 8>(block, out);
+    else rc = kernel_info<KGRT_MODEL_TORUS, 16>(block, out);
+    return rc == KGRT_OK ? KGRT_OK : fail(ctx, rc, "kernel attribute query failed");
+}
 
 int kgrt_check_args(const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz, int32_t nfreq,
                     const kgrt_integrator* integ) {

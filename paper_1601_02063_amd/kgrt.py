@@ -66,6 +66,11 @@ class CLaunch(ctypes.Structure):
                 "mode": self.mode}
 
 
+class CKernelInfo(ctypes.Structure):
+    _fields_ = [("vgprs", ctypes.c_int32), ("scratch_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("waves_per_simd", ctypes.c_int32)]
+
+
 class CAdam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
@@ -149,6 +154,9 @@ def lib() -> ctypes.CDLL:
         L.kgrt_ctx_destroy.argtypes, L.kgrt_ctx_destroy.restype = [vp], ctypes.c_int
         L.kgrt_ctx_set_launch.argtypes, L.kgrt_ctx_set_launch.restype = [vp, P(CLaunch)], ctypes.c_int
         L.kgrt_ctx_num_cus.argtypes, L.kgrt_ctx_num_cus.restype = [vp], ctypes.c_int
+        L.kgrt_kernel_info_get.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(CKernelInfo)]
+        L.kgrt_kernel_info_get.restype = ctypes.c_int
         L.kgrt_check_args.argtypes = [P(CCamera), P(CModel), P(d), i32, P(CIntegrator)]
         L.kgrt_check_args.restype = ctypes.c_int
         L.kgrt_trace.argtypes = [vp, P(CCamera), P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
@@ -250,6 +258,14 @@ class Context:
     @property
     def num_cus(self) -> int:
         return lib().kgrt_ctx_num_cus(self._h)
+
+    def kernel_info(self, model: int, nfreq: int = 1, block: int = 0) -> dict:
+        """kgrt_kernel_info_get: VGPRs, scratch bytes per lane, blocks per CU and waves per SIMD of the
+        integrator kernel for this model and number of frequencies."""
+        info = CKernelInfo()
+        self._check(lib().kgrt_kernel_info_get(self._h, model, nfreq, block, ctypes.byref(info)))
+        return {"vgprs": info.vgprs, "scratch_bytes": info.scratch_bytes, "blocks_per_cu": info.blocks_per_cu,
+                "waves_per_simd": info.waves_per_simd}
 
     def set_launch(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0, mode: int = 0):
         self._check(lib().kgrt_ctx_set_launch(self._h, ctypes.byref(CLaunch(block, blocks_per_cu, refill_min, mode))))

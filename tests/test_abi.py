@@ -44,10 +44,10 @@ def test_struct_layout_matches_header(K):
 #define P(T) printf(#T " %zu\n", sizeof(T));
 #define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
-  P(kgrt_camera) P(kgrt_model) P(kgrt_integrator) P(kgrt_outputs) P(kgrt_launch) P(kgrt_adam) P(kgrt_fallback)
+  P(kgrt_camera) P(kgrt_model) P(kgrt_integrator) P(kgrt_outputs) P(kgrt_launch) P(kgrt_adam) P(kgrt_fallback) P(kgrt_kernel_info)
   F(kgrt_camera, nx) F(kgrt_camera, x_min) F(kgrt_camera, y_max)
   F(kgrt_model, r_in) F(kgrt_model, r_emit_max) F(kgrt_integrator, max_steps) F(kgrt_integrator, flags)
-  F(kgrt_outputs, tau) F(kgrt_launch, refill_min) F(kgrt_adam, eps) F(kgrt_fallback, grad_max)
+  F(kgrt_outputs, tau) F(kgrt_launch, refill_min) F(kgrt_adam, eps) F(kgrt_fallback, grad_max) F(kgrt_kernel_info, waves_per_simd)
   return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
@@ -60,7 +60,7 @@ int main(void) {
         "kgrt_camera": ctypes.sizeof(K.CCamera), "kgrt_model": ctypes.sizeof(K.CModel),
         "kgrt_integrator": ctypes.sizeof(K.CIntegrator), "kgrt_outputs": ctypes.sizeof(K.COutputs),
         "kgrt_launch": ctypes.sizeof(K.CLaunch), "kgrt_adam": ctypes.sizeof(K.CAdam),
-        "kgrt_fallback": ctypes.sizeof(K.CFallback),
+        "kgrt_fallback": ctypes.sizeof(K.CFallback), "kgrt_kernel_info": ctypes.sizeof(K.CKernelInfo),
         "kgrt_camera.nx": K.CCamera.nx.offset, "kgrt_camera.x_min": K.CCamera.x_min.offset,
         "kgrt_camera.y_max": K.CCamera.y_max.offset, "kgrt_model.r_in": K.CModel.r_in.offset,
         "kgrt_model.r_emit_max": K.CModel.r_emit_max.offset,
@@ -68,6 +68,7 @@ int main(void) {
         "kgrt_integrator.flags": K.CIntegrator.flags.offset, "kgrt_outputs.tau": K.COutputs.tau.offset,
         "kgrt_launch.refill_min": K.CLaunch.refill_min.offset, "kgrt_adam.eps": K.CAdam.eps.offset,
         "kgrt_fallback.grad_max": K.CFallback.grad_max.offset,
+        "kgrt_kernel_info.waves_per_simd": K.CKernelInfo.waves_per_simd.offset,
     }
     for k, v in want.items():
         assert int(got[k]) == v, k
