@@ -86,7 +86,7 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
     constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
     static_assert(kTileRows % (16 * RI) == 0 && kH % (16 * UJ) == 0, "tile shape");
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-    __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
+    __shared__ __align__(16) __bf16 actbuf[2][kTileRows * kLdsStride];  // ping-pong between layers
     __shared__ float xs[kTileRows * kIn];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -128,8 +128,8 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
             for (int i = 0; i < RI; ++i) acc[i][j] = b;
         }
     };
-    // ht = zt / (1 + 2^zt) of one layer into the activation buffer
-    auto store = [&](const f32x4 (&acc)[RI][UJ]) {
+    // ht = zt / (1 + 2^zt) of one layer into activation buffer `act`
+    auto store = [&](const f32x4 (&acc)[RI][UJ], __bf16* act) {
 #pragma unroll
         for (int j = 0; j < UJ; ++j) {
             const int u = 16 * (UJ * wu + j) + 4 * lg;
@@ -171,11 +171,12 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
                 for (int j = 0; j < UJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, acc[i][j], 0, 0, 0);
             }
-            store(acc);
+            store(acc, actbuf[0]);
         }
         __syncthreads();
-        // hidden layers 2..4 on MFMA, in place
+        // hidden layers 2..4 on MFMA, from buffer l % 2 into the other
         for (int l = 0; l < 3; ++l) {
+            const __bf16* act = actbuf[l & 1];
             const __bf16* W = Wf + (int64_t)l * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
             const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
             f32x4 acc[RI][UJ];
@@ -194,10 +195,10 @@ mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict_
                     for (int j = 0; j < UJ; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
             }
-            __syncthreads();  // every wave has read this layer's input
-            store(acc);
+            store(acc, actbuf[(l + 1) & 1]);
             __syncthreads();
         }
+        const __bf16* act = actbuf[1];
         // output head: row tile rt, outputs 0..15 (5 used), hi and lo parts of W5
         for (int rt = wave; rt < kTileRows / 16; rt += NT / 64) {
             const __bf16* Wh = Wf + kW5Split + lr * kH;

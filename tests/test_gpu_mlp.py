@@ -94,6 +94,34 @@ def test_gradients_match_reference(ctx):
     mlp.close()
 
 
+def test_gradients_partial_tile_no_gather(ctx):
+    """n = 96 rows: one whole 64-row tile and half of another, no index gather."""
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(9)
+    rng = np.random.Generator(np.random.PCG64(12))
+    n = 96
+    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    t = np.zeros((n, 6), dtype=np.float32)
+    t[:, 0] = rng.integers(0, 2, n)
+    t[:, 1:5] = rng.normal(size=(n, 4))
+    t[:, 5] = rng.integers(0, 2, n)
+    mlp = K.Mlp(ctx, max_batch=112)  # not a multiple of 64 either
+    mlp.set_params(p)
+    loss, g = mlp.loss_grads(torch.from_numpy(x).to(ctx.device), torch.from_numpy(t).to(ctx.device))
+    torch.cuda.synchronize()
+    lref, gref = M.loss_and_grads(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert abs(float(loss) - lref) <= REL * abs(lref)
+    g = g.cpu().numpy()
+    k = 0
+    for li, (i, o) in enumerate(M.LAYERS):
+        for name, size in (("W", i * o), ("b", o)):
+            e = rel_fro(g[k:k + size], gref[k:k + size])
+            assert e <= REL, (li + 1, name, e)
+            k += size
+    mlp.close()
+
+
 def test_features_and_targets_kernels(ctx):
     import torch
     from paper_1601_02063_amd import kgrt as K
