@@ -185,9 +185,11 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
     int32_t rit = 0;
     double hs = 0.0;
     State yk{};
-    double tau[NF], Iacc[NF], ap[NF], ep[NF];
+    // per frequency: optical depth, intensity, attenuation e^-tau (carried as a
+    // product of the steps' e^-dtau), coefficients at the last accepted point
+    double tau[NF], Iacc[NF], att[NF], ap[NF], ep[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) tau[f] = Iacc[f] = ap[f] = ep[f] = 0.0;
+    for (int f = 0; f < NF; ++f) tau[f] = Iacc[f] = ap[f] = ep[f] = 0.0, att[f] = 1.0;
     const Outputs O = P.out;
     const int nf = P.nf;
     const int64_t nall = P.nrays;
@@ -237,6 +239,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                                 for (int f = 0; f < NF; ++f) {
                                     tau[f] = 0.0;
                                     Iacc[f] = 0.0;
+                                    att[f] = 1.0;
                                     if (f < nf)
                                         torus_coeffs(q, P.torus, g0, ig0, P.freqs[f], P.inv_freqs[f], ap[f], ep[f]);
                                 }
@@ -365,9 +368,11 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                                 double a1, e1;
                                 torus_coeffs(q, P.torus, g1, ig1, P.freqs[f], P.inv_freqs[f], a1, e1);
                                 const double dtau = hdone * (ap[f] + a1) / 2.0;
-                                const double phi = (dtau > 0.0) ? -fm::expm1(-dtau) * fm::rcp(dtau) : 1.0;
-                                Iacc[f] += fm::exp(-tau[f]) * hdone * (ep[f] + e1) / 2.0 * phi;
+                                const double em = fm::expm1(-dtau);  // e^-dtau - 1
+                                const double phi = (dtau > 0.0) ? -em * fm::rcp(dtau) : 1.0;
+                                Iacc[f] += att[f] * hdone * (ep[f] + e1) / 2.0 * phi;
                                 tau[f] += dtau;
+                                att[f] += att[f] * em;
                                 ap[f] = a1;
                                 ep[f] = e1;
                             }

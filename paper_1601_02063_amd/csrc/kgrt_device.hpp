@@ -181,18 +181,26 @@ __host__ __device__ __forceinline__ double log(double x) {
     return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, lm));
 }
 
+// y^N by repeated squaring (4 multiplications for N = 12, 2 for 4, 3 for 5).
+template <int N>
+__device__ __forceinline__ double ipow(double y) {
+    if constexpr (N == 1) {
+        return y;
+    } else if constexpr (N % 2 == 0) {
+        const double h = ipow<N / 2>(y);
+        return h * h;
+    } else {
+        return ipow<N - 1>(y) * y;
+    }
+}
+
 // x^(-1/N) for 1e-30 <= x <= 1e30.
 template <int N>
 __device__ __forceinline__ double inv_root(double x) {
     const float xf = (float)x;
     double y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(xf) * (1.0f / N));
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double yn = y;
-#pragma unroll
-        for (int k = 1; k < N; ++k) yn *= y;
-        y = fma(y * (1.0 / N), fma(-x, yn, 1.0), y);
-    }
+    for (int it = 0; it < 2; ++it) y = fma(y * (1.0 / N), fma(-x, ipow<N>(y), 1.0), y);
     return y;
 }
 
