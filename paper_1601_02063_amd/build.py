@@ -26,7 +26,14 @@ HIPCC_FLAGS = [
 # of the FP64 polynomial constants into SGPRs, which then spilled to VGPR
 # lanes and came back through v_readlane on every step (measured on gfx950:
 # 591 -> 251 readlanes, 205 -> 134 VGPRs for the torus kernel).
-SOURCE_FLAGS = {"kgrt.hip": ["-mllvm", "-disable-machine-licm"]}
+#
+# It is also built without the accumulating v_fmac_f64 form, so an FP64 fused
+# multiply-add whose addend is a constant reads it from an SGPR pair (set by
+# scalar moves, which issue beside the vector ALU) instead of first copying it
+# into the destination VGPRs with two vector moves: each Horner step of the
+# polynomial approximations cost three vector instructions instead of one
+# (static vector moves in the torus kernel 409 -> 183).
+SOURCE_FLAGS = {"kgrt.hip": ["-mllvm", "-disable-machine-licm", "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst"]}
 
 
 def hipcc() -> str:

@@ -116,6 +116,22 @@ constexpr int kRecFields = 10;
 
 // ------------------------------------------------------------ kernels
 
+// The kernel's first argument (KParams: explicit kernel arguments start the
+// kernarg segment, in order), read again with scalar loads where it is used.
+// The torus and frequency parameters of the transfer are uniform values that
+// the compiler would otherwise load once and keep across the persistent loop;
+// with the SGPRs that loop needs they do not fit, so they would be parked in
+// VGPR lanes and restored with one v_readlane (a vector instruction) per 32
+// bits at every accepted step. The empty asm makes the pointer opaque, so the
+// loads cannot be hoisted out of the loop; they stay scalar loads from the
+// constant address space.
+__device__ __forceinline__ const KParams& reread_params() {
+    typedef const __attribute__((address_space(4))) KParams CK;
+    CK* p = (CK*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const KParams*)p;
+}
+
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
 
 // One thread per ray of the chunk [base, base + count): ray start (section 2.2).
@@ -234,14 +250,15 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                             if (MODEL == KGRT_MODEL_TORUS) {
                                 const double g0 = redshift_sc(y.r, sy, cy, a, a2, -L);
                                 const double ig0 = fm::rcp(g0);
-                                const Plasma q = torus_plasma(P.torus, y.r, cy, r_cap);
+                                const KParams& PR = reread_params();
+                                const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
 #pragma unroll
                                 for (int f = 0; f < NF; ++f) {
                                     tau[f] = 0.0;
                                     Iacc[f] = 0.0;
                                     att[f] = 1.0;
                                     if (f < nf)
-                                        torus_coeffs(q, P.torus, g0, ig0, P.freqs[f], P.inv_freqs[f], ap[f], ep[f]);
+                                        torus_coeffs(q, PR.torus, g0, ig0, PR.freqs[f], PR.inv_freqs[f], ap[f], ep[f]);
                                 }
                             }
                         } else {
@@ -361,12 +378,13 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         // each accepted endpoint, exponential-trapezoid increment
                         const double g1 = redshift_sc(y.r, sy, cy, a, a2, -L);
                         const double ig1 = fm::rcp(g1);
-                        const Plasma q = torus_plasma(P.torus, y.r, cy, r_cap);
+                        const KParams& PR = reread_params();
+                        const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
 #pragma unroll
                         for (int f = 0; f < NF; ++f) {
                             if (f < nf) {
                                 double a1, e1;
-                                torus_coeffs(q, P.torus, g1, ig1, P.freqs[f], P.inv_freqs[f], a1, e1);
+                                torus_coeffs(q, PR.torus, g1, ig1, PR.freqs[f], PR.inv_freqs[f], a1, e1);
                                 const double dtau = hdone * (ap[f] + a1) / 2.0;
                                 const double em = fm::expm1(-dtau);  // e^-dtau - 1
                                 const double phi = (dtau > 0.0) ? -em * fm::rcp(dtau) : 1.0;
@@ -553,6 +571,7 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     T.r_emit_max = m->r_emit_max;
     T.cB = 8.0 * kPi * T.eps_B * kMp * kC * kC / 6.0;
     T.cTheta = kKb * T.T0 / (kMe * kC * kC);
+    T.cInvTheta = (T.T0 > 0.0) ? 1.0 / T.cTheta : 0.0;
     T.cNu = 3.0 * kQe / (4.0 * kPi * kMe * kC);
     T.cJ = kQe * kQe / (1.7320508075688772 * kC);
     T.cH = (T.T0 > 0.0) ? kH / (kKb * T.T0) : 0.0;

@@ -156,6 +156,18 @@ __host__ __device__ __forceinline__ double expm1(double x) {
     return fm::exp(x) - 1.0;
 }
 
+// a/b within an ulp: quotient from a reciprocal seed (two Newton steps on the
+// device, the IEEE reciprocal on the host) and one residual correction.
+__host__ __device__ __forceinline__ double div(double a, double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double r = rcp(b);
+#else
+    const double r = 1.0 / b;
+#endif
+    const double q = a * r;
+    return fma(r, fma(-b, q, a), q);
+}
+
 // Natural logarithm for finite x > 0.
 __host__ __device__ __forceinline__ double log(double x) {
     int e;
@@ -164,7 +176,7 @@ __host__ __device__ __forceinline__ double log(double x) {
         m *= 2.0;
         e -= 1;
     }
-    const double f = (m - 1.0) / (m + 1.0);
+    const double f = div(m - 1.0, m + 1.0);
     const double s = f * f;
     double p = 1.0 / 23.0;
     p = fma(p, s, 1.0 / 21.0);
@@ -378,8 +390,10 @@ __device__ __forceinline__ double redshift(double r, double th, double a, double
 //  x > 2: K_2 = f(t) e^-x / sqrt(x) with f(t) = sqrt(x) e^x K_2(x), t = 2/x,
 //     a smooth function on (0, 1] evaluated from its Chebyshev expansion in
 //     s = 2t - 1 (Clenshaw's recurrence; coefficients by csrc/gen_k2_cheb.py).
-// Kept out of line: inlined into the integrator it raised the torus kernel's
-// spills from 124 to 284 bytes per lane and made it 45% slower (measured).
+// Inlined: out of line, the call made the integrator save and restore the
+// uniform values it keeps in SGPRs around every call (measured 1-2% slower
+// than inline once the kernel no longer spilled; in an earlier build that still
+// spilled, inlining had raised the spills instead).
 namespace k2 {
 constexpr double harm(int n) { return n == 0 ? 0.0 : harm(n - 1) + 1.0 / n; }
 template <int K> struct C { static constexpr double value = 1.0 / (trig::fact(K) * trig::fact(K + 2)); };
@@ -414,7 +428,7 @@ constexpr double kCheb[23] = {
 };
 }  // namespace k2
 
-__device__ __noinline__ double bessel_k2(double x) {
+__device__ inline double bessel_k2(double x) {
     if (x <= 2.0) {
         const double q = 0.25 * x * x;
         const double lg = fm::log(0.5 * x) + kEulerGamma;
@@ -443,10 +457,10 @@ __device__ __noinline__ double bessel_k2(double x) {
 // Torus and emission parameters in the form the kernels use.
 struct TorusParams {
     double n0, inv_rnorm, n_index, inv_2h2, T0, T_index, eps_B, rg, r_emit_max;
-    // products of constants, set on the host: B^2 = cB n_e / r, Theta_e = cTheta T_e/T0,
+    // products of constants, set on the host: B^2 = cB n_e / r, Theta_e = cTheta T_e/T0 = 1/(cInvTheta T0/T_e),
     // nu_c = cNu B Theta_e^2, j prefactor = cJ n_e / K_2(1/Theta_e), h/(k T_e) = cH T0/T_e,
     // 1/B_nu = cBnu expm1(h nu/(k T_e)) / nu^3
-    double cB, cTheta, cNu, cJ, cH, cBnu;
+    double cB, cTheta, cInvTheta, cNu, cJ, cH, cBnu;
 };
 
 // Emission and absorption per unit affine parameter at (r, theta), redshift g,
@@ -476,7 +490,7 @@ __device__ inline Plasma torus_plasma(const TorusParams& P, double r, double cth
     const double B = sqrt(P.cB * q.ne * fm::rcp(r));
     const double theta_e = P.cTheta * eT;
     q.inv_nu_c = fm::rcp(P.cNu * B * theta_e * theta_e);
-    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT / P.cTheta));
+    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT * P.cInvTheta));
     q.hkT = P.cH * ieT;
     return q;
 }
