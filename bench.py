@@ -43,7 +43,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # divergence-free run (every lane traces the same ray), see
 # profiles/trace_kernel_flop_calibration.md (the thin-disk figure, from three disk
 # rays, also serves the projection workload, which runs the same kernel).
-FLOPS_PER_ATTEMPT = {"torus": (1521.0, "calibrated"), "thin_disk": (995.0, "calibrated"),
+FLOPS_PER_ATTEMPT = {"torus": (1461.0, "calibrated"), "thin_disk": (995.0, "calibrated"),
                      "projection": (995.0, "calibrated")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -53,9 +53,9 @@ FLOPS_PER_ATTEMPT = {"torus": (1521.0, "calibrated"), "thin_disk": (995.0, "cali
 # VALU lane utilisation of the dominant kernel on the 1024^2 torus image (useful
 # FP64 FLOPs / FP64 lane slots issued, rocprofv3 counters), valid for the sources it
 # was taken on; see profiles/trace_kernel_flop_calibration.md.
-LANE_UTILISATION = {"torus": {"value": 0.860, "source_md5": "2f8c07a5de3c45d6d8f15d57eb4d9914"}}
+LANE_UTILISATION = {"torus": {"value": 0.876, "source_md5": "c9619453c4f4a4a9b486ba16433b13a0"}}
 
-TRAFFIC = {"torus": {"bytes": 500424640, "source_md5": "2f8c07a5de3c45d6d8f15d57eb4d9914"}}
+TRAFFIC = {"torus": {"bytes": 512566688, "source_md5": "c9619453c4f4a4a9b486ba16433b13a0"}}
 
 
 def kernel_source_md5() -> str:

@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 #define KGRT_WAVES_DISK 3
 #endif
 #ifndef KGRT_WAVES_TORUS
-#define KGRT_WAVES_TORUS 3
+#define KGRT_WAVES_TORUS 4
 #endif
 #ifndef KGRT_WAVES_TORUS_MULTI
 #define KGRT_WAVES_TORUS_MULTI 2
@@ -248,8 +248,8 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         if (isfinite(y.r)) {
                             active = true;
                             if (MODEL == KGRT_MODEL_TORUS) {
-                                const double g0 = redshift_sc(y.r, sy, cy, a, a2, -L);
-                                const double ig0 = fm::rcp(g0);
+                                double ig0;
+                                const double g0 = redshift_sc(y.r, sy, cy, a, a2, -L, ig0);
                                 const KParams& PR = reread_params();
                                 const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
 #pragma unroll
@@ -376,8 +376,8 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     if (MODEL == KGRT_MODEL_TORUS) {
                         // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
                         // each accepted endpoint, exponential-trapezoid increment
-                        const double g1 = redshift_sc(y.r, sy, cy, a, a2, -L);
-                        const double ig1 = fm::rcp(g1);
+                        double ig1;
+                        const double g1 = redshift_sc(y.r, sy, cy, a, a2, -L, ig1);
                         const KParams& PR = reread_params();
                         const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
 #pragma unroll
@@ -572,7 +572,9 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     T.cB = 8.0 * kPi * T.eps_B * kMp * kC * kC / 6.0;
     T.cTheta = kKb * T.T0 / (kMe * kC * kC);
     T.cInvTheta = (T.T0 > 0.0) ? 1.0 / T.cTheta : 0.0;
+    T.cLnHalfInvTheta = (T.T0 > 0.0) ? std::log(0.5 * T.cInvTheta) : 0.0;
     T.cNu = 3.0 * kQe / (4.0 * kPi * kMe * kC);
+    T.cNuC = T.cB * T.cNu * T.cNu * (T.cTheta * T.cTheta) * (T.cTheta * T.cTheta);
     T.cJ = kQe * kQe / (1.7320508075688772 * kC);
     T.cH = (T.T0 > 0.0) ? kH / (kKb * T.T0) : 0.0;
     T.cBnu = kC * kC / (2.0 * kH);

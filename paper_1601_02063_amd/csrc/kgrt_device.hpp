@@ -206,9 +206,19 @@ __device__ __forceinline__ double ipow(double y) {
     }
 }
 
+// 1/sqrt(x) for positive normal x: hardware seed (relative error about 2^-23)
+// and two Newton steps y <- y + y (1 - x y^2)/2.
+__device__ __forceinline__ double rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(y * 0.5, fma(-x * y, y, 1.0), y);
+    y = fma(y * 0.5, fma(-x * y, y, 1.0), y);
+    return y;
+}
+
 // x^(-1/N) for 1e-30 <= x <= 1e30.
 template <int N>
 __device__ __forceinline__ double inv_root(double x) {
+    if constexpr (N == 2) return rsqrt(x);
     const float xf = (float)x;
     double y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(xf) * (1.0f / N));
 #pragma unroll
@@ -359,27 +369,30 @@ __device__ __forceinline__ bool start_ray(double a, double a2, double r_obs, dou
 // seen by an observer at rest at infinity; the zero-angular-momentum
 // observer replaces it where u.u = -1 has no solution. xi = L_z/E.
 // With sin(theta) (clamped) and cos(theta) given.
-__device__ __forceinline__ double redshift_sc(double r, double s, double c, double a, double a2, double xi) {
+// Returns g and sets ig = 1/g.
+__device__ __forceinline__ double redshift_sc(double r, double s, double c, double a, double a2, double xi,
+                                              double& ig) {
     const double s2 = s * s;
     const double Sigma = r * r + a2 * c * c;
     const double iS = fm::rcp(Sigma);
     const double gtt = -(1.0 - 2.0 * r * iS);
     const double gtp = -2.0 * a * r * s2 * iS;
     const double gpp = (r * r + a2 + 2.0 * a2 * r * s2 * iS) * s2;
-    double Om = fm::rcp(r * sqrt(r) + a);
+    double Om = fm::rcp(fma(r * r, fm::rsqrt(r), a));  // 1/(r^3/2 + a)
     double arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
     if (!(arg > 0.0)) {
         Om = -gtp * fm::rcp(gpp);
         arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
     }
-    // 1/(u^t (1 - xi Omega)) with u^t = arg^-1/2
-    return sqrt(arg) * fm::rcp(1.0 - xi * Om);
+    // g = 1/(u^t (1 - xi Omega)) with u^t = arg^-1/2
+    ig = (1.0 - xi * Om) * fm::rsqrt(arg);
+    return fm::rcp(ig);
 }
 
 __device__ __forceinline__ double redshift(double r, double th, double a, double a2, double xi) {
-    double s, c;
+    double s, c, ig;
     sincos_bounded(th, &s, &c);
-    return redshift_sc(r, clamp_sin(s), c, a, a2, xi);
+    return redshift_sc(r, clamp_sin(s), c, a, a2, xi, ig);
 }
 
 // Modified Bessel function K_2(x), x > 0, to ~1e-15 relative.
@@ -428,10 +441,11 @@ constexpr double kCheb[23] = {
 };
 }  // namespace k2
 
-__device__ inline double bessel_k2(double x) {
+// lnh = ln(x/2), which the caller has from the logarithm it already takes.
+__device__ inline double bessel_k2(double x, double lnh) {
     if (x <= 2.0) {
         const double q = 0.25 * x * x;
-        const double lg = fm::log(0.5 * x) + kEulerGamma;
+        const double lg = lnh + kEulerGamma;
         double pb = k2::CB<12>::value, pc = k2::C<12>::value;
 #define KGRT_K2_TERM(K)                      \
     pb = fma(pb, q, k2::CB<K>::value);       \
@@ -458,9 +472,10 @@ __device__ inline double bessel_k2(double x) {
 struct TorusParams {
     double n0, inv_rnorm, n_index, inv_2h2, T0, T_index, eps_B, rg, r_emit_max;
     // products of constants, set on the host: B^2 = cB n_e / r, Theta_e = cTheta T_e/T0 = 1/(cInvTheta T0/T_e),
-    // nu_c = cNu B Theta_e^2, j prefactor = cJ n_e / K_2(1/Theta_e), h/(k T_e) = cH T0/T_e,
-    // 1/B_nu = cBnu expm1(h nu/(k T_e)) / nu^3
-    double cB, cTheta, cInvTheta, cNu, cJ, cH, cBnu;
+    // nu_c = cNu B Theta_e^2, so 1/nu_c^2 = 1/(cNuC n_e (T_e/T0)^4 / r) with cNuC = cB cNu^2 cTheta^4,
+    // j prefactor = cJ n_e / K_2(1/Theta_e), ln(1/(2 Theta_e)) = T_index ln(r/r_norm) + cLnHalfInvTheta,
+    // h/(k T_e) = cH T0/T_e, 1/B_nu = cBnu expm1(h nu/(k T_e)) / nu^3
+    double cB, cTheta, cInvTheta, cLnHalfInvTheta, cNu, cNuC, cJ, cH, cBnu;
 };
 
 // Emission and absorption per unit affine parameter at (r, theta), redshift g,
@@ -487,10 +502,9 @@ __device__ inline Plasma torus_plasma(const TorusParams& P, double r, double cth
     const double eT = fm::exp(-P.T_index * lx);                       // T_e/T0
     const double ieT = fm::rcp(eT);
     q.Te = P.T0 * eT;
-    const double B = sqrt(P.cB * q.ne * fm::rcp(r));
-    const double theta_e = P.cTheta * eT;
-    q.inv_nu_c = fm::rcp(P.cNu * B * theta_e * theta_e);
-    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT * P.cInvTheta));
+    const double eT2 = eT * eT;
+    q.inv_nu_c = fm::rsqrt(P.cNuC * q.ne * (eT2 * eT2) * fm::rcp(r));  // 1/(cNu B Theta_e^2)
+    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT * P.cInvTheta, fma(P.T_index, lx, P.cLnHalfInvTheta)));
     q.hkT = P.cH * ieT;
     return q;
 }
