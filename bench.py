@@ -445,7 +445,7 @@ def bench_infer(ctx, args, dev):
             "config": {"workload": f"MLP 4-256x4-5 SiLU forward, {n} samples per step"},
             "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": BF16_DENSE_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(ach / BF16_DENSE_PEAK_TFLOPS, 5), "traffic": None,
-                         "flops_per_sample": MLP_INFER_MFMA_FLOPS, "kernel": "mlp_infer_fused"}}
+                         "flops_per_sample": MLP_INFER_MFMA_FLOPS, "kernel": "mlp_infer_rows"}}
     mlp.close()
     print(json.dumps(line), flush=True)
 

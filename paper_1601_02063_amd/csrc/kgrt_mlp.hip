@@ -58,17 +58,11 @@ __device__ __forceinline__ float sigmoidf_(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
-// ----------------------------------------------------- fused inference
-// Inference of the whole network for tiles of 64 samples, one tile at a time
-// per block: the activations stay in one LDS buffer (64 x 256 BF16, rows
-// padded by 8 elements against bank conflicts) that each layer overwrites in
-// place, the weights stream from L2. The output head runs on MFMA too, with
-// W5 split into BF16 hi + lo parts (about 16 significant bits) and FP32
-// accumulation. A wave computes 16 RI rows x 16 UJ units of a hidden layer
-// (RI x UJ MFMA tiles, so each weight fragment serves RI row tiles); the
-// block has (4 / RI) x (16 / UJ) waves. Blocks use 39 KB of LDS, so several
-// share a compute unit and overlap one block's SiLU epilogue with another's
-// matrix products.
+// Tiles of the training kernels: 64 samples per block, activations in one LDS
+// buffer (64 x 256 BF16, rows padded by 8 elements against bank conflicts); a
+// wave computes 16 RI rows x 16 UJ units of a layer (RI x UJ MFMA tiles, so
+// each weight fragment serves RI row tiles); the block has (4 / RI) x
+// (16 / UJ) waves.
 constexpr int kTileRows = 64, kLdsStride = kH + 8;
 #ifndef KGRT_MLP_RI
 #define KGRT_MLP_RI 4
@@ -76,159 +70,173 @@ constexpr int kTileRows = 64, kLdsStride = kH + 8;
 #ifndef KGRT_MLP_UJ
 #define KGRT_MLP_UJ 2
 #endif
-constexpr int kInferRI = KGRT_MLP_RI, kInferUJ = KGRT_MLP_UJ;
-constexpr int kInferThreads = 64 * (4 / kInferRI) * (16 / kInferUJ);
+constexpr int kTrainRI = KGRT_MLP_RI, kTrainUJ = KGRT_MLP_UJ;
+constexpr int kTrainThreads = 64 * (4 / kTrainRI) * (16 / kTrainUJ);
 
-template <int RI, int UJ>
-__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
-mlp_infer_fused(const float* __restrict__ x, int64_t n, const float* __restrict__ P, const __bf16* __restrict__ Wf,
-                const float* __restrict__ Pi, float* __restrict__ y) {
-    constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
-    static_assert(kTileRows % (16 * RI) == 0 && kH % (16 * UJ) == 0, "tile shape");
-    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-    __shared__ __align__(16) __bf16 actbuf[2][kTileRows * kLdsStride];  // ping-pong between layers
-    __shared__ float xs[kTileRows * kIn];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / WU, wu = wave % WU;
-    const int lr = lane & 15, lg = lane >> 4;
-    // Input layer on MFMA with W1 and x split into BF16 hi + lo parts along k:
-    // k 0..3 W1hi.xhi, 4..7 W1hi.xlo, 8..11 W1lo.xhi (about 2^-16 relative), the rest zero.
-    auto split = [](float v, __bf16& hi, __bf16& lo) {
-        hi = (__bf16)v;
-        lo = (__bf16)(v - (float)hi);
-    };
-    const __bf16 z16 = (__bf16)0.0f;
-    bf16x8 w1f[UJ];
-#pragma unroll
-    for (int j = 0; j < UJ; ++j) {
-        const float* w = Pi + kPiW1 + (16 * (UJ * wu + j) + lr) * kIn;
-        bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
-        __bf16 hi[kIn], lo[kIn];
-#pragma unroll
-        for (int c = 0; c < kIn; ++c) split(w[c], hi[c], lo[c]);
-#pragma unroll
-        for (int c = 0; c < kIn; ++c) {
-            if (lg == 0) {
-                f[c] = hi[c];
-                f[4 + c] = hi[c];
-            } else if (lg == 1) {
-                f[c] = lo[c];
-            }
+// ------------------------------------------- row-parallel fused inference
+// Each wave owns 16 RB rows and computes every unit of every layer for them,
+// so a layer's activations never leave the wave's registers: the MFMA result
+// of a 16-unit block (lane (r, g) holds units 4g..4g+3 of row r) is, after
+// SiLU and conversion to BF16, directly a quarter of the next layer's B
+// operand, provided the next layer's weights are stored with their inputs
+// permuted to match. For k step s (units 32s..32s+31) lane group g holds
+// units 32s+4g..32s+4g+3 and 32s+16+4g..32s+16+4g+3, so fragment element
+// e of lane (r, g) multiplies input unit kperm(s, g, e) below. The weights of
+// one hidden layer (128 KB of fragments) sit in LDS, loaded by the whole block
+// between layers; all waves of the block then read the same fragments.
+//
+// Fragment arrays in Wr (BF16, 64 lanes x 8 values = 1 KB per fragment):
+//   hidden layers l = 0..2 (W2..W4): [l][jb 16][s 8][lane 64][8], element e of
+//     lane (r, g): W[16 jb + r][kperm(s, g, e)];
+//   input layer (scaled W1 in hi + lo parts): [jb 16][lane][8];
+//   output head (scaled W5, hi and lo parts): [s 8][part 2][lane][8].
+constexpr int64_t kWrFrag = 64 * 8;
+constexpr int64_t kWrHid = 0, kWrW1 = 3 * 16 * 8 * kWrFrag, kWrW5 = kWrW1 + 16 * kWrFrag;
+constexpr int64_t kWrSize = kWrW5 + 8 * 2 * kWrFrag;
+constexpr int kRowsRB = 2, kRowsWaves = 8, kRowsThreads = 64 * kRowsWaves, kRowsTile = 16 * kRowsRB * kRowsWaves;
+
+__host__ __device__ constexpr int kperm(int s, int g, int e) { return 32 * s + 4 * g + (e < 4 ? e : 12 + e); }
+
+__global__ void __launch_bounds__(256) pack_rows(const float* __restrict__ P, __bf16* __restrict__ Wr) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kWrSize; i += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(i % 8), lane = (int)((i / 8) % 64), r = lane % 16, g = lane / 16;
+        const int64_t f = i / kWrFrag;  // fragment index
+        float v = 0.0f;
+        if (i < kWrW1) {
+            const int l = (int)(f / 128), jb = (int)((f / 8) % 16), s = (int)(f % 8);
+            const float* W = P + (l == 0 ? kW2 : (l == 1 ? kW3 : kW4));
+            v = W[(16 * jb + r) * kH + kperm(s, g, e)];
+        } else if (i < kWrW5) {
+            // k 0..3 W1hi.xhi, 4..7 W1hi.xlo, 8..11 W1lo.xhi: lane group 0 holds W1hi twice, group 1 W1lo
+            const int jb = (int)(f - kWrW1 / kWrFrag);
+            const float w = -kLog2e * P[kW1 + (16 * jb + r) * kIn + (e & 3)];
+            const float hi = (float)(__bf16)w;
+            v = (g == 0) ? hi : ((g == 1 && e < 4) ? w - hi : 0.0f);
+        } else {
+            const int s = (int)((f - kWrW5 / kWrFrag) / 2), part = (int)((f - kWrW5 / kWrFrag) % 2);
+            const float w = (r < kOut) ? -P[kW5 + r * kH + kperm(s, g, e)] / kLog2e : 0.0f;
+            const float hi = (float)(__bf16)w;
+            v = part == 0 ? hi : w - hi;
         }
-        w1f[j] = f;
+        Wr[i] = (__bf16)v;
     }
-    // Accumulators start at the layer's scaled bias; accumulator e of (i, j) is
-    // row 16 (RI wr + i) + lr, unit 16 (UJ wu + j) + 4 lg + e.
-    auto init = [&](f32x4 (&acc)[RI][UJ], int layer) {
+}
+
+__global__ void __launch_bounds__(kRowsThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__ P, const __bf16* __restrict__ Wr,
+               const float* __restrict__ Pi, float* __restrict__ y) {
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    constexpr int RB = kRowsRB;
+    __shared__ bf16x8 wl[16 * 8 * 64];  // one hidden layer's fragments
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    auto silu = [](const f32x4& z) {  // ht = zt / (1 + 2^zt), see the scaling note above
+        bf16x4 v;
 #pragma unroll
-        for (int j = 0; j < UJ; ++j) {
-            const f32x4 b = *reinterpret_cast<const f32x4*>(Pi + kPiB + layer * kH + 16 * (UJ * wu + j) + 4 * lg);
-#pragma unroll
-            for (int i = 0; i < RI; ++i) acc[i][j] = b;
-        }
+        for (int e = 0; e < 4; ++e) v[e] = (__bf16)(z[e] * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z[e])));
+        return v;
     };
-    // ht = zt / (1 + 2^zt) of one layer into activation buffer `act`
-    auto store = [&](const f32x4 (&acc)[RI][UJ], __bf16* act) {
-#pragma unroll
-        for (int j = 0; j < UJ; ++j) {
-            const int u = 16 * (UJ * wu + j) + 4 * lg;
-#pragma unroll
-            for (int i = 0; i < RI; ++i) {
-                bf16x4 v;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float zt = acc[i][j][e];
-                    v[e] = (__bf16)(zt * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(zt)));
-                }
-                *reinterpret_cast<bf16x4*>(act + (16 * (RI * wr + i) + lr) * kLdsStride + u) = v;
-            }
-        }
-    };
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    auto cat = [](const bf16x4& a, const bf16x4& b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); };
+    const int64_t ntiles = (n + kRowsTile - 1) / kRowsTile;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row0 = tile * kTileRows;
-        __syncthreads();  // the previous tile's head has read the buffer
-        for (int i = tid; i < kTileRows * kIn; i += NT) xs[i] = (row0 + i / kIn < n) ? x[row0 * kIn + i] : 0.0f;
-        __syncthreads();
-        // input layer (rows past n compute on zeros and are never written out)
+        // Parameter pointers made opaque per tile: otherwise the compiler hoists
+        // every fragment and bias load out of the tile loop, and those loop
+        // invariants (hundreds of registers) spill.
+        typedef const __attribute__((address_space(1))) bf16x8 GW;
+        typedef const __attribute__((address_space(1))) float GF;
+        GW* Wg = (GW*)Wr;
+        GF* Pb = (GF*)Pi;
+        asm volatile("" : "+s"(Wg), "+s"(Pb));
+        const int64_t row0 = tile * kRowsTile + 16 * RB * wave;
+        bf16x4 act[RB][16], nxt[RB][16];
+        // input layer: B fragment of the features, split into hi + lo parts
         {
-            f32x4 acc[RI][UJ];
-            init(acc, 0);
+            bf16x8 xf[RB];
 #pragma unroll
-            for (int i = 0; i < RI; ++i) {
-                const float* xr = xs + (16 * (RI * wr + i) + lr) * kIn;
-                bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
-                __bf16 hi[kIn], lo[kIn];
+            for (int rb = 0; rb < RB; ++rb) {
+                const int64_t row = row0 + 16 * rb + r;
+                f32x4 xv = {0.f, 0.f, 0.f, 0.f};
+                if (row < n && g <= 1) xv = *reinterpret_cast<const f32x4*>(x + row * kIn);
+                bf16x8 f;
 #pragma unroll
-                for (int c = 0; c < kIn; ++c) split(xr[c], hi[c], lo[c]);
+                for (int c = 0; c < 4; ++c) {
+                    const __bf16 hi = (__bf16)xv[c];
+                    f[c] = hi;
+                    f[4 + c] = (g == 0) ? (__bf16)(xv[c] - (float)hi) : (__bf16)0.0f;
+                }
+                xf[rb] = f;
+            }
 #pragma unroll
-                for (int c = 0; c < kIn; ++c) {
-                    if (lg <= 1) f[c] = hi[c];
-                    if (lg == 0) f[4 + c] = lo[c];
+            for (int jb = 0; jb < 16; ++jb) {
+                const bf16x8 w1 = Wg[kWrW1 / 8 + jb * 64 + lane];
+                const f32x4 b = *(const __attribute__((address_space(1))) f32x4*)(Pb + kPiB + 16 * jb + 4 * g);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) act[rb][jb] = silu(__builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, xf[rb], b, 0, 0, 0));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // hidden layers W2..W4 from LDS
+#pragma unroll 1
+        for (int l = 0; l < 3; ++l) {
+            __syncthreads();  // every wave is done with the previous layer's fragments
+            GW* src = Wg + kWrHid / 8 + l * (16 * 8 * 64);
+#pragma unroll
+            for (int i = 0; i < 16 * 8 * 64 / kRowsThreads; ++i) wl[i * kRowsThreads + tid] = src[i * kRowsThreads + tid];
+            __syncthreads();
+#pragma unroll
+            for (int jb = 0; jb < 16; ++jb) {
+                const f32x4 b = *(const __attribute__((address_space(1))) f32x4*)(Pb + kPiB + (l + 1) * kH + 16 * jb + 4 * g);
+                f32x4 acc[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[rb] = b;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const bf16x8 w = wl[(jb * 8 + s) * 64 + lane];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, cat(act[rb][2 * s], act[rb][2 * s + 1]), acc[rb], 0, 0, 0);
                 }
 #pragma unroll
-                for (int j = 0; j < UJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, acc[i][j], 0, 0, 0);
+                for (int rb = 0; rb < RB; ++rb) nxt[rb][jb] = silu(acc[rb]);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            store(acc, actbuf[0]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int jb = 0; jb < 16; ++jb) act[rb][jb] = nxt[rb][jb];
         }
-        __syncthreads();
-        // hidden layers 2..4 on MFMA, from buffer l % 2 into the other
-        for (int l = 0; l < 3; ++l) {
-            const __bf16* act = actbuf[l & 1];
-            const __bf16* W = Wf + (int64_t)l * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
-            const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
-            f32x4 acc[RI][UJ];
-            init(acc, l + 1);
-#pragma unroll 1
-            for (int s = 0; s < kH / 32; ++s) {
-                const int k = 32 * s + 8 * lg;
-                bf16x8 af[UJ], bfg[RI];
+        // output head, W5 in hi + lo parts: lane (r, g) gets outputs 4g..4g+3 of row r
+        f32x4 acc[RB];
 #pragma unroll
-                for (int j = 0; j < UJ; ++j) af[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + k);
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
+        for (int s = 0; s < 8; ++s) {
+            const bf16x8 wh = Wg[kWrW5 / 8 + (2 * s) * 64 + lane], wo = Wg[kWrW5 / 8 + (2 * s + 1) * 64 + lane];
 #pragma unroll
-                for (int i = 0; i < RI; ++i)
-#pragma unroll
-                    for (int j = 0; j < UJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
+            for (int rb = 0; rb < RB; ++rb) {
+                const bf16x8 hv = cat(act[rb][2 * s], act[rb][2 * s + 1]);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hv, acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wo, hv, acc[rb], 0, 0, 0);
             }
-            store(acc, actbuf[(l + 1) & 1]);
-            __syncthreads();
         }
-        const __bf16* act = actbuf[1];
-        // output head: row tile rt, outputs 0..15 (5 used), hi and lo parts of W5
-        for (int rt = wave; rt < kTileRows / 16; rt += NT / 64) {
-            const __bf16* Wh = Wf + kW5Split + lr * kH;
-            const __bf16* A = act + (16 * rt + lr) * kLdsStride;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int s = 0; s < kH / 32; ++s) {
-                const int k = 32 * s + 8 * lg;
-                const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + k);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + k), hv, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + kW5Rows * kH + k), hv,
-                                                              acc, 0, 0, 0);
-            }
-            // accumulator e: output 4 lg + e of row 16 rt + lr
-            const int64_t b = row0 + 16 * rt + lr;
-            if (b < n && lg == 0) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) y[b * kOut + e] = acc[e] + P[kB5 + e];
-            } else if (b < n && lg == 1) {
-                y[b * kOut + 4] = acc[0] + P[kB5 + 4];
+        for (int rb = 0; rb < RB; ++rb) {
+            const int64_t row = row0 + 16 * rb + r;
+            if (row < n && g == 0) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) y[row * kOut + e] = acc[rb][e] + P[kB5 + e];
+            } else if (row < n && g == 1) {
+                y[row * kOut + 4] = acc[rb][0] + P[kB5 + 4];
             }
         }
     }
 }
 
-
 // ------------------------------------------------------- fused training
 // One training step in four kernels over 64-sample tiles of the batch
 // (gathered through idx):
-//  train_fwd: the inference kernel's structure in unscaled form; stores each
+//  train_fwd: the network in unscaled form on 64-row tiles whose activations
+//    pass between layers through LDS (the tile shape above); stores each
 //    layer's SiLU'(z) and activation h (layers 1..4) feature-major [256][ld]
 //    in BF16, dL/do [B][5] (FP32) and the loss;
 //  train_bwd: dz4 = (dL/do W5) SiLU'(z4), then dh_{l-1} = dz_l W_l on MFMA
@@ -984,7 +992,8 @@ struct kgrt_mlp {
     int64_t max_batch = 0;
     float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr;
     __bf16 *Wf = nullptr, *Wb = nullptr;
-    float* Pi = nullptr;  // scaled W1 and biases for inference
+    __bf16* Wr = nullptr;  // MFMA fragments of all layers for the row-parallel inference kernel
+    float* Pi = nullptr;   // scaled W1 and biases for inference
     // training arrays, feature-major [256][max_batch] BF16: z[l] holds SiLU'(z_l),
     // hT[l] and dz the activations h_l (l = 1..3) and h_4, h[l] the gradients dL/dz_l
     __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr;
@@ -1029,7 +1038,7 @@ int64_t kgrt_mlp_num_params(void) { return kNumParams; }
 int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
-    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Pi, m->part, m->dz, m->dout, m->r_feat, m->r_pred,
+    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Wr, m->Pi, m->part, m->dz, m->dout, m->r_feat, m->r_pred,
                     m->r_tab, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
                     m->h[1], m->h[2], m->h[3], m->h[4], m->z[1], m->z[2], m->z[3], m->z[4],
                     m->hT[1], m->hT[2], m->hT[3]};
@@ -1053,6 +1062,7 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
     bool ok = hipMalloc(&m->P, kNumParams * 4) == hipSuccess && hipMalloc(&m->M, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->V, kNumParams * 4) == hipSuccess && hipMalloc(&m->G, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->Wf, kWfSize * sizeof(__bf16)) == hipSuccess &&
+              hipMalloc(&m->Wr, kWrSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Pi, kPiSize * sizeof(float)) == hipSuccess &&
               hipMalloc(&m->Wb, 3 * kH * kH * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess &&
@@ -1079,6 +1089,7 @@ int kgrt_mlp_set_params(kgrt_mlp* m, const float* params, int64_t n) {
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->M, kNumParams, 0.0f);
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->V, kNumParams, 0.0f);
     hipLaunchKernelGGL(pack_weights, dim3(64, 5), dim3(256), 0, 0, m->P, m->Wf, m->Wb, m->Pi);
+    hipLaunchKernelGGL(pack_rows, dim3(208), dim3(256), 0, 0, m->P, m->Wr);
     m->step = 0;
     if (hipDeviceSynchronize() != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "set_params failed");
     return KGRT_OK;
@@ -1100,15 +1111,14 @@ int kgrt_mlp_forward(kgrt_mlp* m, const float* x, float* y, int64_t n, void* str
     if (!x || !y) return mlp_fail(m, KGRT_E_INVALID_ARG, "x and y must be device pointers");
     DevGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
-    // a persistent grid: as many resident blocks as fit, looping over 64-sample tiles
+    // a persistent grid: as many resident blocks as fit, looping over 256-sample tiles
     int dev = 0, ncu = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    auto kern = mlp_infer_fused<kInferRI, kInferUJ>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kInferThreads, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mlp_infer_rows, kRowsThreads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    const int64_t ntiles = (n + kRowsTile - 1) / kRowsTile;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)ncu * per_cu));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kInferThreads), 0, st, x, n, m->P, m->Wf, m->Pi, y);
+    hipLaunchKernelGGL(mlp_infer_rows, dim3(grid), dim3(kRowsThreads), 0, st, x, n, m->P, m->Wr, m->Pi, y);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
@@ -1137,14 +1147,14 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     tb.inv_n = 1.0f / (float)n;
     int dev = 0, ncu = 256, pf = 1, pb = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    auto kf = train_fwd<kInferRI, kInferUJ>;
-    auto kb = train_bwd<kInferRI, kInferUJ>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pf, kf, kInferThreads, 0) != hipSuccess || pf < 1) pf = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pb, kb, kInferThreads, 0) != hipSuccess || pb < 1) pb = 1;
+    auto kf = train_fwd<kTrainRI, kTrainUJ>;
+    auto kb = train_bwd<kTrainRI, kTrainUJ>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pf, kf, kTrainThreads, 0) != hipSuccess || pf < 1) pf = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pb, kb, kTrainThreads, 0) != hipSuccess || pb < 1) pb = 1;
     const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-    hipLaunchKernelGGL(kf, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pf)), dim3(kInferThreads), 0, st, x,
+    hipLaunchKernelGGL(kf, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pf)), dim3(kTrainThreads), 0, st, x,
                        idx, t, n, m->P, m->Wf, tb);
-    hipLaunchKernelGGL(kb, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pb)), dim3(kInferThreads), 0, st, x,
+    hipLaunchKernelGGL(kb, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pb)), dim3(kTrainThreads), 0, st, x,
                        idx, n, m->P, m->Wb, tb, m->G);
     hipLaunchKernelGGL(train_dw, dim3(kH / 64, kDwChunks, 3), dim3(256), 0, st, tb, n, m->part);
     hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
@@ -1168,6 +1178,7 @@ int kgrt_mlp_train_step(kgrt_mlp* m, const float* x, const float* t, const int32
     hipLaunchKernelGGL(adam, dim3(256), dim3(256), 0, st, m->P, m->M, m->V, m->G, kNumParams, opt->lr, opt->beta1,
                        opt->beta2, opt->eps, c1, c2);
     hipLaunchKernelGGL(pack_weights, dim3(64, 5), dim3(256), 0, st, m->P, m->Wf, m->Wb, m->Pi);
+    hipLaunchKernelGGL(pack_rows, dim3(208), dim3(256), 0, st, m->P, m->Wr);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
