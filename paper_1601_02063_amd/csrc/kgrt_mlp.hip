@@ -128,6 +128,7 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
     constexpr int RB = kRowsRB;
     __shared__ bf16x8 wl[16 * 8 * 64];  // one hidden layer's fragments
+    __shared__ f32x4 bl[4 * kH / 4];      // scaled biases b1..b4
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     auto silu = [](const f32x4& z) {  // ht = zt / (1 + 2^zt), see the scaling note above
@@ -138,15 +139,15 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
     };
     auto cat = [](const bf16x4& a, const bf16x4& b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); };
     const int64_t ntiles = (n + kRowsTile - 1) / kRowsTile;
+    for (int i = tid; i < kH; i += kRowsThreads) bl[i] = reinterpret_cast<const f32x4*>(Pi + kPiB)[i];
+    __syncthreads();
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // Parameter pointers made opaque per tile: otherwise the compiler hoists
         // every fragment and bias load out of the tile loop, and those loop
         // invariants (hundreds of registers) spill.
         typedef const __attribute__((address_space(1))) bf16x8 GW;
-        typedef const __attribute__((address_space(1))) float GF;
         GW* Wg = (GW*)Wr;
-        GF* Pb = (GF*)Pi;
-        asm volatile("" : "+s"(Wg), "+s"(Pb));
+        asm volatile("" : "+s"(Wg));
         const int64_t row0 = tile * kRowsTile + 16 * RB * wave;
         bf16x4 act[RB][16], nxt[RB][16];
         // input layer: B fragment of the features, split into hi + lo parts
@@ -169,7 +170,7 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
 #pragma unroll
             for (int jb = 0; jb < 16; ++jb) {
                 const bf16x8 w1 = Wg[kWrW1 / 8 + jb * 64 + lane];
-                const f32x4 b = *(const __attribute__((address_space(1))) f32x4*)(Pb + kPiB + 16 * jb + 4 * g);
+                const f32x4 b = bl[4 * jb + g];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) act[rb][jb] = silu(__builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, xf[rb], b, 0, 0, 0));
                 __builtin_amdgcn_sched_barrier(0);
@@ -183,22 +184,40 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
 #pragma unroll
             for (int i = 0; i < 16 * 8 * 64 / kRowsThreads; ++i) wl[i * kRowsThreads + tid] = src[i * kRowsThreads + tid];
             __syncthreads();
+            // software pipeline: the MFMAs of unit block jb run while the SiLU of jb - 1 is computed
+            f32x4 prev[RB];
 #pragma unroll
-            for (int jb = 0; jb < 16; ++jb) {
-                const f32x4 b = *(const __attribute__((address_space(1))) f32x4*)(Pb + kPiB + (l + 1) * kH + 16 * jb + 4 * g);
+            for (int jb = 0; jb <= 16; ++jb) {
                 f32x4 acc[RB];
+                if (jb < 16) {
+                    const f32x4 b = bl[(l + 1) * (kH / 4) + 4 * jb + g];
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) acc[rb] = b;
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = b;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const bf16x8 w = wl[(jb * 8 + s) * 64 + lane];
+                    for (int s = 0; s < 8; ++s) {
+                        const bf16x8 w = wl[(jb * 8 + s) * 64 + lane];
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-                        acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, cat(act[rb][2 * s], act[rb][2 * s + 1]), acc[rb], 0, 0, 0);
+                        for (int rb = 0; rb < RB; ++rb)
+                            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, cat(act[rb][2 * s], act[rb][2 * s + 1]), acc[rb], 0, 0, 0);
+                    }
                 }
+                if (jb > 0) {
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) nxt[rb][jb] = silu(acc[rb]);
+                    for (int rb = 0; rb < RB; ++rb) nxt[rb][jb - 1] = silu(prev[rb]);
+                }
+                if (jb < 16) {
+                    // LDS reads one k step ahead of the MFMAs that use them, SiLU VALU work between
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                        if (i < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) prev[rb] = acc[rb];
             }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
