@@ -49,15 +49,31 @@ __device__ __forceinline__ double clamp_sin(double s) { return (s < kSinFloor) ?
 
 // sin and cos of one argument for |x| < 2^20 (polar angles stay near [0, pi]).
 // Cody-Waite reduction by a three-part pi/2 (fused multiply-adds keep the
-// reduced argument exact to about 2^-100), then the Taylor series of sin and
-// cos on |r| <= pi/4, truncated where the next term is below 1e-19 (r^17 and
-// r^18), and the quadrant rotation. Accuracy ~1 ulp; much lighter than the
-// general-argument library routine, whose large-argument path costs registers.
+// reduced argument exact to about 2^-100), then polynomials on |r| <= pi/4 and
+// the quadrant rotation: sin r = r + r^3 S(r^2), cos r = 1 - r^2/2 + r^4 C(r^2)
+// with S, C of degree 5 fitted near-minimax by csrc/gen_poly.py (their
+// approximation error 0.18 and 0.011 ulp; the truncated Taylor series needs
+// two more terms each for the same accuracy). About 1 ulp in all; much lighter
+// than the general-argument library routine, whose large-argument path costs
+// registers.
 namespace trig {
 constexpr double kTwoOverPi = 0.6366197723675814;
 constexpr double kPio2Hi = 1.5707963267948966;      // 0x1.921fb54442d18p+0
 constexpr double kPio2Mid = 6.123233995736766e-17;  // 0x1.1a62633145c07p-54
 constexpr double kPio2Lo = -1.4973849048591698e-33; // -0x1.f1976b7ed8fbcp-110
+// S and C, highest power of z = r^2 first
+constexpr double kSinPoly[6] = {1.5918129294866608e-10, -2.5051131845003624e-08, 2.755731610255244e-06,
+                                -0.00019841269836758574, 0.008333333333330948, -0.16666666666666666};
+constexpr double kCosPoly[6] = {-1.1382632425521717e-11, 2.08761462684032e-09, -2.7557317271729793e-07,
+                                2.480158729876569e-05, -0.0013888888888887398, 0.041666666666666664};
+// e^r - 1 = r + r^2/2 + r^3 E(r) on |r| <= ln(2)/2 and atanh f = f + f^3 A(f^2)
+// on |f| <= 3 - 2 sqrt(2), E and A from the same generator
+constexpr double kExpm1Poly[10] = {2.091122972975856e-09,  2.5100375832561234e-08, 2.755728298405588e-07,
+                                   2.7557268480310024e-06, 2.4801587317135164e-05, 0.00019841269863040545,
+                                   0.0013888888888886554,  0.008333333333330065,   0.041666666666666664,
+                                   0.16666666666666669};
+constexpr double kAtanhPoly[7] = {0.07308224842521703, 0.07665860800278021, 0.09091444562630861, 0.1111110556739754,
+                                  0.14285714312987743, 0.19999999999949752, 0.3333333333333335};
 constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
 // 1/n! as a compile-time constant (a class-template constant forces constant evaluation)
 template <int N>
@@ -73,25 +89,14 @@ __host__ __device__ __forceinline__ void sincos_bounded(double x, double* sp, do
     r = fma(-k, kPio2Mid, r);
     r = fma(-k, kPio2Lo, r);
     const double z = r * r;
-    double ps = InvFact<17>::value;
-    ps = fma(ps, z, -InvFact<15>::value);
-    ps = fma(ps, z, InvFact<13>::value);
-    ps = fma(ps, z, -InvFact<11>::value);
-    ps = fma(ps, z, InvFact<9>::value);
-    ps = fma(ps, z, -InvFact<7>::value);
-    ps = fma(ps, z, InvFact<5>::value);
-    ps = fma(ps, z, -InvFact<3>::value);
+    double ps = kSinPoly[0], pc = kCosPoly[0];
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+        ps = fma(ps, z, kSinPoly[i]);
+        pc = fma(pc, z, kCosPoly[i]);
+    }
     const double sr = fma(r * z, ps, r);
-    double pc = -InvFact<18>::value;
-    pc = fma(pc, z, InvFact<16>::value);
-    pc = fma(pc, z, -InvFact<14>::value);
-    pc = fma(pc, z, InvFact<12>::value);
-    pc = fma(pc, z, -InvFact<10>::value);
-    pc = fma(pc, z, InvFact<8>::value);
-    pc = fma(pc, z, -InvFact<6>::value);
-    pc = fma(pc, z, InvFact<4>::value);
-    pc = fma(pc, z, -0.5);
-    const double cr = fma(z, pc, 1.0);
+    const double cr = fma(z, fma(z, pc, -0.5), 1.0);
     const int q = ((int)k) & 3;
     const double s1 = (q & 1) ? cr : sr;
     const double c1 = (q & 1) ? sr : cr;
@@ -105,8 +110,9 @@ __host__ __device__ __forceinline__ void sincos_bounded(double x, double* sp, do
 // would halve the kernel's occupancy; these cover the argument ranges that
 // occur here, with ~1-3 ulp accuracy (checked on the host against a
 // multiple-precision reference). All from textbook methods:
-//   exp/expm1: Cody & Waite reduction x = k ln2 + r, |r| <= ln2/2, Taylor series;
-//   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), log m = 2 atanh((m-1)/(m+1)) series;
+//   exp/expm1: Cody & Waite reduction x = k ln2 + r, |r| <= ln2/2, polynomial;
+//   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), log m = 2 atanh((m-1)/(m+1)), polynomial;
+//   (the polynomials: leading Taylor terms plus a near-minimax remainder, above);
 //   x^(-1/n): single-precision seed 2^(-log2(x)/n) and two Newton steps
 //             y <- y + y (1 - x y^n)/n in double (quadratic convergence);
 //   1/x: hardware reciprocal seed and two Newton steps r <- r + r (1 - x r).
@@ -123,20 +129,11 @@ __device__ __forceinline__ double rcp(double x) {
     return r;
 }
 
-// e^r - 1 for |r| <= ln2/2 (Taylor series through r^14/14!).
+// e^r - 1 for |r| <= ln2/2.
 __host__ __device__ __forceinline__ double expm1_reduced(double r) {
-    double p = trig::InvFact<14>::value;
-    p = fma(p, r, trig::InvFact<13>::value);
-    p = fma(p, r, trig::InvFact<12>::value);
-    p = fma(p, r, trig::InvFact<11>::value);
-    p = fma(p, r, trig::InvFact<10>::value);
-    p = fma(p, r, trig::InvFact<9>::value);
-    p = fma(p, r, trig::InvFact<8>::value);
-    p = fma(p, r, trig::InvFact<7>::value);
-    p = fma(p, r, trig::InvFact<6>::value);
-    p = fma(p, r, trig::InvFact<5>::value);
-    p = fma(p, r, trig::InvFact<4>::value);
-    p = fma(p, r, trig::InvFact<3>::value);
+    double p = trig::kExpm1Poly[0];
+#pragma unroll
+    for (int i = 1; i < 10; ++i) p = fma(p, r, trig::kExpm1Poly[i]);
     p = fma(p, r, 0.5);
     return fma(r * r, p, r);
 }
@@ -178,17 +175,9 @@ __host__ __device__ __forceinline__ double log(double x) {
     }
     const double f = div(m - 1.0, m + 1.0);
     const double s = f * f;
-    double p = 1.0 / 23.0;
-    p = fma(p, s, 1.0 / 21.0);
-    p = fma(p, s, 1.0 / 19.0);
-    p = fma(p, s, 1.0 / 17.0);
-    p = fma(p, s, 1.0 / 15.0);
-    p = fma(p, s, 1.0 / 13.0);
-    p = fma(p, s, 1.0 / 11.0);
-    p = fma(p, s, 1.0 / 9.0);
-    p = fma(p, s, 1.0 / 7.0);
-    p = fma(p, s, 1.0 / 5.0);
-    p = fma(p, s, 1.0 / 3.0);
+    double p = trig::kAtanhPoly[0];
+#pragma unroll
+    for (int i = 1; i < 7; ++i) p = fma(p, s, trig::kAtanhPoly[i]);
     const double lm = fma(2.0 * f * s, p, 2.0 * f);  // 2 atanh(f)
     return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, lm));
 }
@@ -248,10 +237,13 @@ __device__ __forceinline__ State rhs_sc(const State& y, double s, double c, doub
     const double r2a2 = r * r + a2;
     const double Sigma = r * r + a2 * c * c;
     const double Delta = r2a2 - 2.0 * r;
-    const double iSD = fm::rcp(Sigma * Delta);
+    // one reciprocal for both 1/(Sigma Delta) and 1/sin^2
+    const double SD = Sigma * Delta, s2 = s * s;
+    const double R = fm::rcp(SD * s2);
+    const double iSD = R * s2;
     const double iS = Delta * iSD;
     const double iD = Sigma * iSD;
-    const double is2 = fm::rcp(s * s);
+    const double is2 = R * SD;
     const double W = -r2a2 - a * L;
     const double WiD = W * iD;
     State d;
