@@ -339,7 +339,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                 const double tol = P.rtol;
 #define KGRT_ERR(f)                                                                      \
     {                                                                                    \
-        const double e = fabs(ye.f) * fm::rcp(tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12)); \
+        const double e = fabs(ye.f) * fm::rcp_coarse(tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12)); \
         if (e > errmax) errmax = e;                                                      \
     }
                 KGRT_ERR(r) KGRT_ERR(th) KGRT_ERR(ph) KGRT_ERR(t) KGRT_ERR(pr) KGRT_ERR(pth)

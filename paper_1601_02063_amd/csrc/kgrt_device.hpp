@@ -45,7 +45,9 @@ struct State {
     double r, th, ph, t, pr, pth;
 };
 
-__device__ __forceinline__ double clamp_sin(double s) { return (s < kSinFloor) ? kSinFloor : s; }
+// max(s, floor) in one instruction (a NaN s gives the floor; the state's own
+// finiteness test catches NaN states)
+__device__ __forceinline__ double clamp_sin(double s) { return fmax(s, kSinFloor); }
 
 // sin and cos of one argument for |x| < 2^20 (polar angles stay near [0, pi]).
 // Cody-Waite reduction by a three-part pi/2 (fused multiply-adds keep the
@@ -97,11 +99,13 @@ __host__ __device__ __forceinline__ void sincos_bounded(double x, double* sp, do
     }
     const double sr = fma(r * z, ps, r);
     const double cr = fma(z, fma(z, pc, -0.5), 1.0);
-    const int q = ((int)k) & 3;
+    // quadrant rotation: swap for odd k, then the signs as bit flips of the high word
+    const int q = (int)k;
     const double s1 = (q & 1) ? cr : sr;
     const double c1 = (q & 1) ? sr : cr;
-    *sp = (q & 2) ? -s1 : s1;
-    *cp = ((q + 1) & 2) ? -c1 : c1;
+    const uint64_t ssign = (uint64_t)(uint32_t)(q & 2) << 62, csign = (uint64_t)(uint32_t)((q + 1) & 2) << 62;
+    *sp = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s1) ^ ssign);
+    *cp = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c1) ^ csign);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,6 +131,13 @@ __device__ __forceinline__ double rcp(double x) {
     r = fma(r, fma(-x, r, 1.0), r);
     r = fma(r, fma(-x, r, 1.0), r);
     return r;
+}
+
+// 1/x to about 2^-46 relative (one Newton step), for the step-size controller's
+// error norm: it only decides acceptance against 1 and scales the next step.
+__device__ __forceinline__ double rcp_coarse(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
 }
 
 // e^r - 1 for |r| <= ln2/2.
