@@ -294,7 +294,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
         bool terminate = false;
         const State yb = (kDisk && refine) ? yk : y;
         const double hb = (kDisk && refine) ? hs : h;
-        const State k1 = rhs_sc(yb, (kDisk && refine) ? syk : sy, (kDisk && refine) ? cyk : cy, a, a2, L);
+        const State k1 = rhs_sc(yb, (kDisk && refine) ? syk : sy, (kDisk && refine) ? cyk : cy, a, a2, L, hb);
         State yn, ye;
         cash_karp(yb, k1, hb, a, a2, L, yn, ye);
         bool check_end = false;
@@ -337,10 +337,10 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
             double errmax = 0.0;
             {
                 const double tol = P.rtol;
-#define KGRT_ERR(f)                                                                      \
-    {                                                                                    \
-        const double e = fabs(ye.f) * fm::rcp_coarse(tol * (fabs(y.f) + fabs(h * k1.f) + 1e-12)); \
-        if (e > errmax) errmax = e;                                                      \
+#define KGRT_ERR(f)                                                                   \
+    {                                                                                 \
+        const double e = fabs(ye.f) * fm::rcp_coarse(tol * (fabs(y.f) + fabs(k1.f) + 1e-12)); \
+        if (e > errmax) errmax = e;                                                   \
     }
                 KGRT_ERR(r) KGRT_ERR(th) KGRT_ERR(ph) KGRT_ERR(t) KGRT_ERR(pr) KGRT_ERR(pth)
 #undef KGRT_ERR

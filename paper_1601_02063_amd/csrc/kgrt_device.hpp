@@ -243,7 +243,10 @@ __device__ __forceinline__ double pow_m02(double x) { return inv_root<5>(x); }
 // equal to the printed form on the null cone; it keeps 2 Sigma H conserved,
 // which the printed form does not on ingoing rays.
 // With sin(theta) (clamped) and cos(theta) of y given.
-__device__ __forceinline__ State rhs_sc(const State& y, double s, double c, double a, double a2, double L) {
+// h f(y): the right-hand side scaled by the step size h (the Cash-Karp stages
+// only ever use h k_i, so the scale is folded into the two common factors
+// 1/(Sigma Delta) and 1/Sigma instead of multiplying every component).
+__device__ __forceinline__ State rhs_sc(const State& y, double s, double c, double a, double a2, double L, double h) {
     const double r = y.r;
     const double r2a2 = r * r + a2;
     const double Sigma = r * r + a2 * c * c;
@@ -252,66 +255,64 @@ __device__ __forceinline__ State rhs_sc(const State& y, double s, double c, doub
     const double SD = Sigma * Delta, s2 = s * s;
     const double R = fm::rcp(SD * s2);
     const double iSD = R * s2;
-    const double iS = Delta * iSD;
     const double iD = Sigma * iSD;
     const double is2 = R * SD;
+    const double hSD = h * iSD;     // h/(Sigma Delta)
+    const double hS = Delta * hSD;  // h/Sigma
     const double W = -r2a2 - a * L;
     const double WiD = W * iD;
     State d;
-    d.r = Delta * y.pr * iS;
-    d.th = y.pth * iS;
-    d.ph = (-2.0 * a * r + (Sigma - 2.0 * r) * L * is2) * iSD;
-    d.t = -1.0 - 2.0 * r * (r2a2 + a * L) * iSD;
-    d.pr = (-2.0 * r * WiD - (r - 1.0) * (WiD * WiD + y.pr * y.pr)) * iS;
-    d.pth = s * c * iS * (L * L * is2 * is2 - a2);
+    d.r = Delta * y.pr * hS;
+    d.th = y.pth * hS;
+    d.ph = (-2.0 * a * r + (Sigma - 2.0 * r) * L * is2) * hSD;
+    d.t = -h - 2.0 * r * (r2a2 + a * L) * hSD;
+    d.pr = (-2.0 * r * WiD - (r - 1.0) * (WiD * WiD + y.pr * y.pr)) * hS;
+    d.pth = s * c * hS * (L * L * is2 * is2 - a2);
     return d;
 }
 
-__device__ __forceinline__ State rhs(const State& y, double a, double a2, double L) {
+__device__ __forceinline__ State rhs(const State& y, double a, double a2, double L, double h) {
     double s, c;
     sincos_bounded(y.th, &s, &c);
-    return rhs_sc(y, clamp_sin(s), c, a, a2, L);
+    return rhs_sc(y, clamp_sin(s), c, a, a2, L, h);
 }
 
-__device__ __forceinline__ State axpy(const State& y, double h, const State& k) {
-    return State{y.r + h * k.r, y.th + h * k.th, y.ph + h * k.ph, y.t + h * k.t, y.pr + h * k.pr, y.pth + h * k.pth};
-}
+// y + sum(w_i k_i) componentwise (k_i already scaled by h), written out per field.
+#define KGRT_STAGE(OUT, Y, EXPR_R, EXPR_TH, EXPR_PH, EXPR_T, EXPR_PR, EXPR_PTH)                                 \
+    State OUT{(Y).r + (EXPR_R), (Y).th + (EXPR_TH), (Y).ph + (EXPR_PH), (Y).t + (EXPR_T), (Y).pr + (EXPR_PR), \
+              (Y).pth + (EXPR_PTH)}
 
-// y + h * sum(w_i k_i) componentwise, written out per field.
-#define KGRT_STAGE(OUT, Y, H, EXPR_R, EXPR_TH, EXPR_PH, EXPR_T, EXPR_PR, EXPR_PTH) \
-    State OUT{(Y).r + (H) * (EXPR_R), (Y).th + (H) * (EXPR_TH), (Y).ph + (H) * (EXPR_PH), (Y).t + (H) * (EXPR_T), \
-              (Y).pr + (H) * (EXPR_PR), (Y).pth + (H) * (EXPR_PTH)}
-
-// One Cash-Karp step of size h from y with k1 = f(y): fifth-order result in
-// y5, embedded error estimate (y5 - y4) in err. Five RHS evaluations.
+// One Cash-Karp step of size h from y with k1 = h f(y): fifth-order result in
+// y5, embedded error estimate (y5 - y4) in err. Five RHS evaluations, each
+// returning h f at its stage point.
 __device__ __forceinline__ void cash_karp(const State& y, const State& k1, double h, double a, double a2, double L,
                                           State& y5, State& err) {
     using namespace ck;
 #define S2(f) (a21 * k1.f)
-    KGRT_STAGE(y2, y, h, S2(r), S2(th), S2(ph), S2(t), S2(pr), S2(pth));
+    KGRT_STAGE(y2, y, S2(r), S2(th), S2(ph), S2(t), S2(pr), S2(pth));
 #undef S2
-    const State k2 = rhs(y2, a, a2, L);
+    const State k2 = rhs(y2, a, a2, L, h);
 #define S3(f) (a31 * k1.f + a32 * k2.f)
-    KGRT_STAGE(y3, y, h, S3(r), S3(th), S3(ph), S3(t), S3(pr), S3(pth));
+    KGRT_STAGE(y3, y, S3(r), S3(th), S3(ph), S3(t), S3(pr), S3(pth));
 #undef S3
-    const State k3 = rhs(y3, a, a2, L);
+    const State k3 = rhs(y3, a, a2, L, h);
 #define S4(f) (a41 * k1.f + a42 * k2.f + a43 * k3.f)
-    KGRT_STAGE(y4, y, h, S4(r), S4(th), S4(ph), S4(t), S4(pr), S4(pth));
+    KGRT_STAGE(y4, y, S4(r), S4(th), S4(ph), S4(t), S4(pr), S4(pth));
 #undef S4
-    const State k4 = rhs(y4, a, a2, L);
+    const State k4 = rhs(y4, a, a2, L, h);
 #define S5(f) (a51 * k1.f + a52 * k2.f + a53 * k3.f + a54 * k4.f)
-    KGRT_STAGE(y5s, y, h, S5(r), S5(th), S5(ph), S5(t), S5(pr), S5(pth));
+    KGRT_STAGE(y5s, y, S5(r), S5(th), S5(ph), S5(t), S5(pr), S5(pth));
 #undef S5
-    const State k5 = rhs(y5s, a, a2, L);
+    const State k5 = rhs(y5s, a, a2, L, h);
 #define S6(f) (a61 * k1.f + a62 * k2.f + a63 * k3.f + a64 * k4.f + a65 * k5.f)
-    KGRT_STAGE(y6s, y, h, S6(r), S6(th), S6(ph), S6(t), S6(pr), S6(pth));
+    KGRT_STAGE(y6s, y, S6(r), S6(th), S6(ph), S6(t), S6(pr), S6(pth));
 #undef S6
-    const State k6 = rhs(y6s, a, a2, L);
+    const State k6 = rhs(y6s, a, a2, L, h);
 #define B5(f) (b1 * k1.f + b3 * k3.f + b4 * k4.f + b6 * k6.f)
-    y5 = State{y.r + h * B5(r), y.th + h * B5(th), y.ph + h * B5(ph), y.t + h * B5(t), y.pr + h * B5(pr),
-               y.pth + h * B5(pth)};
+    KGRT_STAGE(yo, y, B5(r), B5(th), B5(ph), B5(t), B5(pr), B5(pth));
+    y5 = yo;
 #undef B5
-#define DE(f) (h * (d1 * k1.f + d3 * k3.f + d4 * k4.f + d5 * k5.f + d6 * k6.f))
+#define DE(f) (d1 * k1.f + d3 * k3.f + d4 * k4.f + d5 * k5.f + d6 * k6.f)
     err = State{DE(r), DE(th), DE(ph), DE(t), DE(pr), DE(pth)};
 #undef DE
 }
