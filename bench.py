@@ -43,8 +43,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # divergence-free run (every lane traces the same ray), see
 # profiles/trace_kernel_flop_calibration.md (the thin-disk figure, from three disk
 # rays, also serves the projection workload, which runs the same kernel).
-FLOPS_PER_ATTEMPT = {"torus": (1350.0, "calibrated"), "thin_disk": (908.0, "calibrated"),
-                     "projection": (908.0, "calibrated")}
+FLOPS_PER_ATTEMPT = {"torus": (1294.0, "calibrated"), "thin_disk": (852.0, "calibrated"),
+                     "projection": (852.0, "calibrated")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
@@ -53,9 +53,9 @@ FLOPS_PER_ATTEMPT = {"torus": (1350.0, "calibrated"), "thin_disk": (908.0, "cali
 # VALU lane utilisation of the dominant kernel on the 1024^2 torus image (useful
 # FP64 FLOPs / FP64 lane slots issued, rocprofv3 counters), valid for the sources it
 # was taken on; see profiles/trace_kernel_flop_calibration.md.
-LANE_UTILISATION = {"torus": {"value": 0.875, "source_md5": "05b08bb51d030b7cf88cef8428ee6314"}}
+LANE_UTILISATION = {"torus": {"value": 0.872, "source_md5": "a24dd3904ef3dc5796fe5daba1ed1e5b"}}
 
-TRAFFIC = {"torus": {"bytes": 492080704, "source_md5": "05b08bb51d030b7cf88cef8428ee6314"}}
+TRAFFIC = {"torus": {"bytes": 490228960, "source_md5": "a24dd3904ef3dc5796fe5daba1ed1e5b"}}
 
 
 def kernel_source_md5() -> str:
