@@ -445,8 +445,9 @@ constexpr double kCheb[23] = {
 };
 }  // namespace k2
 
-// lnh = ln(x/2), which the caller has from the logarithm it already takes.
-__device__ inline double bessel_k2(double x, double lnh) {
+// lnh = ln(x/2), which the caller has from the logarithm it already takes;
+// ix = 1/x, which the caller also has without a division.
+__device__ inline double bessel_k2(double x, double ix, double lnh) {
     if (x <= 2.0) {
         const double q = 0.25 * x * x;
         const double lg = lnh + kEulerGamma;
@@ -457,9 +458,9 @@ __device__ inline double bessel_k2(double x, double lnh) {
         KGRT_K2_TERM(11) KGRT_K2_TERM(10) KGRT_K2_TERM(9) KGRT_K2_TERM(8) KGRT_K2_TERM(7) KGRT_K2_TERM(6)
         KGRT_K2_TERM(5) KGRT_K2_TERM(4) KGRT_K2_TERM(3) KGRT_K2_TERM(2) KGRT_K2_TERM(1) KGRT_K2_TERM(0)
 #undef KGRT_K2_TERM
-        return fma(q, fma(-lg, pc, pb), fma(0.5, fm::rcp(q), -0.5));
+        return fma(q, fma(-lg, pc, pb), fma(2.0 * ix, ix, -0.5));  // 1/(2q) = 2/x^2
     }
-    const double s = fma(4.0, fm::rcp(x), -1.0);
+    const double s = fma(4.0, ix, -1.0);
     const double s2 = 2.0 * s;
     double b1 = 0.0, b2 = 0.0;
 #pragma unroll
@@ -508,7 +509,8 @@ __device__ inline Plasma torus_plasma(const TorusParams& P, double r, double cth
     q.Te = P.T0 * eT;
     const double eT2 = eT * eT;
     q.inv_nu_c = fm::rsqrt(P.cNuC * q.ne * (eT2 * eT2) * fm::rcp(r));  // 1/(cNu B Theta_e^2)
-    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT * P.cInvTheta, fma(P.T_index, lx, P.cLnHalfInvTheta)));
+    // K_2 at x = 1/Theta_e: 1/x = Theta_e = cTheta T_e/T0
+    q.jpref = q.ne * P.cJ * fm::rcp(bessel_k2(ieT * P.cInvTheta, P.cTheta * eT, fma(P.T_index, lx, P.cLnHalfInvTheta)));
     q.hkT = P.cH * ieT;
     return q;
 }

@@ -61,6 +61,9 @@ def test_forward_matches_reference(ctx):
     # rows are independent: a prefix evaluated alone gives the same bits
     y2 = mlp.forward(xd[:300].contiguous()).cpu().numpy()
     assert np.array_equal(y2, y[:300])
+    # a single row and a tile that is mostly empty
+    for m in (1, 17):
+        assert np.array_equal(mlp.forward(xd[:m].contiguous()).cpu().numpy(), y[:m])
     assert np.array_equal(mlp.get_params(), p)
     mlp.close()
 
