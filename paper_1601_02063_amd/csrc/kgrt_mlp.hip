@@ -1,19 +1,21 @@
 // kgrt_mlp.hip -- the learned surrogate: a 4-256-256-256-256-5 SiLU perceptron
-// trained and evaluated by hand-written kernels (BF16 MFMA with FP32
-// accumulation for the three 256x256 layers, FP32 VALU for the 4-wide input
-// layer and the 5-wide output head), plus Adam.
+// trained and evaluated by hand-written kernels on v_mfma_f32_16x16x32_bf16
+// (BF16 operands, FP32 accumulation; the 4-wide input layer and the 5-wide
+// output head also run on MFMA, with their FP32 operands split into BF16
+// hi + lo parts), plus Adam, and the surrogate renderer with its fallback to
+// the FP64 integrator.
 //
-// Layouts. Activations are batch-major [B][256] BF16. The 256x256 products run
-// as out[b][n] = sum_k A[b][k] Bt[n][k] on v_mfma_f32_16x16x32_bf16 with the
-// MFMA's row index on n and its column index on b, so both operands are read
-// K-contiguous and each lane's four accumulators are four consecutive n of one
-// b (one 8-byte store). The weight-gradient products contract over the batch,
-// so the forward and backward epilogues also write feature-major copies
-// [256][B] of the layer inputs and of dL/dz.
+// Inference (mlp_infer_rows) is row-parallel: a wave keeps its rows'
+// activations in registers through all layers, and the weights come as MFMA
+// fragments in a permuted order that lets one layer's accumulators serve as
+// the next layer's operand directly. Training (train_fwd, train_bwd,
+// train_dw) works on 64-sample tiles with the activations in LDS and stores
+// per-sample arrays tile-major for the weight-gradient products, which
+// contract over the batch.
 //
 // Parameters: one flat FP32 vector, per layer W[out][in] then b[out] (the FP32
-// master copy); BF16 copies of W2..W4 in [out][in] (forward) and [in][out]
-// (input gradients) are refreshed after every update.
+// master copy); the BF16 copies and fragment arrays derived from it are
+// refreshed after every update.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,18 +40,18 @@ constexpr int64_t kW3 = kB2 + kH, kB3 = kW3 + kH * kH;
 constexpr int64_t kW4 = kB3 + kH, kB4 = kW4 + kH * kH;
 constexpr int64_t kW5 = kB4 + kH, kB5 = kW5 + kOut * kH;
 constexpr int64_t kNumParams = kB5 + kOut;  // 199941
-// the packed BF16 weights Wf: W2..W4 [3][out][in], then W5 split into hi and lo
-// parts [2][16][256] twice: scaled for inference (see below) and unscaled for training
-constexpr int64_t kW5Split = 3 * kH * kH, kW5Rows = 16;
-constexpr int64_t kW5SplitU = kW5Split + 2 * kW5Rows * kH;
+// the packed BF16 weights of the training kernels, Wf: W2..W4 [3][out][in], then
+// W5 split into hi and lo parts [2][16][256] (outputs 5..15 zero)
+constexpr int64_t kW5SplitU = 3 * kH * kH, kW5Rows = 16;
 constexpr int64_t kWfSize = kW5SplitU + 2 * kW5Rows * kH;
 // Inference folds the base-2 exponential's scale c = log2(e) into the weights:
 // with W1, b1..b4 scaled by -c and W5 by -1/c, every hidden layer computes
 // ht = -c SiLU(z) directly from zt = -c z as zt / (1 + 2^zt) (W2..W4 are
-// unchanged, since -c cancels between consecutive layers). The scaled FP32 W1
-// [256][4] and biases [4][256] live in a small buffer Pi.
+// unchanged, since -c cancels between consecutive layers). The scaled FP32
+// biases [4][256] live in a small buffer Pi, the scaled W1 and W5 in the
+// inference kernel's fragment array.
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr int64_t kPiW1 = 0, kPiB = kH * kIn, kPiSize = kPiB + 4 * kH;
+constexpr int64_t kPiB = 0, kPiSize = 4 * kH;
 constexpr float kWCap = 1.0f, kWLogR = 10.0f, kWG = 10.0f, kWPhi = 1.0f;
 
 // sigmoid with the hardware base-2 exponential and reciprocal (about 1 ulp
@@ -650,31 +652,24 @@ __global__ void __launch_bounds__(256) adam(float* __restrict__ P, float* __rest
     }
 }
 
-// BF16 copies of W2..W4: Wf[l][out][in] (forward) and Wb[l][in][out] (input
-// gradients); after them in Wf, W5 as two BF16 parts hi + lo of 16 x 256
-// (outputs 5..15 zero) for the inference kernel's output head.
+// For the training kernels, BF16 copies of W2..W4: Wf[l][out][in] (forward) and
+// Wb[l][in][out] (input gradients); after them in Wf, W5 as two BF16 parts
+// hi + lo of 16 x 256 (outputs 5..15 zero) for the output head. For inference,
+// the scaled biases in Pi.
 __global__ void __launch_bounds__(256) pack_weights(const float* __restrict__ P, __bf16* __restrict__ Wf,
                                                     __bf16* __restrict__ Wb, float* __restrict__ Pi) {
-    const int l = blockIdx.y;  // 0..2 -> W2..W4, 3 -> W5 split, 4 -> scaled W1 and biases
+    const int l = blockIdx.y;  // 0..2 -> W2..W4, 3 -> W5 split, 4 -> scaled biases
     if (l == 4) {
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kPiSize; i += gridDim.x * blockDim.x) {
-            if (i < kPiB) {
-                Pi[i] = -kLog2e * P[kW1 + i];
-            } else {
-                const int layer = (i - kPiB) / kH, u = (i - kPiB) % kH;
-                const int64_t off = layer == 0 ? kB1 : (layer == 1 ? kB2 : (layer == 2 ? kB3 : kB4));
-                Pi[i] = -kLog2e * P[off + u];
-            }
+            const int layer = (i - kPiB) / kH, u = (i - kPiB) % kH;
+            const int64_t off = layer == 0 ? kB1 : (layer == 1 ? kB2 : (layer == 2 ? kB3 : kB4));
+            Pi[i] = -kLog2e * P[off + u];
         }
         return;
     }
     if (l == 3) {
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kW5Rows * kH; i += gridDim.x * blockDim.x) {
             const int o = i / kH;
-            const float w = (o < kOut) ? -P[kW5 + i] / kLog2e : 0.0f;
-            const __bf16 hi = (__bf16)w;
-            Wf[kW5Split + i] = hi;
-            Wf[kW5Split + kW5Rows * kH + i] = (__bf16)(w - (float)hi);
             const float wu = (o < kOut) ? P[kW5 + i] : 0.0f;
             const __bf16 hu = (__bf16)wu;
             Wf[kW5SplitU + i] = hu;
