@@ -194,6 +194,18 @@ def test_torus_multifrequency_ragged(ctx):
     compare_torus(g, o, 8, "torus 8 freqs")
 
 
+@pytest.mark.parametrize("nf", [2, 3, 12])
+def test_torus_frequency_counts(ctx, nf):
+    """Every compiled frequency width (2, 4 and 16 slots, partly filled) against the oracle."""
+    import oracle as O
+    freqs = [86e9 * (690.0 / 86.0) ** (k / max(nf - 1, 1)) for k in range(nf)]
+    w = scenes.torus_image(11, a=0.9, incl_deg=40.0, freqs=freqs)
+    w["camera"]["ny"] = 7
+    g = run_gpu(ctx, w)
+    o = O.trace_image(oracle_scene(w), 11, 7, -20, 20, -20, 20).ravel()
+    compare_torus(g, o, nf, f"torus {nf} freqs")
+
+
 def test_torus_full_resolution_sampled(ctx):
     """The benchmark configuration (1024^2) in its launch shape; the oracle
     recomputes a seeded sample of pixels one by one."""
