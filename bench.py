@@ -43,7 +43,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # divergence-free run (every lane traces the same ray), see
 # profiles/trace_kernel_flop_calibration.md (the thin-disk figure, from three disk
 # rays, also serves the projection workload, which runs the same kernel).
-FLOPS_PER_ATTEMPT = {"torus": (1294.0, "calibrated"), "thin_disk": (852.0, "calibrated"),
+FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "calibrated"),
                      "projection": (852.0, "calibrated")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -53,9 +53,9 @@ FLOPS_PER_ATTEMPT = {"torus": (1294.0, "calibrated"), "thin_disk": (852.0, "cali
 # VALU lane utilisation of the dominant kernel on the 1024^2 torus image (useful
 # FP64 FLOPs / FP64 lane slots issued, rocprofv3 counters), valid for the sources it
 # was taken on; see profiles/trace_kernel_flop_calibration.md.
-LANE_UTILISATION = {"torus": {"value": 0.872, "source_md5": "a24dd3904ef3dc5796fe5daba1ed1e5b"}}
+LANE_UTILISATION = {"torus": {"value": 0.875, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
 
-TRAFFIC = {"torus": {"bytes": 490228960, "source_md5": "a24dd3904ef3dc5796fe5daba1ed1e5b"}}
+TRAFFIC = {"torus": {"bytes": 490773120, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
 
 
 def kernel_source_md5() -> str:

@@ -157,12 +157,13 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 
 // Waves per SIMD the register allocation targets, per model and number of
 // frequencies carried (measured on MI355X, with the build's machine-LICM
-// setting for this file): the one-frequency transfer kernel (133 VGPRs) and the
-// thin disk (161) run fastest at three waves without spills; the
-// eight-frequency kernel (192 VGPRs) at two (three would spill, one wave is
-// 35% slower).
+// setting for this file). The one-frequency torus kernel and the thin-disk and
+// projection kernels run fastest at four waves: the register budget of 128
+// costs them a few spilled words (the disk kernel, 157 VGPRs at three waves,
+// spills 128 B at four and is still 3.5% faster). The eight-frequency kernel
+// (192 VGPRs) runs at two (three would spill, one wave is 35% slower).
 #ifndef KGRT_WAVES_DISK
-#define KGRT_WAVES_DISK 3
+#define KGRT_WAVES_DISK 4
 #endif
 #ifndef KGRT_WAVES_TORUS
 #define KGRT_WAVES_TORUS 4
@@ -192,11 +193,12 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
     double h = 0.0, a = 0.0, a2 = 0.0, L = 0.0, r_cap = 0.0, r_in = 0.0, r_obs = 0.0;
     // sin(theta) (clamped, section 2.1) and cos(theta) of y, computed once per
     // point and shared by the first RHS stage, the redshift, the plasma and the
-    // crossing test; for the crossing-tracking models also those of y_k
+    // crossing test; syk, cyk those of the parked y_k+1 while a crossing is refined
     double sy = 0.0, cy = 0.0, syk = 0.0, cyk = 0.0;
     int32_t steps = 0, attempts = 0, status = 0;
     // crossing refinement (thin disk / geodesic): Newton iteration on the
-    // step size from y_k, run in lockstep with the other lanes' attempts
+    // step size from y_k, run in lockstep with the other lanes' attempts; the
+    // accepted y_k+1 and the next adaptive step wait in yk and hs meanwhile
     bool crossed = false, refine = false;
     int32_t rit = 0;
     double hs = 0.0;
@@ -289,14 +291,15 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
         if (__ballot(active || !done) == 0ull) break;
         if (!active) continue;
 
-        // ---- one Cash-Karp evaluation (section 2.1): an adaptive attempt from
-        // y, or, for a lane refining a crossing, a fixed step of size hs from y_k
+        // ---- one Cash-Karp evaluation (section 2.1) of size h from y: an adaptive
+        // attempt, or, for a lane refining a crossing, a Newton trial step from y_k
+        // (while refining, y holds y_k, yk holds the accepted y_k+1 and hs the next
+        // adaptive step, so every lane starts from y with step h and no state is
+        // selected per lane)
         bool terminate = false;
-        const State yb = (kDisk && refine) ? yk : y;
-        const double hb = (kDisk && refine) ? hs : h;
-        const State k1 = rhs_sc(yb, (kDisk && refine) ? syk : sy, (kDisk && refine) ? cyk : cy, a, a2, L, hb);
+        const State k1 = rhs_sc(y, sy, cy, a, a2, L, h);
         State yn, ye;
-        cash_karp(yb, k1, hb, a, a2, L, yn, ye);
+        cash_karp(y, k1, h, a, a2, L, yn, ye);
         bool check_end = false;
 
         if (kDisk && refine) {
@@ -326,11 +329,15 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     if (O.i_bol) O.i_bol[rid] = Ib;
                     if (P.flags & KGRT_STOP_AT_CROSSING) terminate = true;
                 }
-                // the accepted y_k+1 still has to pass the end-of-step tests
+                // back to the accepted y_k+1, which still has to pass the end-of-step tests
+                y = yk;
+                sy = syk;
+                cy = cyk;
+                h = hs;
                 check_end = !terminate;
             } else {
                 const double thdot = yn.pth / (yn.r * yn.r + a2 * cz * cz);
-                hs = hs + cz / (sz * thdot);
+                h = h + cz / (sz * thdot);
             }
         } else {
             ++attempts;
@@ -360,19 +367,33 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                 const double hdone = h;
                 double hnext = (errmax > 1.89e-4) ? h * (0.9 * fm::pow_m02(errmax)) : h * 5.0;
                 ++steps;
-                if (kDisk) {
-                    yk = y;
-                    syk = sy;
-                    cyk = cy;
-                }
                 const double c0 = cy;  // cos(theta) at y_k
-                y = yn;
-                sincos_bounded(y.th, &sy, &cy);
-                sy = clamp_sin(sy);
-                if (!finite6(y)) {
+                double sn, cn;
+                sincos_bounded(yn.th, &sn, &cn);
+                sn = clamp_sin(sn);
+                bool start_refine = false;
+                if (!finite6(yn)) {
+                    y = yn;
                     status |= ST_NONFINITE;
                     terminate = true;
+                } else if (kDisk && !crossed && ((c0 > 0.0 && cn <= 0.0) || (c0 < 0.0 && cn >= 0.0))) {
+                    // first equatorial crossing inside this step: park y_k+1 and refine from
+                    // y_k over the next evaluations, starting from linear interpolation of cos(theta)
+                    crossed = true;
+                    refine = true;
+                    start_refine = true;
+                    rit = 0;
+                    yk = yn;
+                    syk = sn;
+                    cyk = cn;
+                    const double hcap = P.hmax_frac * yn.r;
+                    hs = (hnext > hcap) ? hcap : hnext;
+                    h = hdone * c0 / (c0 - cn);
                 } else {
+                    y = yn;
+                    sy = sn;
+                    cy = cn;
+                    check_end = true;
                     if (MODEL == KGRT_MODEL_TORUS) {
                         // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
                         // each accepted endpoint, exponential-trapezoid increment
@@ -395,24 +416,13 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                                 ep[f] = e1;
                             }
                         }
-                        check_end = true;
-                    } else {
-                        const double c1 = cy;
-                        if (!crossed && ((c0 > 0.0 && c1 <= 0.0) || (c0 < 0.0 && c1 >= 0.0))) {
-                            // first equatorial crossing inside this step: refine it over the
-                            // next evaluations, starting from linear interpolation of cos(theta)
-                            crossed = true;
-                            refine = true;
-                            rit = 0;
-                            hs = hdone * c0 / (c0 - c1);
-                        } else {
-                            check_end = true;
-                        }
                     }
                 }
-                const double hcap = P.hmax_frac * y.r;
-                if (hnext > hcap) hnext = hcap;
-                h = hnext;
+                if (!start_refine) {
+                    const double hcap = P.hmax_frac * y.r;
+                    if (hnext > hcap) hnext = hcap;
+                    h = hnext;
+                }
             }
         }
         if (check_end) {
