@@ -64,7 +64,8 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 // buffer (64 x 256 BF16, rows padded by 8 elements against bank conflicts); a
 // wave computes 16 RI rows x 16 UJ units of a layer (RI x UJ MFMA tiles, so
 // each weight fragment serves RI row tiles); the block has (4 / RI) x
-// (16 / UJ) waves.
+// (16 / UJ) waves. Both passes fit two blocks per CU (four waves per SIMD), so
+// one block's MFMA work overlaps the other's element-wise phases and barriers.
 constexpr int kTileRows = 64, kLdsStride = kH + 8;
 #ifndef KGRT_MLP_RI
 #define KGRT_MLP_RI 4
@@ -283,7 +284,7 @@ struct TrainBufs {
 };
 
 template <int RI, int UJ>
-__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(3, 3)))
+__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
 train_fwd(const float* __restrict__ x, const int32_t* __restrict__ idx, const float* __restrict__ t, int64_t n,
           const float* __restrict__ P, const __bf16* __restrict__ Wf, const TrainBufs B) {
     constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
@@ -544,12 +545,20 @@ train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t 
             for (int i = 0; i < RI; ++i)
 #pragma unroll
                 for (int j = 0; j < UJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            // the weight fragments of step s + 1 load while step s multiplies
+            bf16x8 afn[UJ];
+#pragma unroll
+            for (int j = 0; j < UJ; ++j) afn[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + 8 * lg);
 #pragma unroll 1
             for (int s = 0; s < kH / 32; ++s) {
                 const int k = 32 * s + 8 * lg;
+                const int kn = 32 * (s + 1 < kH / 32 ? s + 1 : s) + 8 * lg;
                 bf16x8 af[UJ], bfg[RI];
 #pragma unroll
-                for (int j = 0; j < UJ; ++j) af[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + k);
+                for (int j = 0; j < UJ; ++j) {
+                    af[j] = afn[j];
+                    afn[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + kn);
+                }
 #pragma unroll
                 for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
 #pragma unroll
@@ -589,8 +598,15 @@ train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t 
 
 // Partial dW_L over one row chunk: block (column group cg of 64 input units,
 // chunk, layer L - 2), 4 waves of 64 output units x 64 input units each.
+// Blocks go to the eight XCDs in turn (block b to XCD b mod 8); the four
+// column groups of one (layer, chunk) read the same dz rows, so they take four
+// consecutive block slots of one XCD and share its L2.
+constexpr int kDwBlocks = 3 * kDwChunks * (kH / 64);
+static_assert(kH / 64 == 4 && kDwBlocks % 32 == 0, "train_dw block mapping");
 __global__ void __launch_bounds__(256) train_dw(const TrainBufs B, int64_t n, float* __restrict__ part) {
-    const int li = blockIdx.z, chunk = blockIdx.y, cg = blockIdx.x;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int cg = slot & 3, pair = (slot >> 2) * 8 + xcd;
+    const int li = pair / kDwChunks, chunk = pair % kDwChunks;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const int64_t per = (((n + kDwChunks - 1) / kDwChunks) + 31) / 32 * 32;
@@ -1170,7 +1186,7 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
                        idx, t, n, m->P, m->Wf, tb);
     hipLaunchKernelGGL(kb, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pb)), dim3(kTrainThreads), 0, st, x,
                        idx, n, m->P, m->Wb, tb, m->G);
-    hipLaunchKernelGGL(train_dw, dim3(kH / 64, kDwChunks, 3), dim3(256), 0, st, tb, n, m->part);
+    hipLaunchKernelGGL(train_dw, dim3(kDwBlocks), dim3(256), 0, st, tb, n, m->part);
     hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
     if (grads && hipMemcpyAsync(grads, m->G, kNumParams * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return mlp_fail(m, KGRT_E_HIP, "gradient copy failed");
