@@ -484,13 +484,31 @@ train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t 
     // L >= 2, feature-major to global
     auto column = [&](int L, int64_t row0) {
         const int rbeg = ch * RPT;
+        // the thread's SiLU'(z) (and, for L = 4, h) loads are all issued before
+        // the first is used; the rows are then processed in a loop that is not
+        // unrolled (unrolled, its LDS reads are hoisted and spill)
+        bf16x8 svq[RPT / 8], hvq[RPT / 8];
+#pragma unroll
+        for (int q = 0; q < RPT / 8; ++q) {
+            const int64_t b8 = row0 + rbeg + 8 * q;
+            svq[q] = bf16x8{};
+            hvq[q] = bf16x8{};
+            if (b8 < n) {
+                svq[q] = *reinterpret_cast<const bf16x8*>(B.sT[L - 1] + tm_index(cu, b8));
+                if (L == 4) hvq[q] = *reinterpret_cast<const bf16x8*>(B.hT[3] + tm_index(cu, b8));
+            }
+        }
+#pragma unroll 1
         for (int q = 0; q < RPT / 8; ++q) {
             const int r8 = rbeg + 8 * q;
             const int64_t b8 = row0 + r8;
             if (b8 >= n) break;  // n is a multiple of 32: groups of 8 rows are whole
-            const bf16x8 sv = *reinterpret_cast<const bf16x8*>(B.sT[L - 1] + tm_index(cu, b8));
-            bf16x8 hv{};
-            if (L == 4) hv = *reinterpret_cast<const bf16x8*>(B.hT[3] + tm_index(cu, b8));
+            const bf16x8 sv = svq[0], hv = hvq[0];
+#pragma unroll
+            for (int k = 0; k + 1 < RPT / 8; ++k) {
+                svq[k] = svq[k + 1];
+                hvq[k] = hvq[k + 1];
+            }
             bf16x8 out;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
