@@ -314,6 +314,25 @@ def bench_batch(ctx, args, dev):
         line["roofline"] = {"bound": "alu", "achieved": round(ach, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
                             "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
                             "flops_per_attempt": fpa, "flops_basis": basis, "kernel": "trace_kernel<torus,8>"}
+    # spectra of the batch: flux density of every image at every frequency, seen from 8 kpc
+    # (one read of each intensity: an HBM-bound reduction)
+    dom = torch.tensor([K.pixel_solid_angle(c, mod.mbh_msun, SPECTRA_DISTANCE_CM) for c in cams],
+                       dtype=torch.float64, device=dev)
+    flux = plan.spectra(out["intensity"], dom, stream)
+    torch.cuda.synchronize()
+    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for s, e in sev:
+        s.record(stream)
+        flux = plan.spectra(out["intensity"], dom, stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    sms = sum(s.elapsed_time(e) for s, e in sev) / len(sev)
+    sbytes = plan.num_rays * len(freqs) * 8
+    sgbs = sbytes / (sms * 1e-3) / 1e9
+    line["spectra"] = {"ms": round(sms, 4), "kernel": "spectra_kernel", "bound": "hbm",
+                       "achieved": round(sgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(sgbs / HBM_PEAK_GBS, 4), "bytes": sbytes,
+                       "total_flux_cgs": [float(v) for v in flux.sum(0).cpu()]}
     if args.baselines:
         for label, mode in (("per_image_persistent", K.LAUNCH_PERSISTENT),
                             ("per_image_one_ray_per_thread", K.LAUNCH_ONE_RAY_PER_THREAD)):
@@ -334,6 +353,8 @@ def bench_batch(ctx, args, dev):
     print(json.dumps(line), flush=True)
 
 
+SPECTRA_DISTANCE_CM = 8.0 * 3.0856775814913673e21  # 8 kpc
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MLP_TRAIN_MFMA_FLOPS = 3 * 3 * 2 * 256 * 256  # per sample: forward, input- and weight-gradient of the 256x256 layers
 MLP_FWD_FLOPS = 397824  # per sample, all layers
 BF16_DENSE_PEAK_TFLOPS = 2500.0

@@ -211,6 +211,35 @@ int kgrt_trace_batch(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const
                      const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out,
                      void* stream);
 
+/* ------------------------------------------------------------- spectra */
+
+/* Flux density of each image at each frequency, the spectra of section 4:
+ * F_nu = sum over the image's pixels of I_nu times the solid angle of one
+ * pixel. The intensities are laid out as the torus outputs of a plan,
+ * intensity[f * total + i] for frequency f < nfreq and ray i < total, and
+ * image k owns rays [offsets[k], offsets[k + 1]) (a plan's offsets are the
+ * prefix sums of its image sizes). Writes
+ *   flux[k * nfreq + f] = domega[k] * sum_{i in image k} intensity[f * total + i]
+ * (erg s^-1 cm^-2 Hz^-1 for intensities in erg s^-1 cm^-2 Hz^-1 sr^-1 and
+ * domega in sr, see kgrt_pixel_solid_angle).
+ * Arguments: device arrays intensity [nfreq][total] (read; may be NULL when
+ * total == 0), offsets [nimg + 1] int64 and domega [nimg] (read), flux
+ * [nimg][nfreq] (written); the caller owns all of them. Each image's range is
+ * clamped to [0, total] on the device, so offsets outside it read nothing
+ * (an empty or reversed range gives 0). Every sum is taken in a fixed order
+ * (per-thread strided partial sums, then a fixed tree), so repeated calls give
+ * identical results. Asynchronous on `stream`. Returns KGRT_E_INVALID_ARG for
+ * nimg < 0 or > 65535, nfreq < 1, total < 0 or a NULL array that would be
+ * read or written; nimg == 0 does nothing. */
+int kgrt_image_spectra(const double* intensity_dev, int64_t total, int32_t nfreq, const int64_t* offsets_dev,
+                       const double* domega_dev, int32_t nimg, double* flux_dev, void* stream);
+/* Solid angle in sr of one pixel of cam seen from distance_cm (section 2.2:
+ * the image plane is flat, in units of M = r_g = G M_bh / c^2 with M_bh =
+ * mbh_msun solar masses): dx dy (r_g / distance_cm)^2 with dx, dy the pixel
+ * pitch in M. Host function. Returns -1 for a NULL camera, an empty image, a
+ * non-positive or non-finite extent, mass or distance. */
+double kgrt_pixel_solid_angle(const kgrt_camera* cam, double mbh_msun, double distance_cm);
+
 /* ----------------------------------------------------------- surrogate */
 
 /* A learned surrogate of the integrator: a perceptron 4 -> 256 -> 256 -> 256 -> 256 -> 5

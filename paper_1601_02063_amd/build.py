@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkgrt.so")
-SOURCES = [os.path.join(CSRC, "kgrt.hip"), os.path.join(CSRC, "kgrt_mlp.hip")]
+SOURCES = [os.path.join(CSRC, "kgrt.hip"), os.path.join(CSRC, "kgrt_mlp.hip"), os.path.join(CSRC, "kgrt_spectra.hip")]
 HEADERS = [os.path.join(CSRC, "kgrt_device.hpp"), os.path.join(ROOT, "include", "kgrt.h")]
 
 HIPCC_FLAGS = [

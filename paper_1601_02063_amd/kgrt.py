@@ -194,6 +194,9 @@ def lib() -> ctypes.CDLL:
                                           vp]
         L.kgrt_trace_rays_dev.restype = ctypes.c_int
         L.kgrt_critical_curve.argtypes, L.kgrt_critical_curve.restype = [d, d, vp, i32], ctypes.c_int
+        L.kgrt_image_spectra.argtypes = [vp, i64, i32, vp, vp, i32, vp, vp]
+        L.kgrt_image_spectra.restype = ctypes.c_int
+        L.kgrt_pixel_solid_angle.argtypes, L.kgrt_pixel_solid_angle.restype = [P(CCamera), d, d], d
         L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
         L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
@@ -365,6 +368,45 @@ class Plan:
     def set_launch(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0, mode: int = 0):
         self.ctx._check(lib().kgrt_plan_set_launch(self._h, ctypes.byref(CLaunch(block, blocks_per_cu,
                                                                                  refill_min, mode))))
+
+    def spectra(self, intensity: torch.Tensor, domega: torch.Tensor, stream=None) -> torch.Tensor:
+        """kgrt_image_spectra over this plan's images: flux density [nimg, nfreq] (float64, device)."""
+        if getattr(self, "_offsets_dev", None) is None:
+            self._offsets_dev = torch.tensor(self.offsets, dtype=torch.int64, device=self.ctx.device)
+        return image_spectra(intensity, self._offsets_dev, domega, stream)
+
+
+def image_spectra(intensity: torch.Tensor, offsets: torch.Tensor, domega: torch.Tensor,
+                  stream=None) -> torch.Tensor:
+    """kgrt_image_spectra: flux[k, f] = domega[k] * sum of intensity[f, offsets[k]:offsets[k+1]].
+
+    intensity: contiguous CUDA float64 [nfreq, total] (or [total] for one frequency); offsets:
+    contiguous CUDA int64 [nimg + 1]; domega: contiguous CUDA float64 [nimg]. Returns a new
+    CUDA float64 tensor [nimg, nfreq] written on `stream` (asynchronously)."""
+    I = intensity.unsqueeze(0) if intensity.dim() == 1 else intensity
+    if not (I.is_cuda and I.dtype == torch.float64 and I.is_contiguous() and I.dim() == 2):
+        raise ValueError("intensity must be a contiguous CUDA float64 tensor [nfreq, total]")
+    for t, dt, nm in ((offsets, torch.int64, "offsets"), (domega, torch.float64, "domega")):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.dim() == 1):
+            raise ValueError(f"{nm} must be a contiguous 1-D CUDA {dt} tensor")
+    nimg = domega.shape[0]
+    if offsets.shape[0] != nimg + 1:
+        raise ValueError("offsets must have nimg + 1 entries")
+    nfreq, total = I.shape
+    flux = torch.empty((nimg, nfreq), dtype=torch.float64, device=I.device)
+    rc = lib().kgrt_image_spectra(I.data_ptr() if total else None, total, nfreq, offsets.data_ptr(),
+                                  domega.data_ptr(), nimg, flux.data_ptr(), _stream_handle(stream))
+    if rc != OK:
+        raise KgrtError(rc, "kgrt_image_spectra failed")
+    return flux
+
+
+def pixel_solid_angle(camera: Camera, mbh_msun: float, distance_cm: float) -> float:
+    """kgrt_pixel_solid_angle: sr subtended by one pixel of `camera` at `distance_cm`."""
+    v = float(lib().kgrt_pixel_solid_angle(ctypes.byref(camera.c()), mbh_msun, distance_cm))
+    if v < 0.0:
+        raise ValueError("invalid camera, mass or distance")
+    return v
 
 
 def alloc_outputs(n: int, model: Model, nfreq: int, device, names: Iterable[str] = OUTPUT_FIELDS):

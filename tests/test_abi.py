@@ -151,3 +151,32 @@ def test_critical_curve_table_matches_parametrisation(K, a, inc):
     # bins hold the largest radius in their angular range: ~dR/dpsi x half a bin (< 0.01 M),
     # against a fallback band of 0.5 M
     assert np.median(d) < 1e-2 and d.max() < 2e-2, (np.median(d), d.max())
+
+
+def test_pixel_solid_angle_matches_oracle(K):
+    """Host function of the library against the oracle's definition (no GPU needed)."""
+    from oracle import spectra as S
+    for (nx, ny, ext, m, d) in [(1024, 1024, (-20.0, 20.0, -20.0, 20.0), 4e6, 2.4687e22),
+                                (64, 48, (-15.0, 15.0, -10.0, 12.0), 10.0, 3.0857e22)]:
+        cam = K.Camera(a=0.5, incl_deg=30.0, nx=nx, ny=ny, x_min=ext[0], x_max=ext[1], y_min=ext[2], y_max=ext[3])
+        got = K.pixel_solid_angle(cam, m, d)
+        assert got == pytest.approx(S.pixel_solid_angle(nx, ny, *ext, m, d), rel=1e-15)
+    bad = K.Camera(a=0.5, incl_deg=30.0, nx=0, ny=4)
+    with pytest.raises(ValueError):
+        K.pixel_solid_angle(bad, 4e6, 1e22)
+    with pytest.raises(ValueError):
+        K.pixel_solid_angle(K.Camera(a=0.5, incl_deg=30.0, nx=4, ny=4), 4e6, -1.0)
+
+
+def test_image_spectra_rejects_bad_arguments(K):
+    """Argument checks run on the host before any launch (no GPU needed)."""
+    L = K.lib()
+    dummy = ctypes.c_void_p(16)
+    assert L.kgrt_image_spectra(dummy, 10, 0, dummy, dummy, 1, dummy, None) == K.E_INVALID_ARG   # nfreq < 1
+    assert L.kgrt_image_spectra(dummy, -1, 1, dummy, dummy, 1, dummy, None) == K.E_INVALID_ARG   # total < 0
+    assert L.kgrt_image_spectra(dummy, 10, 1, dummy, dummy, -1, dummy, None) == K.E_INVALID_ARG  # nimg < 0
+    assert L.kgrt_image_spectra(dummy, 10, 1, dummy, dummy, 70000, dummy, None) == K.E_INVALID_ARG
+    assert L.kgrt_image_spectra(None, 10, 1, dummy, dummy, 1, dummy, None) == K.E_INVALID_ARG    # NULL intensity
+    assert L.kgrt_image_spectra(dummy, 10, 1, None, dummy, 1, dummy, None) == K.E_INVALID_ARG    # NULL offsets
+    assert L.kgrt_image_spectra(dummy, 10, 1, dummy, dummy, 1, None, None) == K.E_INVALID_ARG    # NULL flux
+    assert L.kgrt_image_spectra(None, 0, 1, None, None, 0, None, None) == K.OK                   # nothing to do

@@ -1,0 +1,71 @@
+"""Pins of the oracle's spectra (flux density per image and frequency, section 4).
+
+The sum is checked against closed forms a plausible slip would break: a
+separable geometric image (a wrong index, a dropped or extra pixel, an image
+range shifted by one, frequencies and images swapped all change it), a
+constant image, linearity, and the solid-angle bookkeeping (the pixels of an
+image add up to the solid angle of the whole image plane)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import spectra as S
+
+
+def geometric_batch(dims, freqs_scale, r=0.93, q=0.71):
+    """Images of nx x ny pixels with I[f][j nx + i] = c_f r^i q^j, concatenated."""
+    parts, offsets = [], [0]
+    for nx, ny in dims:
+        i = np.arange(nx)[None, :]
+        j = np.arange(ny)[:, None]
+        img = (r ** i) * (q ** j)
+        parts.append(img.ravel())
+        offsets.append(offsets[-1] + nx * ny)
+    base = np.concatenate(parts) if parts else np.zeros(0)
+    I = np.stack([c * base for c in freqs_scale])
+    return I, offsets
+
+
+def geometric_sum(nx, ny, r=0.93, q=0.71):
+    return (1 - r ** nx) / (1 - r) * (1 - q ** ny) / (1 - q)
+
+
+def test_geometric_images_closed_form():
+    dims = [(7, 5), (0, 0), (1, 1), (31, 17), (12, 40)]
+    cs = [1.0, 2.5e-3, 7.0e4]
+    I, off = geometric_batch(dims, cs)
+    dom = [1.0, 2.0, 3.0, 0.5, 1e-20]
+    F = S.image_spectra(I, off, dom)
+    assert F.shape == (len(dims), len(cs))
+    for k, (nx, ny) in enumerate(dims):
+        for f, c in enumerate(cs):
+            want = dom[k] * c * geometric_sum(nx, ny) if nx * ny else 0.0
+            assert F[k, f] == pytest.approx(want, rel=1e-14, abs=0.0), (k, f)
+
+
+def test_constant_image_and_linearity():
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 10000
+    I = np.full((2, n), 3.0)
+    F = S.image_spectra(I, [0, n], [0.25])
+    assert F[0, 0] == 0.25 * 3.0 * n and F[0, 1] == F[0, 0]
+    A = rng.uniform(0, 1, (3, 5000))
+    B = rng.uniform(0, 1, (3, 5000))
+    off, dom = [0, 1234, 5000], [1.0, 1.0]
+    FA, FB, FAB = (S.image_spectra(X, off, dom) for X in (A, B, 2 * A + B))
+    assert np.allclose(FAB, 2 * FA + FB, rtol=1e-14, atol=0)
+    # images are disjoint: the spectra of a batch add up to the spectrum of all rays
+    assert math.isclose(FA[:, 1].sum(), math.fsum(A[1]), rel_tol=1e-15)
+
+
+def test_pixel_solid_angles_cover_the_image_plane():
+    nx, ny, ext = 1024, 768, (-20.0, 20.0, -15.0, 15.0)
+    mbh, dist = 4e6, 8.0 * 3.0856775814913673e21  # Sgr A*-like: 4e6 solar masses (section 4.5) at 8 kpc
+    dom = S.pixel_solid_angle(nx, ny, *ext, mbh, dist)
+    rg = S.gravitational_radius_cm(mbh)
+    assert rg == pytest.approx(5.9065e11, rel=1e-4)  # G M / c^2 for 4e6 solar masses
+    whole = (ext[1] - ext[0]) * (ext[3] - ext[2]) * (rg / dist) ** 2
+    assert nx * ny * dom == pytest.approx(whole, rel=1e-14)
+    # halving the pitch quarters the pixel
+    assert S.pixel_solid_angle(2 * nx, 2 * ny, *ext, mbh, dist) == pytest.approx(dom / 4, rel=1e-15)
