@@ -42,9 +42,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # FP64 VALU instructions per attempt from rocprofv3 counters on a
 # divergence-free run (every lane traces the same ray), see
 # profiles/trace_kernel_flop_calibration.md (the thin-disk figure, from three disk
-# rays, also serves the projection workload, which runs the same kernel).
+# rays, also serves the projection workload, which runs the same kernel; the
+# batch figure is the eight-frequency torus kernel's, from the torus rays traced
+# at the batch's eight frequencies).
 FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "calibrated"),
-                     "projection": (852.0, "calibrated")}
+                     "projection": (852.0, "calibrated"), "batch": (2173.0, "calibrated")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
@@ -53,9 +55,13 @@ FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "cali
 # VALU lane utilisation of the dominant kernel on the 1024^2 torus image (useful
 # FP64 FLOPs / FP64 lane slots issued, rocprofv3 counters), valid for the sources it
 # was taken on; see profiles/trace_kernel_flop_calibration.md.
-LANE_UTILISATION = {"torus": {"value": 0.875, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
+LANE_UTILISATION = {"torus": {"value": 0.875, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"},
+                    "batch": {"value": 0.881, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
 
-TRAFFIC = {"torus": {"bytes": 490773120, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
+TRAFFIC = {"torus": {"bytes": 490773120, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"},
+           # all chunk launches of one plan launch of the 256-image batch, see
+           # profiles/batch256_trace_kernel_traffic.md
+           "batch": {"bytes": 21520900000, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
 
 
 def kernel_source_md5() -> str:
@@ -311,9 +317,13 @@ def bench_batch(ctx, args, dev):
     }
     if fpa:
         ach = fpa * attempts / (ms * 1e-3) / 1e12
+        tr = TRAFFIC.get("batch")
         line["roofline"] = {"bound": "alu", "achieved": round(ach, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                            "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                            "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 5),
+                            "traffic": tr["bytes"] if tr["source_md5"] == kernel_source_md5() else None,
                             "flops_per_attempt": fpa, "flops_basis": basis, "kernel": "trace_kernel<torus,8>"}
+        lu = LANE_UTILISATION.get("batch")
+        line["lane_utilisation"] = lu["value"] if lu["source_md5"] == kernel_source_md5() else None
     # spectra of the batch: flux density of every image at every frequency, seen from 8 kpc
     # (one read of each intensity: an HBM-bound reduction)
     dom = torch.tensor([K.pixel_solid_angle(c, mod.mbh_msun, SPECTRA_DISTANCE_CM) for c in cams],
