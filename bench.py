@@ -61,7 +61,9 @@ LANE_UTILISATION = {"torus": {"value": 0.875, "source_md5": "2e852ca6f923bf77f26
 TRAFFIC = {"torus": {"bytes": 490773120, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"},
            # all chunk launches of one plan launch of the 256-image batch, see
            # profiles/batch256_trace_kernel_traffic.md
-           "batch": {"bytes": 21520900000, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
+           "batch": {"bytes": 21520900000, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"},
+           # the 1024^2 thin-disk image, see profiles/trace_kernel_flop_calibration.md
+           "thin_disk": {"bytes": 1023473280, "source_md5": "2e852ca6f923bf77f2622bcd19ff01eb"}}
 
 
 def kernel_source_md5() -> str:
@@ -235,9 +237,11 @@ def main():
     fpa, basis = FLOPS_PER_ATTEMPT[args.workload]
     achieved = fpa * attempts / (ms_mean * 1e-3) / 1e12
     tr = TRAFFIC.get(args.workload)
-    traffic = tr["bytes"] if (tr and args.n in (None, 1024) and tr["source_md5"] == kernel_source_md5()) else None
+    traffic = tr["bytes"] if (tr and cam.nx == 1024 and cam.ny == 1024 and tr["source_md5"] == kernel_source_md5()) \
+        else None
     lu = LANE_UTILISATION.get(args.workload)
-    lane_util = lu["value"] if (lu and args.n in (None, 1024) and lu["source_md5"] == kernel_source_md5()) else None
+    lane_util = lu["value"] if (lu and cam.nx == 1024 and cam.ny == 1024 and lu["source_md5"] == kernel_source_md5()) \
+        else None
     kinfo = ctx.kernel_info(mod.kind, max(len(freqs), 1), args.block or 256)
     line = {
         "metric": METRIC,
