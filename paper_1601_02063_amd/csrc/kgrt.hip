@@ -161,7 +161,8 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 // projection kernels run fastest at four waves: the register budget of 128
 // costs them a few spilled words (the disk kernel, 157 VGPRs at three waves,
 // spills 128 B at four and is still 3.5% faster). The eight-frequency kernel
-// (192 VGPRs) runs at two (three would spill, one wave is 35% slower).
+// keeps its per-frequency sums in LDS and runs at three (below); the 2-, 4-
+// and 16-frequency kernels (143 to 256 VGPRs) at two (one wave is 35% slower).
 #ifndef KGRT_WAVES_DISK
 #define KGRT_WAVES_DISK 4
 #endif
@@ -171,10 +172,21 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 #ifndef KGRT_WAVES_TORUS_MULTI
 #define KGRT_WAVES_TORUS_MULTI 2
 #endif
+// The eight-frequency kernel keeps each thread's optical depths, intensities
+// and attenuations in LDS (three slots per frequency, 48 KB per 256-thread
+// block) instead of VGPRs: it then fits three waves per SIMD without spills.
+template <int NF> struct AccInLds {
+    static constexpr bool value = (NF == 8);
+};
 template <int MODEL, int NF> struct WavesPerEU {
     static constexpr int value =
-        (MODEL != KGRT_MODEL_TORUS) ? KGRT_WAVES_DISK : (NF == 1 ? KGRT_WAVES_TORUS : KGRT_WAVES_TORUS_MULTI);
+        (MODEL != KGRT_MODEL_TORUS) ? KGRT_WAVES_DISK
+                                    : (NF == 1 ? KGRT_WAVES_TORUS : (AccInLds<NF>::value ? 3 : KGRT_WAVES_TORUS_MULTI));
 };
+// dynamic LDS bytes of one block of `block` threads
+template <int NF> constexpr size_t acc_lds_bytes(int block) {
+    return AccInLds<NF>::value ? (size_t)3 * NF * block * sizeof(double) : 0;
+}
 
 // Persistent integrator over the rays of one chunk. MODEL selects the
 // crossing-tracking models (geodesic, thin disk) or the transfer model
@@ -204,10 +216,24 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
     double hs = 0.0;
     State yk{};
     // per frequency: optical depth, intensity, attenuation e^-tau (carried as a
-    // product of the steps' e^-dtau), coefficients at the last accepted point
-    double tau[NF], Iacc[NF], att[NF], ap[NF], ep[NF];
+    // product of the steps' e^-dtau), coefficients at the last accepted point;
+    // the first three in registers or in the thread's LDS slots
+    // (slot (3 f + k) blockDim.x + threadIdx.x: consecutive lanes, consecutive words)
+    constexpr bool kLds = AccInLds<NF>::value;
+    extern __shared__ double acc_lds[];
+    double tau[kLds ? 1 : NF], Iacc[kLds ? 1 : NF], att[kLds ? 1 : NF], ap[NF], ep[NF];
+    double* const lds_t = acc_lds + threadIdx.x;  // slot of (f, k): lds_t[(3 f + k) blockDim.x]
 #pragma unroll
-    for (int f = 0; f < NF; ++f) tau[f] = Iacc[f] = ap[f] = ep[f] = 0.0, att[f] = 1.0;
+    for (int f = 0; f < NF; ++f) {
+        ap[f] = ep[f] = 0.0;
+        if constexpr (kLds) {
+            lds_t[(3 * f) * blockDim.x] = lds_t[(3 * f + 1) * blockDim.x] = 0.0;
+            lds_t[(3 * f + 2) * blockDim.x] = 1.0;
+        } else {
+            tau[f] = Iacc[f] = 0.0;
+            att[f] = 1.0;
+        }
+    }
     const Outputs O = P.out;
     const int nf = P.nf;
     const int64_t nall = P.nrays;
@@ -256,9 +282,14 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                                 const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
 #pragma unroll
                                 for (int f = 0; f < NF; ++f) {
-                                    tau[f] = 0.0;
-                                    Iacc[f] = 0.0;
-                                    att[f] = 1.0;
+                                    if constexpr (kLds) {
+                                        lds_t[(3 * f) * blockDim.x] = lds_t[(3 * f + 1) * blockDim.x] = 0.0;
+                                        lds_t[(3 * f + 2) * blockDim.x] = 1.0;
+                                    } else {
+                                        tau[f] = 0.0;
+                                        Iacc[f] = 0.0;
+                                        att[f] = 1.0;
+                                    }
                                     if (f < nf)
                                         torus_coeffs(q, PR.torus, g0, ig0, PR.freqs[f], PR.inv_freqs[f], ap[f], ep[f]);
                                 }
@@ -409,9 +440,17 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                                 const double dtau = hdone * (ap[f] + a1) / 2.0;
                                 const double em = fm::expm1(-dtau);  // e^-dtau - 1
                                 const double phi = (dtau > 0.0) ? -em * fm::rcp(dtau) : 1.0;
-                                Iacc[f] += att[f] * hdone * (ep[f] + e1) / 2.0 * phi;
-                                tau[f] += dtau;
-                                att[f] += att[f] * em;
+                                if constexpr (kLds) {
+                                    double* const t = lds_t + (3 * f) * blockDim.x;
+                                    const double at = t[2 * blockDim.x];
+                                    t[blockDim.x] += at * hdone * (ep[f] + e1) / 2.0 * phi;
+                                    t[0] += dtau;
+                                    t[2 * blockDim.x] = at + at * em;
+                                } else {
+                                    Iacc[f] += att[f] * hdone * (ep[f] + e1) / 2.0 * phi;
+                                    tau[f] += dtau;
+                                    att[f] += att[f] * em;
+                                }
                                 ap[f] = a1;
                                 ep[f] = e1;
                             }
@@ -445,8 +484,10 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
             if (MODEL == KGRT_MODEL_TORUS) {
                 for (int f = 0; f < NF; ++f) {
                     if (f < nf) {
-                        if (O.intensity) O.intensity[(int64_t)f * nall + rid] = Iacc[f];
-                        if (O.tau) O.tau[(int64_t)f * nall + rid] = tau[f];
+                        const double If = kLds ? lds_t[(3 * f + 1) * blockDim.x] : Iacc[kLds ? 0 : f];
+                        const double tf = kLds ? lds_t[(3 * f) * blockDim.x] : tau[kLds ? 0 : f];
+                        if (O.intensity) O.intensity[(int64_t)f * nall + rid] = If;
+                        if (O.tau) O.tau[(int64_t)f * nall + rid] = tf;
                     }
                 }
             }
@@ -630,9 +671,11 @@ template <int MODEL, int NF>
 int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
     const int block = (env.launch.block == 64 || env.launch.block == 128) ? env.launch.block : 256;
     auto kern = trace_kernel<MODEL, NF>;
+    const size_t shmem = acc_lds_bytes<NF>(block);
     int per_cu = env.launch.blocks_per_cu;
     if (per_cu <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, shmem) != hipSuccess || per_cu <= 0)
+            per_cu = 1;
     }
     P.counter = env.counter;
     P.naive = (env.launch.mode == KGRT_LAUNCH_ONE_RAY_PER_THREAD) ? 1 : 0;
@@ -647,7 +690,7 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
         const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, (int64_t)env.num_cus * 16));
         hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, env.counter);
         hipLaunchKernelGGL(start_kernel, dim3(sgrid), dim3(256), 0, st, P, base, count, env.rec, cap);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, P, base, count, (const double*)env.rec, cap);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shmem, st, P, base, count, (const double*)env.rec, cap);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(ctx, KGRT_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     }
@@ -676,7 +719,8 @@ int kernel_info(int block, kgrt_kernel_info* out) {
     hipFuncAttributes fa{};
     if (hipFuncGetAttributes(&fa, (const void*)kern) != hipSuccess) return KGRT_E_HIP;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess) return KGRT_E_HIP;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, acc_lds_bytes<NF>(block)) != hipSuccess)
+        return KGRT_E_HIP;
     out->vgprs = fa.numRegs;
     out->scratch_bytes = (int32_t)fa.localSizeBytes;
     out->blocks_per_cu = per_cu;
