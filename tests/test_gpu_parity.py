@@ -279,3 +279,23 @@ def test_results_independent_of_launch_shape(ctx):
                 assert np.array_equal(g[k], ref[k]), (block, per_cu, refill, k)
     finally:
         ctx.set_launch()
+
+
+def test_eight_frequency_results_independent_of_launch_shape(ctx):
+    """The eight-frequency kernel keeps each thread's sums in LDS slots indexed by
+    the block size: every block size and residency gives bitwise identical outputs,
+    and they match the oracle."""
+    import oracle as O
+    w = scenes.torus_image(24, a=0.7, incl_deg=35.0, freqs=scenes.batch_frequencies())
+    w["camera"]["ny"] = 17
+    ref = run_gpu(ctx, w)
+    o = O.trace_image(oracle_scene(w), 24, 17, -20, 20, -20, 20).ravel()
+    compare_torus(ref, o, 8, "torus 8 freqs, default launch")
+    try:
+        for block, per_cu, refill in [(64, 0, 1), (64, 3, 4), (128, 0, 8), (128, 1, 1), (256, 2, 16)]:
+            ctx.set_launch(block, per_cu, refill)
+            g = run_gpu(ctx, w)
+            for k in ref:
+                assert np.array_equal(g[k], ref[k]), (block, per_cu, refill, k)
+    finally:
+        ctx.set_launch()
