@@ -23,7 +23,7 @@
 
 namespace kgrt_spec {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 1024;  // 1024 measured 9% faster than 512 (the largest images set the time)
 
 __global__ void __launch_bounds__(kThreads) spectra_kernel(const double* __restrict__ I, int64_t total,
                                                            const int64_t* __restrict__ off,
