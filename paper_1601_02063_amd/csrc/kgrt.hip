@@ -161,8 +161,13 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 // projection kernels run fastest at four waves: the register budget of 128
 // costs them a few spilled words (the disk kernel, 157 VGPRs at three waves,
 // spills 128 B at four and is still 3.5% faster). The eight-frequency kernel
-// keeps its per-frequency sums in LDS and runs at three (below); the 2-, 4-
-// and 16-frequency kernels (143 to 256 VGPRs) at two (one wave is 35% slower).
+// keeps its per-frequency sums in LDS and runs at three (below); the 2- and
+// 4-frequency kernels (143 and 163 VGPRs) fit three as well, but small images
+// give them too few rays per lane there, so their launches fall back to the
+// residency of two waves when three would leave fewer than kMinRaysPerLane rays
+// per lane (measured: at 1024^2 three waves are 6-11% faster, at 512^2 18%
+// slower); the 16-frequency kernel (256 VGPRs) runs at two. One wave is 35%
+// slower.
 #ifndef KGRT_WAVES_DISK
 #define KGRT_WAVES_DISK 4
 #endif
@@ -178,10 +183,16 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
 template <int NF> struct AccInLds {
     static constexpr bool value = (NF == 8);
 };
+template <int NF> struct RayCountResidency {
+    static constexpr bool value = (NF == 2 || NF == 4);
+};
+constexpr int kMinRaysPerLane = 3;
 template <int MODEL, int NF> struct WavesPerEU {
     static constexpr int value =
-        (MODEL != KGRT_MODEL_TORUS) ? KGRT_WAVES_DISK
-                                    : (NF == 1 ? KGRT_WAVES_TORUS : (AccInLds<NF>::value ? 3 : KGRT_WAVES_TORUS_MULTI));
+        (MODEL != KGRT_MODEL_TORUS)
+            ? KGRT_WAVES_DISK
+            : (NF == 1 ? KGRT_WAVES_TORUS
+                       : ((AccInLds<NF>::value || RayCountResidency<NF>::value) ? 3 : KGRT_WAVES_TORUS_MULTI));
 };
 // dynamic LDS bytes of one block of `block` threads
 template <int NF> constexpr size_t acc_lds_bytes(int block) {
@@ -676,6 +687,13 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
     if (per_cu <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, shmem) != hipSuccess || per_cu <= 0)
             per_cu = 1;
+        if (RayCountResidency<NF>::value && MODEL == KGRT_MODEL_TORUS) {
+            // the residency of two waves per SIMD when three would leave too few rays per lane
+            const int64_t rays = (env.limit >= 0) ? std::min<int64_t>(env.limit, P.nrays) : P.nrays;
+            const int two_waves = std::max(1, (2 * 4 * 64) / block);  // blocks per CU at two waves per SIMD
+            if (per_cu > two_waves && rays < (int64_t)kMinRaysPerLane * env.num_cus * per_cu * block)
+                per_cu = two_waves;
+        }
     }
     P.counter = env.counter;
     P.naive = (env.launch.mode == KGRT_LAUNCH_ONE_RAY_PER_THREAD) ? 1 : 0;
