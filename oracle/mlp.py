@@ -109,3 +109,19 @@ def loss_and_grads(params, x, t):
             dz = (dz @ W) * silu_grad(zs[li - 1])
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return _loss_from_outputs(o, t), flat
+
+
+def adam_step(params, m, v, grads, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One step of Adam (Kingma & Ba 2015, Algorithm 1) in float64.
+
+    t is the index of this step, counted from 1. Returns the new (params, m, v):
+      m_t = beta1 m_{t-1} + (1 - beta1) g,   v_t = beta2 v_{t-1} + (1 - beta2) g^2,
+      params_t = params_{t-1} - lr * (m_t / (1 - beta1^t)) / (sqrt(v_t / (1 - beta2^t)) + eps).
+    """
+    g = np.asarray(grads, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    p = np.asarray(params, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p, m, v
