@@ -31,9 +31,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # status bits (kerr_oracle.cpp)
 CAPTURED, ESCAPED, CROSSED, DISK_HIT = 1, 2, 4, 8
-MAXSTEPS, UNDERFLOW, NONFINITE, REFINE_UNCONVERGED = 16, 32, 64, 256
+MAXSTEPS, UNDERFLOW, NONFINITE, REFINE_UNCONVERGED, SPOT_HIT = 16, 32, 64, 256, 512
 
-MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS = 0, 1, 2
+MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT = 0, 1, 2, 3, 4
 
 
 def build(force: bool = False) -> str:
@@ -59,6 +59,8 @@ class _Scene(ctypes.Structure):
         ("n0_cgs", ctypes.c_double), ("r_norm", ctypes.c_double), ("n_index", ctypes.c_double),
         ("h_over_r", ctypes.c_double), ("T0_K", ctypes.c_double), ("T_index", ctypes.c_double),
         ("eps_B", ctypes.c_double), ("mbh_msun", ctypes.c_double), ("r_emit_max", ctypes.c_double),
+        ("spot_r", ctypes.c_double), ("spot_size", ctypes.c_double), ("spot_phi0", ctypes.c_double),
+        ("t_obs", ctypes.c_double),
         ("pr_form", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
@@ -71,6 +73,7 @@ RAY_DTYPE = np.dtype([
     ("final_state", "<f8", (6,)),
     ("E", "<f8"), ("L", "<f8"), ("Q", "<f8"), ("kappa", "<f8"),
     ("max_H_rel", "<f8"), ("max_Q_rel", "<f8"), ("lambda_end", "<f8"), ("min_sin", "<f8"),
+    ("n_cross", "<i4"), ("reserved", "<i4"),
 ])
 
 
@@ -100,6 +103,10 @@ class Scene:
     eps_B: float = 0.1
     mbh_msun: float = 4e6
     r_emit_max: float = 1000.0
+    spot_r: float = 0.0      # hot spot orbit radius (<= 0: ISCO)
+    spot_size: float = 0.5   # r_spot
+    spot_phi0: float = 0.0   # azimuth of the spot centre at t = 0
+    t_obs: float = 0.0       # observer time of the image
     pr_form: int = 0   # 0: Eq. (14) before the null condition is substituted; 1: as printed
 
     def _c(self) -> _Scene:
@@ -130,6 +137,7 @@ def lib():
         L.orc_k2.argtypes, L.orc_k2.restype = [d], d
         L.orc_synchrotron_j.argtypes, L.orc_synchrotron_j.restype = [d, d, d, d], d
         L.orc_redshift.argtypes, L.orc_redshift.restype = [P(_Scene), d, d, d], d
+        L.orc_spot_redshift.argtypes, L.orc_spot_redshift.restype = [P(_Scene), d, d, d], d
         L.orc_torus_coeffs.argtypes, L.orc_torus_coeffs.restype = [P(_Scene), d, d, d, d, P(d), P(d)], None
         L.orc_rhs.argtypes, L.orc_rhs.restype = [P(_Scene), vp, vp, vp], None
         L.orc_initial_state.argtypes, L.orc_initial_state.restype = [P(_Scene), d, d, vp, vp], ctypes.c_int
@@ -245,3 +253,8 @@ def torus_coeffs(scene: Scene, r: float, th: float, g: float, nu: float):
     e = ctypes.c_double()
     lib().orc_torus_coeffs(ctypes.byref(s), r, th, g, nu, ctypes.byref(a), ctypes.byref(e))
     return a.value, e.value
+
+
+def spot_redshift(scene: Scene, r: float, th: float, xi: float) -> float:
+    s = scene._c()
+    return lib().orc_spot_redshift(ctypes.byref(s), r, th, xi)

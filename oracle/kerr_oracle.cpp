@@ -40,7 +40,8 @@ typedef struct orc_scene {
     double hmax_frac;     // step cap |h| <= hmax_frac * r
     double horizon_delta; // capture when r <= r_plus * (1 + horizon_delta)
     int32_t max_steps;    // accepted-step cap
-    int32_t model;        // 0 = geodesic only, 1 = thin disk, 2 = torus
+    int32_t model;        // 0 = geodesic only, 1 = thin disk, 2 = torus, 3 = thick thin disk through every
+                          // crossing, 4 = orbiting hot spot
     int32_t stop_at_crossing; // terminate at the first equatorial crossing (projection workload)
     int32_t nfreq;        // number of observing frequencies (torus)
     double freqs_hz[16];  // observing frequencies
@@ -49,6 +50,9 @@ typedef struct orc_scene {
     double r_out;
     // analytic torus (synthetic stand-in for section 4.5's shell)
     double n0_cgs, r_norm, n_index, h_over_r, T0_K, T_index, eps_B, mbh_msun, r_emit_max;
+    // orbiting hot spot (section 4.4): orbit radius (<= 0 means r_ISCO(a)), spot
+    // radius r_spot, azimuth of its centre at t = 0, and the observer time of the image
+    double spot_r, spot_size, spot_phi0, t_obs;
     // Form of Eq. (14): 0 = before the null condition eliminates W^2/Delta
     // (default, see orc_rhs), 1 = as printed (kappa form).
     int32_t pr_form;
@@ -70,12 +74,14 @@ typedef struct orc_ray {
     double max_H_rel, max_Q_rel; // largest null-condition and Carter-Q drift seen
     double lambda_end;          // affine parameter at termination
     double min_sin;             // smallest sin(theta) over the accepted points (pole approach)
+    int32_t n_cross;            // model 3: equatorial crossings outside the capture radius, the emitting one included
+    int32_t reserved;
 } orc_ray;
 
 enum {
     ORC_CAPTURED = 1, ORC_ESCAPED = 2, ORC_CROSSED = 4, ORC_DISK_HIT = 8,
     ORC_MAXSTEPS = 16, ORC_UNDERFLOW = 32, ORC_NONFINITE = 64,
-    ORC_REFINE_UNCONVERGED = 256
+    ORC_REFINE_UNCONVERGED = 256, ORC_SPOT_HIT = 512
 };
 
 // ------------------------------------------------------- physical constants
@@ -305,6 +311,62 @@ void orc_torus_coeffs(const orc_scene* s, double r, double th, double g, double 
     *e_lam = rg * g * g * j;
 }
 
+// ----------------------------------------------------------- hot spot
+
+// The orbiting hot spot of section 4.4. reading: its centre moves on the
+// equatorial circle of Boyer-Lindquist radius r_s with the Keplerian angular
+// velocity Omega_s = 1/(r_s^3/2 + a) (prograde), azimuth phi_0 + Omega_s t at
+// coordinate time t. Positions are compared in the pseudo-Cartesian coordinates
+// of section 2.2 (x = sqrt(r^2+a^2) sin(theta) cos(phi), y = ... sin(phi),
+// z = r cos(theta)). The spot is the region z > 0, d < 4 r_spot, d the distance
+// from the centre; it is optically thick, so a ray ends where it first enters
+// the region, and the emissivity there is exp(-d^2 / (2 r_spot^2)) (Eq. (36)).
+static double spot_orbit_radius(const orc_scene* s) { return (s->spot_r > 0.0) ? s->spot_r : orc_isco(s->a); }
+
+static double spot_omega(const orc_scene* s) {
+    const double rs = spot_orbit_radius(s);
+    return 1.0 / (rs * std::sqrt(rs) + s->a);
+}
+
+// Squared distance from the spot centre of the point y (r, theta, phi, t, ...) at
+// the emission time t_obs + t (the traced ray's t runs backwards from 0).
+static double spot_distance2(const orc_scene* s, const double* y) {
+    const double a = s->a, rs = spot_orbit_radius(s);
+    const double t_emm = s->t_obs + y[3];
+    const double phic = s->spot_phi0 + spot_omega(s) * t_emm;
+    const double Rs = std::sqrt(rs * rs + a * a);
+    const double R = std::sqrt(y[0] * y[0] + a * a);
+    const double dx = R * std::sin(y[1]) * std::cos(y[2]) - Rs * std::cos(phic);
+    const double dy = R * std::sin(y[1]) * std::sin(y[2]) - Rs * std::sin(phic);
+    const double dz = y[0] * std::cos(y[1]);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+static bool in_spot(const orc_scene* s, const double* y) {
+    const double cut = 4.0 * s->spot_size;
+    return y[0] * std::cos(y[1]) > 0.0 && spot_distance2(s, y) < cut * cut;
+}
+
+// Redshift (Eq. (2)) of spot material at (r, theta). reading: the spot moves
+// rigidly with its centre, u = u^t (1, 0, 0, Omega_s), u^t from u.u = -1; the
+// zero-angular-momentum observer where that is not timelike.
+double orc_spot_redshift(const orc_scene* s, double r, double th, double xi) {
+    const double M = s->mass, a = s->a;
+    const double sn = clamped_sin(th), cs = std::cos(th);
+    const double Sigma = r * r + a * a * cs * cs;
+    const double gtt = -(1.0 - 2.0 * M * r / Sigma);
+    const double gtp = -2.0 * M * a * r * sn * sn / Sigma;
+    const double gpp = (r * r + a * a + 2.0 * M * a * a * r * sn * sn / Sigma) * sn * sn;
+    double Omega = spot_omega(s);
+    double arg = -(gtt + 2.0 * Omega * gtp + Omega * Omega * gpp);
+    if (!(arg > 0.0)) {
+        Omega = -gtp / gpp;
+        arg = -(gtt + 2.0 * Omega * gtp + Omega * Omega * gpp);
+    }
+    const double ut = 1.0 / std::sqrt(arg);
+    return 1.0 / (ut * (1.0 - xi * Omega));
+}
+
 // ----------------------------------------------------- Cash-Karp stepper
 
 // Embedded Runge-Kutta 5(4) pair of Cash & Karp (1990, ACM TOMS 16, 201);
@@ -369,7 +431,13 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
     const double rcap = rplus * (1.0 + s->horizon_delta);
     const double r_in = (s->r_in > 0.0) ? s->r_in : orc_isco(s->a);
     const int nf = (s->model == 2) ? s->nfreq : 0;
-    const bool want_cross = (s->model != 2);
+    const bool want_cross = (s->model != 2 && s->model != 4);
+    // model 3: the disk of section 4.3 is optically thick and the ray is followed
+    // through every equatorial crossing until one lands on it (the direct image and
+    // the higher-order images the hole's lensing makes of the same disk)
+    const bool every_crossing = (s->model == 3);
+    int32_t n_cross = 0;
+    const bool spot = (s->model == 4);
     const double q0 = c[2];
     const double qden = std::max(std::fabs(c[3]), 1.0);
 
@@ -441,6 +509,35 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
                 const double sabs = std::fabs(std::sin(y[1]));
                 if (sabs < min_sin) min_sin = sabs;
             }
+            // hot spot: the first accepted point inside the spot ends the ray; its entry
+            // point is located by bisection of the step size from y_k (each trial one full
+            // Cash-Karp step without error control), 48 halvings of the accepted step
+            if (spot && in_spot(s, y)) {
+                double lo = 0.0, hi = hdone, yin[6], yt[6], yte[6];
+                for (int i = 0; i < 6; ++i) yin[i] = y[i];
+                for (int it = 0; it < 48; ++it) {
+                    const double hm = 0.5 * (lo + hi);
+                    cash_karp(s, c, yprev, k1, hm, yt, yte);
+                    rhs += 5;
+                    if (in_spot(s, yt)) {
+                        hi = hm;
+                        for (int i = 0; i < 6; ++i) yin[i] = yt[i];
+                    } else {
+                        lo = hm;
+                    }
+                }
+                const double d2 = spot_distance2(s, yin);
+                const double j = std::exp(-d2 / (2.0 * s->spot_size * s->spot_size));  // Eq. (36)
+                status |= ORC_SPOT_HIT;
+                out->r_cross = yin[0];
+                out->phi_cross = yin[2];
+                out->t_cross = s->t_obs + yin[3];  // emission time t_emm = t_obs - Delta t
+                out->g = orc_spot_redshift(s, yin[0], yin[1], xi);
+                out->intensity = out->g * out->g * out->g * j;
+                out->i_bol = out->g * out->g * out->g * out->g * j;
+                for (int i = 0; i < 6; ++i) y[i] = yin[i];
+                goto done;
+            }
             // radiative transfer over the accepted step (Eqs. (30)-(31))
             if (nf > 0) {
                 const double g1 = orc_redshift(s, y[0], y[1], xi);
@@ -458,7 +555,7 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
             // over an accepted step is located by Newton iteration on the
             // step size from y_k, each iterate one full Cash-Karp step without
             // error control; integration then continues from y_{k+1}.
-            if (want_cross && !crossed) {
+            if (want_cross && (!crossed || every_crossing)) {
                 const double c0 = std::cos(yprev[1]), c1 = std::cos(y[1]);
                 if ((c0 > 0.0 && c1 <= 0.0) || (c0 < 0.0 && c1 >= 0.0)) {
                     crossed = true;
@@ -476,7 +573,23 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
                     }
                     if (!conv) status |= ORC_REFINE_UNCONVERGED;
                     const double rc = ys[0];
-                    if (rc > rcap) {
+                    if (every_crossing) {
+                        if (rc > rcap) {
+                            ++n_cross;
+                            if (rc >= r_in && rc <= s->r_out) {
+                                // reading: the first crossing on the disk is where the ray ends
+                                status |= ORC_CROSSED | ORC_DISK_HIT;
+                                out->r_cross = rc;
+                                out->phi_cross = ys[2];
+                                out->t_cross = ys[3];
+                                out->g = orc_redshift(s, rc, PI / 2.0, xi);
+                                const double j = 1.0 / (rc * rc * rc);  // emissivity r^-3
+                                out->intensity = out->g * out->g * out->g * j;
+                                out->i_bol = out->g * out->g * out->g * out->g * j;
+                                goto done;
+                            }
+                        }
+                    } else if (rc > rcap) {
                         status |= ORC_CROSSED;
                         out->r_cross = rc;
                         out->phi_cross = ys[2];
@@ -513,6 +626,7 @@ done:
     out->max_H_rel = maxH;
     out->max_Q_rel = maxQ;
     out->min_sin = min_sin;
+    out->n_cross = n_cross;
 }
 
 int orc_trace_ray(const orc_scene* s, double x, double y, orc_ray* out) {

@@ -339,3 +339,209 @@ def test_step_underflow_at_the_coordinate_horizon():
         real = rts[np.abs(rts.imag) < 1e-9].real
         assert not np.any(real > rplus)  # no radial turning point outside the horizon
     assert np.all(res["status"][~uf] & O.ESCAPED)
+
+
+# ------------------------------------- higher-order images of a thick disk
+
+def _equator_crossings(a, y6, c4, max_cross=4):
+    """All equatorial crossings (state vectors) of the Hamiltonian flow before the ray is captured
+    or escapes, in order."""
+    rplus = 1 + math.sqrt(1 - a * a)
+
+    def equator(lam, z):
+        return z[1] - math.pi / 2
+
+    def horizon(lam, z):
+        return z[0] - rplus * (1 + 1e-3)
+    horizon.terminal = True
+
+    def escape(lam, z):
+        return z[0] - 1001.0
+    escape.terminal = True
+    sol = solve_ivp(_hamilton_flow(a, c4[0], c4[1]), (0.0, 1e5), y6, method="DOP853", rtol=1e-13, atol=1e-13,
+                    events=[equator, horizon, escape])
+    rcap = rplus * (1 + 1e-3)
+    return [z for z in sol.y_events[0] if z[0] > rcap][:max_cross]
+
+
+DISK_IMAGE_RAYS = [(0.0, 80.0, -4.667, -7.867), (0.0, 80.0, -0.933, -5.2), (0.0, 80.0, 3.6, -3.867),
+                   (0.9, 75.0, 0.933, -6.8), (0.9, 75.0, -2.267, 2.8), (0.998, 85.0, -1.467, -4.133),
+                   (0.998, 85.0, -1.0, -3.6), (0.5, 40.0, -4.4, -0.933), (0.5, 40.0, 3.067, 4.667),
+                   (0.9, 60.0, 5.0, 3.0), (0.0, 80.0, -5.3, 0.4), (0.998, 85.0, 2.4, 3.4)]
+
+
+@pytest.mark.parametrize("a,inc,x,y", DISK_IMAGE_RAYS)
+def test_disk_images_through_every_crossing(a, inc, x, y):
+    """Thick thin disk seen through every crossing: the ray ends at the first equatorial crossing
+    that lands on the disk [r_ISCO, 20 M], which may be its second or third (a higher-order image
+    made by the hole's lensing). Crossing order, radius, redshift and intensity against the
+    independent flow (to 1e-9 at rtol 1e-12); the production controls within the method's error,
+    2e-7 for the direct image and about e^pi times more per extra half orbit."""
+    ok, y6, c4 = O.initial_state(O.Scene(a=a, incl_deg=inc), x, y)
+    zs = _equator_crossings(a, y6, c4)
+    r_in = O.isco(a)
+    hit = next((k for k, z in enumerate(zs) if r_in <= z[0] <= 20.0), None)
+    tight = O.trace_ray(O.Scene(a=a, incl_deg=inc, model=O.MODEL_DISK_IMAGES, rtol=1e-12, hmax_frac=0.005), x, y)
+    prod = O.trace_ray(O.Scene(a=a, incl_deg=inc, model=O.MODEL_DISK_IMAGES), x, y)
+    if hit is None:
+        assert not tight["status"] & O.DISK_HIT and not prod["status"] & O.DISK_HIT
+        assert tight["n_cross"] == len(zs) and tight["intensity"] == 0.0
+        return
+    z = zs[hit]
+    g_ref, _ = redshift_contraction(a, z[0], math.pi / 2, c4[1], z[4], z[5])
+    # each half orbit near the photon sphere amplifies an error by about e^pi: the higher the
+    # image order, the larger the true error of the same controls
+    amp = 30.0 ** hit
+    for res, tol in ((tight, 1e-9 * amp), (prod, 2e-7 * amp)):
+        assert res["status"] & O.DISK_HIT and res["status"] & O.CROSSED
+        assert res["n_cross"] == hit + 1
+        assert res["r_cross"] == pytest.approx(z[0], rel=tol)
+        assert res["phi_cross"] == pytest.approx(z[2], rel=tol)
+        assert res["t_cross"] == pytest.approx(z[3], rel=tol)
+        assert res["g"] == pytest.approx(g_ref, rel=tol)
+        assert res["intensity"] == pytest.approx(g_ref ** 3 / z[0] ** 3, rel=5 * tol)
+    # the disk absorbs the ray: it ends there, neither captured nor escaped
+    assert not prod["status"] & 3
+
+
+def test_disk_images_include_higher_orders_and_match_first_crossing_model():
+    """Over an image, the rays whose first crossing is on the disk give exactly the first-crossing
+    model's values, and some pixels show the disk only through a later crossing."""
+    pts = O.pixel_points(24, 24, -9, 9, -9, 9)
+    for a, inc in [(0.0, 80.0), (0.9, 75.0)]:
+        one = O.trace_points(O.Scene(a=a, incl_deg=inc, model=O.MODEL_THIN_DISK), pts)
+        many = O.trace_points(O.Scene(a=a, incl_deg=inc, model=O.MODEL_DISK_IMAGES), pts)
+        first = (one["status"] & O.DISK_HIT) != 0
+        assert np.all(many["status"][first] & O.DISK_HIT)
+        assert np.all(many["n_cross"][first] == 1)
+        for k in ("r_cross", "g", "phi_cross", "t_cross", "intensity", "i_bol"):
+            assert np.array_equal(many[k][first], one[k][first]), k
+        later = ((many["status"] & O.DISK_HIT) != 0) & ~first
+        assert later.sum() >= 5, (a, inc, later.sum())
+        assert np.all(many["n_cross"][later] >= 2)
+
+
+# ------------------------------------------------------------- hot spot
+
+def _spot_geometry(a, r_s, phi0, t_obs):
+    om = 1.0 / (r_s ** 1.5 + a)
+    Rs = math.sqrt(r_s * r_s + a * a)
+
+    def dist(z):  # pseudo-Cartesian distance from the centre at the emission time t_obs + t
+        r, th, ph, t = z[0], z[1], z[2], z[3]
+        R = math.sqrt(r * r + a * a)
+        p = np.array([R * math.sin(th) * math.cos(ph), R * math.sin(th) * math.sin(ph), r * math.cos(th)])
+        pc = phi0 + om * (t_obs + t)
+        return float(np.linalg.norm(p - np.array([Rs * math.cos(pc), Rs * math.sin(pc), 0.0])))
+    return om, dist
+
+
+def _spot_entry(a, y6, c4, r_s, size, phi0, t_obs):
+    """First entry of the Hamiltonian flow into {z > 0, d < 4 r_spot}: the continuous function
+    max(d - 4 r_spot, -z) falls through 0 there, whether through the dome or the base."""
+    om, dist = _spot_geometry(a, r_s, phi0, t_obs)
+    rplus = 1 + math.sqrt(1 - a * a)
+
+    def entry(lam, z):
+        return max(dist(z) - 4 * size, -z[0] * math.cos(z[1]))
+    entry.terminal = True
+    entry.direction = -1
+
+    def horizon(lam, z):
+        return z[0] - rplus * (1 + 1e-3)
+    horizon.terminal = True
+
+    def escape(lam, z):
+        return z[0] - 1001.0
+    escape.terminal = True
+
+    def near(lam, z):  # the spot lies within r_s + 4 r_spot of the hole
+        return z[0] - (r_s + 4 * size + 3.0)
+    near.terminal = True
+    near.direction = -1
+    flow = _hamilton_flow(a, c4[0], c4[1])
+    far = solve_ivp(flow, (0.0, 1e5), y6, method="DOP853", rtol=1e-13, atol=1e-13, events=[near, horizon, escape])
+    if len(far.t_events[0]) == 0:
+        return None
+    # short steps near the spot, so that a ray grazing its surface is not stepped over
+    lam0 = far.t_events[0][0]
+    sol = solve_ivp(flow, (lam0, lam0 + 1e5), far.y_events[0][0], method="DOP853", rtol=1e-13, atol=1e-13,
+                    max_step=0.05, events=[entry, horizon, escape])
+    if len(sol.t_events[0]) == 0:
+        return None
+    return sol.y_events[0][0]
+
+
+SPOT_RAYS = [(0.0, 60.0, 0.0, 0.0, 0.0), (0.0, 60.0, 35.0, 0.0, 0.0), (0.0, 60.0, 170.0, 40.0, 0.0),
+             (0.0, 30.0, 250.0, 13.0, 0.0), (0.9, 60.0, 90.0, -20.0, 8.0), (0.9, 75.0, 300.0, 7.0, 8.0)]
+
+
+@pytest.mark.parametrize("a,inc,phi0_deg,t_obs,orbit", SPOT_RAYS)
+def test_hot_spot_entry_against_hamiltonian_flow(a, inc, phi0_deg, t_obs, orbit):
+    """Section 4.4: rays end where they first enter the optically thick spot, evaluated at the
+    emission time t_obs - Delta t; the entry point (r, phi, t), the redshift of the co-moving spot
+    material and the intensity g^3 exp(-d^2/(2 r_spot^2)) against the independent flow, for pixels
+    over the spot's direct and lensed images."""
+    r_s = orbit if orbit > 0 else O.isco(a)
+    phi0 = math.radians(phi0_deg)
+    spot = dict(model=O.MODEL_HOT_SPOT, spot_r=orbit, spot_size=0.5, spot_phi0=phi0, t_obs=t_obs)
+    scn = O.Scene(a=a, incl_deg=inc, rtol=1e-12, hmax_frac=0.005, **spot)
+    prod = O.Scene(a=a, incl_deg=inc, **spot)
+    pts = O.pixel_points(20, 20, -9, 9, -9, 9)
+    coarse = O.trace_points(prod, pts)
+    hits = np.nonzero((coarse["status"] & O.SPOT_HIT) != 0)[0]
+    assert len(hits) >= 3
+    om, dist = _spot_geometry(a, r_s, phi0, t_obs)
+    checked = grazing = 0
+    for i in hits[:: max(1, len(hits) // 5)]:
+        x, y = pts[i]
+        ok, y6, c4 = O.initial_state(scn, x, y)
+        z = _spot_entry(a, y6, c4, r_s, 0.5, phi0, t_obs)
+        res = O.trace_ray(scn, x, y)
+        if z is None:  # the flow's event search stepped over a grazing entry
+            grazing += 1
+            continue
+        assert res["status"] == O.SPOT_HIT
+        assert res["r_cross"] == pytest.approx(z[0], rel=1e-8)
+        assert res["phi_cross"] == pytest.approx(z[2], rel=1e-8, abs=1e-8)
+        assert res["t_cross"] == pytest.approx(t_obs + z[3], rel=1e-8, abs=1e-8)
+        # the spot material co-rotates with the centre: u = u^t (1, 0, 0, Omega_s), u.u = -1
+        G = kerr_metric(a, z[0], z[1])
+        k = np.array([1.0, 0.0, 0.0, om])
+        assert k @ G @ k < 0  # timelike wherever the spot is
+        u = k / math.sqrt(-(k @ G @ k))
+        g_ref = 1.0 / -(photon_momentum(c4[1], z[4], z[5]) @ u)
+        assert res["g"] == pytest.approx(g_ref, rel=1e-8)
+        j = math.exp(-dist(z) ** 2 / (2 * 0.25))
+        assert res["intensity"] == pytest.approx(g_ref ** 3 * j, rel=1e-6)
+        assert res["i_bol"] == pytest.approx(g_ref ** 4 * j, rel=1e-6)
+        checked += 1
+    assert checked >= 3 and grazing <= 1
+
+
+def test_hot_spot_images_repeat_after_one_orbit():
+    """The spot returns after one orbital period 2 pi / Omega_s: images at t_obs and t_obs + T agree."""
+    a = 0.0
+    T = 2 * math.pi * (6.0 ** 1.5 + a)
+    pts = O.pixel_points(24, 24, -9, 9, -9, 9)
+    im = [O.trace_points(O.Scene(a=a, incl_deg=60.0, model=O.MODEL_HOT_SPOT, t_obs=t), pts) for t in (30.0, 30.0 + T)]
+    hit0, hit1 = (im[0]["status"] & O.SPOT_HIT) != 0, (im[1]["status"] & O.SPOT_HIT) != 0
+    assert hit0.sum() > 5 and np.array_equal(hit0, hit1)
+    np.testing.assert_allclose(im[1]["intensity"][hit0], im[0]["intensity"][hit0], rtol=1e-6)
+    np.testing.assert_allclose(im[1]["t_cross"][hit0] - T, im[0]["t_cross"][hit0], rtol=1e-9)
+
+
+def test_hot_spot_approaching_side_brightest():
+    """Over one orbit the observed flux peaks while the spot approaches the observer (g > 1 then)."""
+    a, inc = 0.0, 60.0
+    T = 2 * math.pi * 6.0 ** 1.5
+    pts = O.pixel_points(32, 32, -9, 9, -9, 9)
+    flux, gmax = [], []
+    for k in range(8):
+        r = O.trace_points(O.Scene(a=a, incl_deg=inc, model=O.MODEL_HOT_SPOT, t_obs=k * T / 8), pts)
+        hit = (r["status"] & O.SPOT_HIT) != 0
+        flux.append(r["i_bol"].sum())
+        gmax.append(r["g"][hit].max())
+    k = int(np.argmax(flux))
+    assert gmax[k] > 1.0
+    assert max(flux) > 3 * min(flux)
