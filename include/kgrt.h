@@ -50,11 +50,21 @@ extern "C" {
 #define KGRT_NONFINITE 64          /* non-finite state or unusable start point */
 #define KGRT_FALLBACK 128          /* (surrogate) ray was re-integrated */
 #define KGRT_REFINE_UNCONVERGED 256 /* crossing Newton refinement hit its iteration cap */
+#define KGRT_SPOT_HIT 512          /* (hot spot) the ray entered the spot and ended there */
 
 /* Emission models. */
 #define KGRT_MODEL_GEODESIC 0   /* geometry only: capture flag and first crossing */
 #define KGRT_MODEL_THIN_DISK 1  /* geometrically thin Keplerian disk, j = r^-3 (section 4.3) */
 #define KGRT_MODEL_TORUS 2      /* thermal-synchrotron torus (section 4.5 emissivity) */
+#define KGRT_MODEL_DISK_IMAGES 3 /* the thin disk of section 4.3 made optically thick and followed through
+                                    every equatorial crossing: the ray ends at the first crossing on the
+                                    disk, which gives the direct image and the higher-order (lensed)
+                                    images of sections 4.2-4.3; the crossing outputs and intensities
+                                    are those of that crossing, n_cross counts the crossings up to it */
+#define KGRT_MODEL_HOT_SPOT 4   /* the orbiting hot spot of section 4.4 (Eq. (36)), optically thick: the ray
+                                   ends where it first enters the spot, seen at the emission time
+                                   t_obs - Delta t (camera.t_obs); r_cross, phi_cross, t_cross, g,
+                                   intensity (g^3 j) and i_bol (g^4 j) describe that entry point */
 
 /* Integrator flags. */
 #define KGRT_STOP_AT_CROSSING 1u /* terminate each ray at its first equatorial crossing */
@@ -72,6 +82,8 @@ typedef struct kgrt_camera {
     int32_t nx, ny;      /* image size, >= 0 (0 => nothing to trace) */
     double x_min, x_max; /* image-plane extent in M, x_min < x_max */
     double y_min, y_max; /* y_min < y_max */
+    double t_obs;        /* observer (coordinate) time of the image, finite; only the hot spot depends
+                            on it (section 4.4: light received at t_obs left the spot at t_obs - Delta t) */
 } kgrt_camera;
 
 /* Emission/absorption model. */
@@ -85,6 +97,14 @@ typedef struct kgrt_model {
      * thermal synchrotron j_nu of Eqs. (37)-(39) per steradian, Kirchhoff absorption;
      * black-hole mass mbh_msun sets r_g; emission only for r_capture < r <= r_emit_max. */
     double n0_cgs, r_norm, n_index, h_over_r, T0_K, T_index, eps_B, mbh_msun, r_emit_max;
+    /* hot spot (section 4.4): the centre orbits the equator at Boyer-Lindquist radius spot_r (<= 0
+     * selects r_ISCO(a)) with the Keplerian Omega = 1/(spot_r^3/2 + a), at azimuth
+     * spot_phi0 + Omega t (radians) at coordinate time t; the spot is the region z > 0,
+     * d < 4 spot_size in the pseudo-Cartesian coordinates of section 2.2 (d the distance from the
+     * centre), its emissivity exp(-d^2 / (2 spot_size^2)) (Eq. (36), arbitrary units); its matter
+     * moves rigidly with the centre (u = u^t (1, 0, 0, Omega), the zero-angular-momentum observer
+     * where that is not timelike). spot_size > 0. */
+    double spot_r, spot_size, spot_phi0;
 } kgrt_model;
 
 /* Adaptive Runge-Kutta controls (section 2.1). */
@@ -110,6 +130,9 @@ typedef struct kgrt_outputs {
                            torus: [nfreq][n] observed I_nu, erg s^-1 cm^-2 Hz^-1 sr^-1 */
     double* i_bol;      /* thin disk: [n] g^4 r_c^-3 on the disk, else 0 */
     double* tau;        /* torus: [nfreq][n] optical depth along the ray */
+    int32_t* n_cross;   /* KGRT_MODEL_DISK_IMAGES: [n] equatorial crossings outside the capture radius
+                           up to the end of the ray (the image order of a disk hit is n_cross - 1);
+                           not written by the other models */
 } kgrt_outputs;
 
 /* Launch modes. */
@@ -240,6 +263,26 @@ int kgrt_image_spectra(const double* intensity_dev, int64_t total, int32_t nfreq
  * non-positive or non-finite extent, mass or distance. */
 double kgrt_pixel_solid_angle(const kgrt_camera* cam, double mbh_msun, double distance_cm);
 
+/* Spectrogram of images of the hot spot (section 4.4, Fig. 7): for each image
+ * k (a frame at its observer time) and energy-shift bin b,
+ *   out[k * nbins + b] = domega[k] * sum of i_bol[i] over the rays i of image k
+ *                        with g_edges[b] <= g[i] < g_edges[b + 1],
+ * i.e. the flux of a line emitted at one rest-frame energy E0, binned by the
+ * observed energy g E0 (i_bol = g^4 j per pixel, the frequency-integrated
+ * intensity). Summed over the bins it is the frame's point of the lightcurve
+ * (Fig. 8). Arguments: device arrays i_bol [total] and g [total] (a plan's
+ * outputs), offsets [nimg + 1] int64 and domega [nimg] (as for
+ * kgrt_image_spectra, ranges clamped to [0, total]), out [nimg][nbins]
+ * (written); g_edges is a HOST array of nbins + 1 increasing finite edges,
+ * 1 <= nbins <= 64. Each sum is taken in a fixed order (per-thread partial
+ * histograms, then threads in order), so repeated calls agree bit for bit.
+ * Asynchronous on `stream`. Returns KGRT_E_INVALID_ARG for nimg < 0 or
+ * > 65535, nbins out of range, edges not increasing, total < 0 or a NULL
+ * array that would be read or written. */
+int kgrt_spot_spectrogram(const double* i_bol_dev, const double* g_dev, int64_t total, const int64_t* offsets_dev,
+                          const double* domega_dev, int32_t nimg, const double* g_edges, int32_t nbins,
+                          double* out_dev, void* stream);
+
 /* ----------------------------------------------------------- surrogate */
 
 /* A learned surrogate of the integrator: a perceptron 4 -> 256 -> 256 -> 256 -> 256 -> 5
@@ -265,6 +308,13 @@ const char* kgrt_mlp_last_error(const kgrt_mlp* mlp);
 /* Host FP32 parameter vector in/out (synchronous). set_params also resets Adam. */
 int kgrt_mlp_set_params(kgrt_mlp* mlp, const float* params_host, int64_t n);
 int kgrt_mlp_get_params(kgrt_mlp* mlp, float* params_host, int64_t n);
+/* Adam state (Kingma & Ba 2015) for checkpoints: first and second moments, FP32
+ * vectors of num_params entries in the parameter order (host arrays, synchronous),
+ * and the number of steps taken (the t of the bias corrections 1 - beta^t).
+ * set_adam rejects non-finite moments or negative second moments and step < 0;
+ * call it after set_params, which resets the state. */
+int kgrt_mlp_get_adam(kgrt_mlp* mlp, float* m_host, float* v_host, int64_t n, int64_t* step);
+int kgrt_mlp_set_adam(kgrt_mlp* mlp, const float* m_host, const float* v_host, int64_t n, int64_t step);
 /* Inference: x_dev [n][4] FP32 features -> y_dev [n][5] FP32 outputs, any n >= 0. */
 int kgrt_mlp_forward(kgrt_mlp* mlp, const float* x_dev, float* y_dev, int64_t n, void* stream);
 /* Loss and gradients of one batch. x_dev [*][4] features, t_dev [*][6] targets

@@ -51,3 +51,21 @@ def image_spectra(intensity, offsets: Sequence[int], domega: Sequence[float]) ->
         for f in range(I.shape[0]):
             F[k, f] = float(domega[k]) * math.fsum(I[f, lo:hi])
     return F
+
+
+def spot_spectrogram(i_bol, g, offsets: Sequence[int], domega: Sequence[float], g_edges: Sequence[float]) -> np.ndarray:
+    """S[k, b] = domega[k] * sum of i_bol over image k's rays with g_edges[b] <= g < g_edges[b + 1]
+    (exactly rounded sums): the flux of a line emitted at one rest-frame energy, binned by its
+    observed energy shift g, one row per frame (the spectrogram of section 4.4, Fig. 7). Summed
+    over the bins it is the frame's point of the lightcurve (Fig. 8)."""
+    w = np.asarray(i_bol, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    e = np.asarray(g_edges, dtype=np.float64)
+    nimg, nb = len(offsets) - 1, len(e) - 1
+    S = np.zeros((nimg, nb))
+    for k in range(nimg):
+        lo, hi = int(offsets[k]), int(offsets[k + 1])
+        for b in range(nb):
+            sel = (g[lo:hi] >= e[b]) & (g[lo:hi] < e[b + 1])
+            S[k, b] = float(domega[k]) * math.fsum(w[lo:hi][sel])
+    return S

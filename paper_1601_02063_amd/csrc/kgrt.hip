@@ -30,7 +30,8 @@ struct ImageDesc {
     double a, a2, r_obs, sqrt_ro2a2;
     double sin_i, cos_i, sin_p, cos_p, phi_obs;
     double x_min, x_w, y_min, y_w;
-    double r_cap, r_in;
+    double r_cap, r_in;  // r_in: the disk's inner edge, or the hot spot's orbit radius
+    double t_obs;        // observer time of the image (hot spot)
     int64_t ray_offset;
     int32_t nx, ny;
 };
@@ -38,6 +39,7 @@ struct ImageDesc {
 struct Outputs {
     int32_t *status, *steps, *attempts;
     double *r_cross, *g, *phi_cross, *t_cross, *intensity, *i_bol, *tau;
+    int32_t* n_cross;
 };
 
 struct KParams {
@@ -54,6 +56,7 @@ struct KParams {
     double freqs[16];
     double inv_freqs[16];
     double r_in_cfg, r_out;
+    double spot_r_cfg, spot_phi0, spot_cut2, spot_inv_2s2;  // hot spot: orbit (<= 0: ISCO), phase, (4 r_spot)^2, 1/(2 r_spot^2)
     TorusParams torus;
     // integrator
     double rtol, hmax_frac, horizon_delta;
@@ -68,7 +71,8 @@ struct KParams {
 // Ray id -> start state and the per-ray uniforms (spin, capture radius,
 // disk inner edge, observer distance).
 __device__ __forceinline__ bool start_from_id(const KParams& P, int64_t rid, State& st, double& a, double& a2,
-                                              double& L, double& r_cap, double& r_in, double& r_obs) {
+                                              double& L, double& r_cap, double& r_in, double& r_obs,
+                                              double& t_obs) {
     if (P.list_mode) {
         const double* q = P.rays4 + 4 * rid;
         const double aa = q[0], incl = q[1], x = q[2], y = q[3];
@@ -81,7 +85,9 @@ __device__ __forceinline__ bool start_from_id(const KParams& P, int64_t rid, Sta
         bool ok = start_ray(aa, a2, r_obs, sqrt(r_obs * r_obs + a2), si, ci, P.list_sin_p, P.list_cos_p,
                             P.list_phi_obs, x, y, st, L);
         r_cap = (1.0 + sqrt(1.0 - a2)) * (1.0 + P.horizon_delta);
-        r_in = (P.r_in_cfg > 0.0) ? P.r_in_cfg : isco_radius(aa);
+        const double r_in_c = (P.model == KGRT_MODEL_HOT_SPOT) ? P.spot_r_cfg : P.r_in_cfg;
+        r_in = (r_in_c > 0.0) ? r_in_c : isco_radius(aa);
+        t_obs = 0.0;
         if (!(fabs(aa) < 1.0) || !(incl > 0.0 && incl < 180.0) || !isfinite(x) || !isfinite(y)) ok = false;
         return ok;
     }
@@ -104,15 +110,37 @@ __device__ __forceinline__ bool start_from_id(const KParams& P, int64_t rid, Sta
     r_obs = d->r_obs;
     r_cap = d->r_cap;
     r_in = d->r_in;
+    t_obs = d->t_obs;
     return start_ray(d->a, d->a2, d->r_obs, d->sqrt_ro2a2, d->sin_i, d->cos_i, d->sin_p, d->cos_p, d->phi_obs, x,
                      y, st, L);
 }
 
+// The hot spot of section 4.4 at the emission time t_obs + y.t of the point y (the
+// traced ray's t runs backwards from 0): its centre sits at pseudo-Cartesian
+// cylindrical radius rho_c and azimuth phi0 + om_s (t_obs + y.t) in the
+// equatorial plane. Squared distance from the centre by the law of cosines in
+// the cylindrical coordinates of section 2.2 (rho = sqrt(r^2 + a^2) sin(theta),
+// z = r cos(theta)); s, c are sin(theta), cos(theta) (unclamped).
+__device__ __forceinline__ double spot_d2(const State& y, double s, double c, double a2, double t_obs, double om_s,
+                                          double rho_c, double phi0) {
+    const double rho = sqrt(fma(y.r, y.r, a2)) * s;
+    const double z = y.r * c;
+    double sd, cd;
+    sincos_bounded(y.ph - fma(om_s, t_obs + y.t, phi0), &sd, &cd);
+    return fma(rho, rho - 2.0 * rho_c * cd, fma(rho_c, rho_c, z * z));
+}
+
+// The spot is the region z > 0, d < 4 r_spot (cut2 = (4 r_spot)^2).
+__device__ __forceinline__ bool spot_inside(const State& y, double s, double c, double a2, double t_obs, double om_s,
+                                            double rho_c, double phi0, double cut2) {
+    return y.r * c > 0.0 && spot_d2(y, s, c, a2, t_obs, om_s, rho_c, phi0) < cut2;
+}
+
 // Per-ray start record written by start_kernel and read by the integrator at
 // refill, structure-of-arrays over the rays of one chunk:
-//   r, theta, phi, p_r, p_theta, L_z, a, r_capture, r_in, r_obs.
+//   r, theta, phi, p_r, p_theta, L_z, a, r_capture, r_in, r_obs, t_obs.
 // A non-finite r marks an unusable start point.
-constexpr int kRecFields = 10;
+constexpr int kRecFields = 11;
 
 // ------------------------------------------------------------ kernels
 
@@ -140,8 +168,8 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
     if (P.count_dev) count = std::max<int64_t>(0, std::min<int64_t>(count, *P.count_dev - base));
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
         State st;
-        double a, a2, L, r_cap, r_in, r_obs;
-        const bool ok = start_from_id(P, base + k, st, a, a2, L, r_cap, r_in, r_obs);
+        double a, a2, L, r_cap, r_in, r_obs, t_obs;
+        const bool ok = start_from_id(P, base + k, st, a, a2, L, r_cap, r_in, r_obs, t_obs);
         rec[0 * cap + k] = ok ? st.r : __builtin_nan("");
         rec[1 * cap + k] = st.th;
         rec[2 * cap + k] = st.ph;
@@ -152,6 +180,7 @@ __global__ void __launch_bounds__(256) start_kernel(const KParams P, int64_t bas
         rec[7 * cap + k] = r_cap;
         rec[8 * cap + k] = r_in;
         rec[9 * cap + k] = r_obs;
+        rec[10 * cap + k] = t_obs;
     }
 }
 
@@ -187,9 +216,13 @@ template <int NF> struct RayCountResidency {
     static constexpr bool value = (NF == 2 || NF == 4);
 };
 constexpr int kMinRaysPerLane = 3;
+#ifndef KGRT_WAVES_SPOT
+#define KGRT_WAVES_SPOT 3
+#endif
 template <int MODEL, int NF> struct WavesPerEU {
     static constexpr int value =
-        (MODEL != KGRT_MODEL_TORUS)
+        (MODEL == KGRT_MODEL_HOT_SPOT) ? KGRT_WAVES_SPOT
+        : (MODEL != KGRT_MODEL_TORUS)
             ? KGRT_WAVES_DISK
             : (NF == 1 ? KGRT_WAVES_TORUS
                        : ((AccInLds<NF>::value || RayCountResidency<NF>::value) ? 3 : KGRT_WAVES_TORUS_MULTI));
@@ -207,6 +240,13 @@ __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WavesPerEU<MODEL, NF>::value, WavesPerEU<MODEL, NF>::value)))
 trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restrict__ rec, int64_t cap) {
     constexpr bool kDisk = (MODEL != KGRT_MODEL_TORUS);
+    // an optically thick disk seen through every crossing: refine each equatorial
+    // crossing, end the ray at the first one on the disk (direct or higher-order image)
+    constexpr bool kEvery = (MODEL == KGRT_MODEL_DISK_IMAGES);
+    // the orbiting hot spot: no crossing tracking; the first accepted point inside
+    // the spot starts a bisection of that step for the entry point
+    constexpr bool kSpot = (MODEL == KGRT_MODEL_HOT_SPOT);
+    constexpr bool kCross = kDisk && !kSpot;
     if (P.count_dev) count = std::max<int64_t>(0, std::min<int64_t>(count, *P.count_dev - base));
     const int lane = __lane_id();
     const uint64_t lane_mask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -223,9 +263,14 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
     // step size from y_k, run in lockstep with the other lanes' attempts; the
     // accepted y_k+1 and the next adaptive step wait in yk and hs meanwhile
     bool crossed = false, refine = false;
-    int32_t rit = 0;
+    int32_t rit = 0, ncross = 0;
     double hs = 0.0;
     State yk{};
+    // hot spot, per ray: observer time, the centre's angular velocity and its
+    // pseudo-Cartesian cylindrical radius sqrt(r_s^2 + a^2); while a lane bisects,
+    // yk holds the latest trial inside the spot, hs that trial's step and syk the
+    // largest step known to end outside
+    double t_obs = 0.0, om_s = 0.0, rho_c = 0.0;
     // per frequency: optical depth, intensity, attenuation e^-tau (carried as a
     // product of the steps' e^-dtau), coefficients at the last accepted point;
     // the first three in registers or in the thread's LDS slots
@@ -279,8 +324,14 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         r_cap = rec[7 * cap + k];
                         r_in = rec[8 * cap + k];
                         r_obs = rec[9 * cap + k];
+                        if (kSpot) {
+                            t_obs = rec[10 * cap + k];
+                            om_s = fm::rcp(fma(r_in, sqrt(r_in), a));  // 1/(r_s^3/2 + a), r_s in the r_in slot
+                            rho_c = sqrt(fma(r_in, r_in, a2));
+                        }
                         h = P.hmax_frac * r_obs;
                         steps = attempts = status = 0;
+                        ncross = 0;
                         crossed = refine = false;
                         sincos_bounded(y.th, &sy, &cy);
                         sy = clamp_sin(sy);
@@ -315,6 +366,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                             if (O.phi_cross) O.phi_cross[rid] = 0.0;
                             if (O.t_cross) O.t_cross[rid] = 0.0;
                             if (O.i_bol) O.i_bol[rid] = 0.0;
+                            if (kEvery && O.n_cross) O.n_cross[rid] = 0;
                             if (MODEL == KGRT_MODEL_TORUS) {
                                 for (int f = 0; f < nf; ++f) {
                                     if (O.intensity) O.intensity[(int64_t)f * nall + rid] = 0.0;
@@ -344,7 +396,35 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
         cash_karp(y, k1, h, a, a2, L, yn, ye);
         bool check_end = false;
 
-        if (kDisk && refine) {
+        if (kSpot && refine) {
+            // bisection of the step size for the spot's entry point (no error control)
+            double sz, cz;
+            sincos_bounded(yn.th, &sz, &cz);
+            ++rit;
+            if (spot_inside(yn, sz, cz, a2, t_obs, om_s, rho_c, P.spot_phi0, P.spot_cut2)) {
+                yk = yn;
+                hs = h;
+            } else {
+                syk = h;
+            }
+            if (rit == 48) {
+                refine = false;
+                double sk, ck;
+                sincos_bounded(yk.th, &sk, &ck);
+                const double j = fm::exp(-spot_d2(yk, sk, ck, a2, t_obs, om_s, rho_c, P.spot_phi0) * P.spot_inv_2s2);
+                const double g = redshift_omega(yk.r, clamp_sin(sk), ck, a, a2, -L, om_s);
+                status |= ST_SPOT_HIT;
+                if (O.r_cross) O.r_cross[rid] = yk.r;
+                if (O.g) O.g[rid] = g;
+                if (O.phi_cross) O.phi_cross[rid] = yk.ph;
+                if (O.t_cross) O.t_cross[rid] = t_obs + yk.t;  // emission time t_obs - Delta t
+                if (O.intensity) O.intensity[rid] = g * g * g * j;
+                if (O.i_bol) O.i_bol[rid] = g * g * g * g * j;
+                terminate = true;
+            } else {
+                h = 0.5 * (syk + hs);
+            }
+        } else if (kCross && refine) {
             // Newton step on h* for cos(theta(h*)) = 0 (no error control)
             double sz, cz;
             sincos_bounded(yn.th, &sz, &cz);
@@ -353,7 +433,24 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                 if (!(fabs(cz) <= 1e-13)) status |= ST_REFINE_UNCONVERGED;
                 refine = false;
                 const double rc = yn.r;
-                if (rc > r_cap) {
+                if (kEvery) {
+                    if (rc > r_cap) {
+                        ++ncross;
+                        if (rc >= r_in && rc <= P.r_out) {
+                            // the first crossing on the disk: the ray ends there
+                            status |= ST_CROSSED | ST_DISK_HIT;
+                            const double g = redshift(rc, kPi / 2.0, a, a2, -L);
+                            const double j = 1.0 / (rc * rc * rc);  // emissivity r^-3
+                            if (O.r_cross) O.r_cross[rid] = rc;
+                            if (O.g) O.g[rid] = g;
+                            if (O.phi_cross) O.phi_cross[rid] = yn.ph;
+                            if (O.t_cross) O.t_cross[rid] = yn.t;
+                            if (O.intensity) O.intensity[rid] = g * g * g * j;
+                            if (O.i_bol) O.i_bol[rid] = g * g * g * g * j;
+                            terminate = true;
+                        }
+                    }
+                } else if (rc > r_cap) {
                     status |= ST_CROSSED;
                     const double g = redshift(rc, kPi / 2.0, a, a2, -L);
                     double I = 0.0, Ib = 0.0;
@@ -418,7 +515,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     y = yn;
                     status |= ST_NONFINITE;
                     terminate = true;
-                } else if (kDisk && !crossed && ((c0 > 0.0 && cn <= 0.0) || (c0 < 0.0 && cn >= 0.0))) {
+                } else if (kCross && (kEvery || !crossed) && ((c0 > 0.0 && cn <= 0.0) || (c0 < 0.0 && cn >= 0.0))) {
                     // first equatorial crossing inside this step: park y_k+1 and refine from
                     // y_k over the next evaluations, starting from linear interpolation of cos(theta)
                     crossed = true;
@@ -431,6 +528,15 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     const double hcap = P.hmax_frac * yn.r;
                     hs = (hnext > hcap) ? hcap : hnext;
                     h = hdone * c0 / (c0 - cn);
+                } else if (kSpot && spot_inside(yn, sn, cn, a2, t_obs, om_s, rho_c, P.spot_phi0, P.spot_cut2)) {
+                    // the step ends inside the spot: bisect [0, hdone] from y_k for the entry
+                    refine = true;
+                    start_refine = true;
+                    rit = 0;
+                    yk = yn;
+                    hs = hdone;
+                    syk = 0.0;
+                    h = 0.5 * hdone;
                 } else {
                     y = yn;
                     sy = sn;
@@ -492,6 +598,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
             if (O.status) O.status[rid] = status;
             if (O.steps) O.steps[rid] = steps;
             if (O.attempts) O.attempts[rid] = attempts;
+            if (kEvery && O.n_cross) O.n_cross[rid] = ncross;
             if (MODEL == KGRT_MODEL_TORUS) {
                 for (int f = 0; f < NF; ++f) {
                     if (f < nf) {
@@ -502,7 +609,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     }
                 }
             }
-            if (!(status & ST_CROSSED)) {
+            if (!(status & (ST_CROSSED | ST_SPOT_HIT))) {
                 if (O.r_cross) O.r_cross[rid] = 0.0;
                 if (O.g) O.g[rid] = 0.0;
                 if (O.phi_cross) O.phi_cross[rid] = 0.0;
@@ -553,11 +660,17 @@ int check(std::string& msg, const kgrt_camera* cam, const kgrt_model* m, const d
         if (cam->nx < 0 || cam->ny < 0) { msg = "camera.nx, ny must be >= 0"; return KGRT_E_INVALID_ARG; }
         if (!(is_finite(cam->x_min) && is_finite(cam->x_max) && cam->x_min < cam->x_max)) { msg = "camera x extent invalid"; return KGRT_E_INVALID_ARG; }
         if (!(is_finite(cam->y_min) && is_finite(cam->y_max) && cam->y_min < cam->y_max)) { msg = "camera y extent invalid"; return KGRT_E_INVALID_ARG; }
+        if (!is_finite(cam->t_obs)) { msg = "camera.t_obs must be finite"; return KGRT_E_INVALID_ARG; }
     }
     if (!m) { msg = "model is NULL"; return KGRT_E_INVALID_ARG; }
     if (m->reserved != 0) { msg = "model.reserved must be 0"; return KGRT_E_INVALID_ARG; }
-    if (m->kind == KGRT_MODEL_THIN_DISK || m->kind == KGRT_MODEL_GEODESIC) {
-        if (m->kind == KGRT_MODEL_THIN_DISK) {
+    if (m->kind == KGRT_MODEL_HOT_SPOT) {
+        if (!(is_finite(m->spot_size) && m->spot_size > 0.0)) { msg = "model.spot_size must be finite and > 0"; return KGRT_E_INVALID_ARG; }
+        if (!is_finite(m->spot_r) || !is_finite(m->spot_phi0)) { msg = "model.spot_r and spot_phi0 must be finite"; return KGRT_E_INVALID_ARG; }
+    }
+    if (m->kind == KGRT_MODEL_THIN_DISK || m->kind == KGRT_MODEL_GEODESIC || m->kind == KGRT_MODEL_DISK_IMAGES ||
+        m->kind == KGRT_MODEL_HOT_SPOT) {
+        if (m->kind != KGRT_MODEL_GEODESIC && m->kind != KGRT_MODEL_HOT_SPOT) {
             if (!(is_finite(m->r_out) && m->r_out > 0.0)) { msg = "model.r_out must be finite and > 0"; return KGRT_E_INVALID_ARG; }
             if (!is_finite(m->r_in) || (m->r_in > 0.0 && !(m->r_in < m->r_out))) { msg = "model.r_in must be <= 0 or < r_out"; return KGRT_E_INVALID_ARG; }
         }
@@ -602,7 +715,9 @@ ImageDesc make_image(const kgrt_camera* c, const kgrt_model* m, double horizon_d
     d.y_min = c->y_min;
     d.y_w = c->y_max - c->y_min;
     d.r_cap = (1.0 + std::sqrt(1.0 - c->a * c->a)) * (1.0 + horizon_delta);
-    d.r_in = (m->r_in > 0.0) ? m->r_in : isco_radius(c->a);
+    const double r_in_c = (m->kind == KGRT_MODEL_HOT_SPOT) ? m->spot_r : m->r_in;
+    d.r_in = (r_in_c > 0.0) ? r_in_c : isco_radius(c->a);
+    d.t_obs = c->t_obs;
     d.ray_offset = offset;
     d.nx = c->nx;
     d.ny = c->ny;
@@ -611,7 +726,7 @@ ImageDesc make_image(const kgrt_camera* c, const kgrt_model* m, double horizon_d
 
 void set_outputs(KParams& P, const kgrt_outputs* o) {
     P.out = Outputs{o->status, o->steps, o->attempts, o->r_cross, o->g, o->phi_cross, o->t_cross,
-                    o->intensity, o->i_bol, o->tau};
+                    o->intensity, o->i_bol, o->tau, o->n_cross};
 }
 
 void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t nfreq, const kgrt_integrator* in,
@@ -621,6 +736,10 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     for (int f = 0; f < 16; ++f) P.freqs[f] = (f < P.nf) ? freqs[f] : 0.0;
     P.r_in_cfg = m->r_in;
     P.r_out = m->r_out;
+    P.spot_r_cfg = m->spot_r;
+    P.spot_phi0 = m->spot_phi0;
+    P.spot_cut2 = 16.0 * m->spot_size * m->spot_size;
+    P.spot_inv_2s2 = (m->spot_size > 0.0) ? 1.0 / (2.0 * m->spot_size * m->spot_size) : 0.0;
     TorusParams& T = P.torus;
     T.n0 = m->n0_cgs;
     T.inv_rnorm = (m->r_norm > 0.0) ? 1.0 / m->r_norm : 0.0;
@@ -716,6 +835,8 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
 }
 
 int dispatch_env(kgrt_ctx* ctx, const LaunchEnv& env, const KParams& P, hipStream_t st) {
+    if (P.model == KGRT_MODEL_DISK_IMAGES) return launch_one<KGRT_MODEL_DISK_IMAGES, 1>(ctx, env, P, st);
+    if (P.model == KGRT_MODEL_HOT_SPOT) return launch_one<KGRT_MODEL_HOT_SPOT, 1>(ctx, env, P, st);
     if (P.model != KGRT_MODEL_TORUS) return launch_one<KGRT_MODEL_THIN_DISK, 1>(ctx, env, P, st);
     if (P.nf <= 1) return launch_one<KGRT_MODEL_TORUS, 1>(ctx, env, P, st);
     if (P.nf <= 2) return launch_one<KGRT_MODEL_TORUS, 2>(ctx, env, P, st);
@@ -782,12 +903,14 @@ int kgrt_kernel_info_get(kgrt_ctx* ctx, int32_t model, int32_t nfreq, int32_t bl
     if (!ctx || !out) return KGRT_E_INVALID_ARG;
     if (block == 0) block = 256;
     if (block != 64 && block != 128 && block != 256) return fail(ctx, KGRT_E_INVALID_ARG, "block must be 64, 128 or 256");
-    if (model < KGRT_MODEL_GEODESIC || model > KGRT_MODEL_TORUS) return fail(ctx, KGRT_E_INVALID_ARG, "unknown model");
+    if (model < KGRT_MODEL_GEODESIC || model > KGRT_MODEL_HOT_SPOT) return fail(ctx, KGRT_E_INVALID_ARG, "unknown model");
     if (model == KGRT_MODEL_TORUS && (nfreq < 1 || nfreq > 16)) return fail(ctx, KGRT_E_INVALID_ARG, "nfreq must be 1..16");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
     int rc;
-    if (model != KGRT_MODEL_TORUS) rc = kernel_info<KGRT_MODEL_THIN_DISK, 1>(block, out);
+    if (model == KGRT_MODEL_DISK_IMAGES) rc = kernel_info<KGRT_MODEL_DISK_IMAGES, 1>(block, out);
+    else if (model == KGRT_MODEL_HOT_SPOT) rc = kernel_info<KGRT_MODEL_HOT_SPOT, 1>(block, out);
+    else if (model != KGRT_MODEL_TORUS) rc = kernel_info<KGRT_MODEL_THIN_DISK, 1>(block, out);
     else if (nfreq <= 1) rc = kernel_info<KGRT_MODEL_TORUS, 1>(block, out);
     else if (nfreq <= 2) rc = kernel_info<KGRT_MODEL_TORUS, 2>(block, out);
     else if (nfreq <= 4) rc = kernel_info<KGRT_MODEL_TORUS, 4>(block, out);

@@ -25,7 +25,7 @@ constexpr double kSinFloor = 1e-8;           // pole clamp of section 2.1
 
 // Status bits (mirror include/kgrt.h).
 constexpr int32_t ST_CAPTURED = 1, ST_ESCAPED = 2, ST_CROSSED = 4, ST_DISK_HIT = 8, ST_MAXSTEPS = 16,
-                  ST_UNDERFLOW = 32, ST_NONFINITE = 64, ST_REFINE_UNCONVERGED = 256;
+                  ST_UNDERFLOW = 32, ST_NONFINITE = 64, ST_REFINE_UNCONVERGED = 256, ST_SPOT_HIT = 512;
 
 // Cash & Karp (1990) embedded 5(4) tableau: stage weights a_ij, fifth-order
 // weights b_i and differences d_i = b_i - b*_i of the embedded fourth order.
@@ -391,6 +391,26 @@ __device__ __forceinline__ double redshift_sc(double r, double s, double c, doub
     // g = 1/(u^t (1 - xi Omega)) with u^t = arg^-1/2
     ig = (1.0 - xi * Om) * fm::rsqrt(arg);
     return fm::rcp(ig);
+}
+
+// As redshift_sc for matter moving with a given angular velocity Om0 (the hot
+// spot of section 4.4 moves rigidly with its centre), the zero-angular-momentum
+// observer where that motion is not timelike.
+__device__ __forceinline__ double redshift_omega(double r, double s, double c, double a, double a2, double xi,
+                                                 double Om0) {
+    const double s2 = s * s;
+    const double Sigma = r * r + a2 * c * c;
+    const double iS = fm::rcp(Sigma);
+    const double gtt = -(1.0 - 2.0 * r * iS);
+    const double gtp = -2.0 * a * r * s2 * iS;
+    const double gpp = (r * r + a2 + 2.0 * a2 * r * s2 * iS) * s2;
+    double Om = Om0;
+    double arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
+    if (!(arg > 0.0)) {
+        Om = -gtp * fm::rcp(gpp);
+        arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
+    }
+    return fm::rcp((1.0 - xi * Om) * fm::rsqrt(arg));
 }
 
 __device__ __forceinline__ double redshift(double r, double th, double a, double a2, double xi) {

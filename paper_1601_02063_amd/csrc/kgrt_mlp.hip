@@ -1152,6 +1152,32 @@ int kgrt_mlp_get_params(kgrt_mlp* m, float* params, int64_t n) {
     return KGRT_OK;
 }
 
+int kgrt_mlp_get_adam(kgrt_mlp* m, float* m_host, float* v_host, int64_t n, int64_t* step) {
+    if (!m || !m_host || !v_host || !step) return KGRT_E_INVALID_ARG;
+    if (n != kNumParams) return mlp_fail(m, KGRT_E_INVALID_ARG, "parameter count mismatch");
+    DevGuard g(m->device);
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(m_host, m->M, kNumParams * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(v_host, m->V, kNumParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return mlp_fail(m, KGRT_E_HIP, "hipMemcpy failed");
+    *step = m->step;
+    return KGRT_OK;
+}
+
+int kgrt_mlp_set_adam(kgrt_mlp* m, const float* m_host, const float* v_host, int64_t n, int64_t step) {
+    if (!m || !m_host || !v_host) return KGRT_E_INVALID_ARG;
+    if (n != kNumParams) return mlp_fail(m, KGRT_E_INVALID_ARG, "parameter count mismatch");
+    if (step < 0) return mlp_fail(m, KGRT_E_INVALID_ARG, "step must be >= 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(v_host[i] >= 0.0f) || !std::isfinite(m_host[i]) || !std::isfinite(v_host[i]))
+            return mlp_fail(m, KGRT_E_INVALID_ARG, "moments must be finite and second moments >= 0");
+    DevGuard g(m->device);
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(m->M, m_host, kNumParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->V, v_host, kNumParams * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return mlp_fail(m, KGRT_E_HIP, "hipMemcpy failed");
+    m->step = step;
+    return KGRT_OK;
+}
+
 int kgrt_mlp_forward(kgrt_mlp* m, const float* x, float* y, int64_t n, void* stream) {
     if (!m) return KGRT_E_INVALID_ARG;
     if (n < 0) return mlp_fail(m, KGRT_E_INVALID_ARG, "n must be >= 0");

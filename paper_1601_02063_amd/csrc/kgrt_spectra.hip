@@ -54,7 +54,67 @@ __global__ void __launch_bounds__(kThreads) spectra_kernel(const double* __restr
     if (threadIdx.x == 0) flux[(int64_t)k * nfreq + f] = domega[k] * part[0];
 }
 
+// Spectrogram of hot-spot frames: one block per image; each thread keeps its
+// own histogram row in LDS (bin-major, [nbins][kSgThreads] doubles, 64 KB at
+// 64 bins), so no two threads add to one slot; the rows are then summed per
+// bin in thread order. Every addition's order is fixed by the image's ray
+// range, so repeated calls agree bit for bit.
+constexpr int kSgThreads = 128;
+constexpr int kSgMaxBins = 64;
+struct SgEdges {
+    double e[kSgMaxBins + 1];
+};
+
+__global__ void __launch_bounds__(kSgThreads) spectrogram_kernel(const double* __restrict__ w,
+                                                                 const double* __restrict__ g, int64_t total,
+                                                                 const int64_t* __restrict__ off,
+                                                                 const double* __restrict__ domega, const SgEdges E,
+                                                                 int nbins, double* __restrict__ out) {
+    extern __shared__ double hist[];  // [nbins][kSgThreads]
+    const int k = blockIdx.x, t = threadIdx.x;
+    for (int b = 0; b < nbins; ++b) hist[b * kSgThreads + t] = 0.0;
+    int64_t lo = off[k], hi = off[k + 1];
+    lo = lo < 0 ? 0 : (lo > total ? total : lo);
+    hi = hi < lo ? lo : (hi > total ? total : hi);
+    for (int64_t i = lo + t; i < hi; i += kSgThreads) {
+        const double wi = w[i];
+        if (wi == 0.0) continue;
+        const double gi = g[i];
+        if (!(gi >= E.e[0] && gi < E.e[nbins])) continue;
+        int b0 = 0, b1 = nbins;  // the bin b with e[b] <= gi < e[b + 1]
+        while (b1 - b0 > 1) {
+            const int m = (b0 + b1) >> 1;
+            if (E.e[m] <= gi) b0 = m; else b1 = m;
+        }
+        hist[b0 * kSgThreads + t] += wi;
+    }
+    __syncthreads();
+    if (t < nbins) {
+        double sum = 0.0;
+        for (int u = 0; u < kSgThreads; ++u) sum += hist[t * kSgThreads + u];
+        out[(int64_t)k * nbins + t] = domega[k] * sum;
+    }
+}
+
 }  // namespace kgrt_spec
+
+extern "C" int kgrt_spot_spectrogram(const double* i_bol_dev, const double* g_dev, int64_t total,
+                                     const int64_t* offsets_dev, const double* domega_dev, int32_t nimg,
+                                     const double* g_edges, int32_t nbins, double* out_dev, void* stream) {
+    if (nimg < 0 || nimg > 65535 || total < 0 || nbins < 1 || nbins > kgrt_spec::kSgMaxBins || !g_edges)
+        return KGRT_E_INVALID_ARG;
+    kgrt_spec::SgEdges E{};
+    for (int b = 0; b <= nbins; ++b) {
+        if (!std::isfinite(g_edges[b]) || (b > 0 && !(g_edges[b] > g_edges[b - 1]))) return KGRT_E_INVALID_ARG;
+        E.e[b] = g_edges[b];
+    }
+    if (nimg == 0) return KGRT_OK;
+    if (!offsets_dev || !domega_dev || !out_dev || (total > 0 && (!i_bol_dev || !g_dev))) return KGRT_E_INVALID_ARG;
+    const size_t shmem = (size_t)nbins * kgrt_spec::kSgThreads * sizeof(double);
+    hipLaunchKernelGGL(kgrt_spec::spectrogram_kernel, dim3((unsigned)nimg), dim3(kgrt_spec::kSgThreads), shmem,
+                       (hipStream_t)stream, i_bol_dev, g_dev, total, offsets_dev, domega_dev, E, (int)nbins, out_dev);
+    return hipGetLastError() == hipSuccess ? KGRT_OK : KGRT_E_HIP;
+}
 
 extern "C" int kgrt_image_spectra(const double* intensity_dev, int64_t total, int32_t nfreq,
                                   const int64_t* offsets_dev, const double* domega_dev, int32_t nimg,

@@ -19,8 +19,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "kgrt.h")
 
 OK, E_INVALID_ARG, E_HIP, E_NOMEM, E_NO_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 CAPTURED, ESCAPED, CROSSED, DISK_HIT = 1, 2, 4, 8
-MAXSTEPS, UNDERFLOW, NONFINITE, FALLBACK, REFINE_UNCONVERGED = 16, 32, 64, 128, 256
-MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS = 0, 1, 2
+MAXSTEPS, UNDERFLOW, NONFINITE, FALLBACK, REFINE_UNCONVERGED, SPOT_HIT = 16, 32, 64, 128, 256, 512
+MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT = 0, 1, 2, 3, 4
 STOP_AT_CROSSING = 1
 
 
@@ -34,7 +34,7 @@ class CCamera(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("incl_deg", ctypes.c_double), ("phi_obs_deg", ctypes.c_double),
                 ("r_obs", ctypes.c_double), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
-                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double)]
+                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double), ("t_obs", ctypes.c_double)]
 
 
 class CModel(ctypes.Structure):
@@ -42,7 +42,8 @@ class CModel(ctypes.Structure):
                 ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
                 ("n0_cgs", ctypes.c_double), ("r_norm", ctypes.c_double), ("n_index", ctypes.c_double),
                 ("h_over_r", ctypes.c_double), ("T0_K", ctypes.c_double), ("T_index", ctypes.c_double),
-                ("eps_B", ctypes.c_double), ("mbh_msun", ctypes.c_double), ("r_emit_max", ctypes.c_double)]
+                ("eps_B", ctypes.c_double), ("mbh_msun", ctypes.c_double), ("r_emit_max", ctypes.c_double),
+                ("spot_r", ctypes.c_double), ("spot_size", ctypes.c_double), ("spot_phi0", ctypes.c_double)]
 
 
 class CIntegrator(ctypes.Structure):
@@ -50,7 +51,9 @@ class CIntegrator(ctypes.Structure):
                 ("max_steps", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
-OUTPUT_FIELDS = ("status", "steps", "attempts", "r_cross", "g", "phi_cross", "t_cross", "intensity", "i_bol", "tau")
+OUTPUT_FIELDS = ("status", "steps", "attempts", "r_cross", "g", "phi_cross", "t_cross", "intensity", "i_bol", "tau",
+                 "n_cross")
+INT_FIELDS = ("status", "steps", "attempts", "n_cross")
 
 
 class COutputs(ctypes.Structure):
@@ -98,10 +101,11 @@ class Camera:
     y_max: float = 15.0
     r_obs: float = 1000.0
     phi_obs_deg: float = 0.0
+    t_obs: float = 0.0
 
     def c(self) -> CCamera:
         return CCamera(self.a, self.incl_deg, self.phi_obs_deg, self.r_obs, self.nx, self.ny,
-                       self.x_min, self.x_max, self.y_min, self.y_max)
+                       self.x_min, self.x_max, self.y_min, self.y_max, self.t_obs)
 
 
 @dataclass
@@ -118,10 +122,14 @@ class Model:
     eps_B: float = 0.1
     mbh_msun: float = 4e6
     r_emit_max: float = 1000.0
+    spot_r: float = 0.0       # hot spot orbit radius (<= 0: ISCO)
+    spot_size: float = 0.5    # r_spot
+    spot_phi0: float = 0.0    # azimuth of the spot centre at t = 0 (radians)
 
     def c(self) -> CModel:
         return CModel(self.kind, 0, self.r_in, self.r_out, self.n0_cgs, self.r_norm, self.n_index, self.h_over_r,
-                      self.T0_K, self.T_index, self.eps_B, self.mbh_msun, self.r_emit_max)
+                      self.T0_K, self.T_index, self.eps_B, self.mbh_msun, self.r_emit_max, self.spot_r,
+                      self.spot_size, self.spot_phi0)
 
 
 @dataclass
@@ -179,6 +187,8 @@ def lib() -> ctypes.CDLL:
         L.kgrt_mlp_last_error.argtypes, L.kgrt_mlp_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_mlp_set_params.argtypes, L.kgrt_mlp_set_params.restype = [vp, vp, i64], ctypes.c_int
         L.kgrt_mlp_get_params.argtypes, L.kgrt_mlp_get_params.restype = [vp, vp, i64], ctypes.c_int
+        L.kgrt_mlp_get_adam.argtypes, L.kgrt_mlp_get_adam.restype = [vp, vp, vp, i64, vp], ctypes.c_int
+        L.kgrt_mlp_set_adam.argtypes, L.kgrt_mlp_set_adam.restype = [vp, vp, vp, i64, i64], ctypes.c_int
         L.kgrt_mlp_forward.argtypes, L.kgrt_mlp_forward.restype = [vp, vp, vp, i64, vp], ctypes.c_int
         L.kgrt_mlp_loss_grads.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
         L.kgrt_mlp_loss_grads.restype = ctypes.c_int
@@ -197,6 +207,8 @@ def lib() -> ctypes.CDLL:
         L.kgrt_image_spectra.argtypes = [vp, i64, i32, vp, vp, i32, vp, vp]
         L.kgrt_image_spectra.restype = ctypes.c_int
         L.kgrt_pixel_solid_angle.argtypes, L.kgrt_pixel_solid_angle.restype = [P(CCamera), d, d], d
+        L.kgrt_spot_spectrogram.argtypes = [vp, vp, i64, vp, vp, i32, P(d), i32, vp, vp]
+        L.kgrt_spot_spectrogram.restype = ctypes.c_int
         L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
         L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
@@ -277,7 +289,7 @@ class Context:
         o = COutputs()
         for name in OUTPUT_FIELDS:
             t = outs.get(name)
-            if name in ("status", "steps", "attempts"):
+            if name in INT_FIELDS:
                 setattr(o, name, _ptr(t, torch.int32, n, self.device))
             else:
                 per = n * nf if (model.kind == MODEL_TORUS and name in ("intensity", "tau")) else n
@@ -401,6 +413,32 @@ def image_spectra(intensity: torch.Tensor, offsets: torch.Tensor, domega: torch.
     return flux
 
 
+def spot_spectrogram(i_bol: torch.Tensor, g: torch.Tensor, offsets: torch.Tensor, domega: torch.Tensor,
+                     g_edges: Sequence[float], stream=None) -> torch.Tensor:
+    """kgrt_spot_spectrogram: out[k, b] = domega[k] * sum of i_bol over image k's rays with
+    g_edges[b] <= g < g_edges[b + 1]. i_bol, g: contiguous CUDA float64 [total]; offsets: CUDA
+    int64 [nimg + 1]; domega: CUDA float64 [nimg]; g_edges: host sequence of nbins + 1 edges."""
+    for t, dt, nm in ((i_bol, torch.float64, "i_bol"), (g, torch.float64, "g"), (offsets, torch.int64, "offsets"),
+                      (domega, torch.float64, "domega")):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.dim() == 1):
+            raise ValueError(f"{nm} must be a contiguous 1-D CUDA {dt} tensor")
+    if i_bol.shape != g.shape:
+        raise ValueError("i_bol and g must have the same length")
+    nimg = domega.shape[0]
+    if offsets.shape[0] != nimg + 1:
+        raise ValueError("offsets must have nimg + 1 entries")
+    nbins = len(g_edges) - 1
+    edges = (ctypes.c_double * max(1, nbins + 1))(*[float(e) for e in g_edges])
+    out = torch.empty((nimg, max(nbins, 0)), dtype=torch.float64, device=g.device)
+    total = g.shape[0]
+    rc = lib().kgrt_spot_spectrogram(i_bol.data_ptr() if total else None, g.data_ptr() if total else None, total,
+                                     offsets.data_ptr(), domega.data_ptr(), nimg, edges, nbins, out.data_ptr(),
+                                     _stream_handle(stream))
+    if rc != OK:
+        raise KgrtError(rc, "kgrt_spot_spectrogram failed")
+    return out
+
+
 def pixel_solid_angle(camera: Camera, mbh_msun: float, distance_cm: float) -> float:
     """kgrt_pixel_solid_angle: sr subtended by one pixel of `camera` at `distance_cm`."""
     v = float(lib().kgrt_pixel_solid_angle(ctypes.byref(camera.c()), mbh_msun, distance_cm))
@@ -413,7 +451,9 @@ def alloc_outputs(n: int, model: Model, nfreq: int, device, names: Iterable[str]
     """Allocates output tensors for n rays (torus intensity/tau are [nfreq, n])."""
     out = {}
     for name in names:
-        if name in ("status", "steps", "attempts"):
+        if name == "n_cross" and model.kind != MODEL_DISK_IMAGES:
+            continue
+        if name in INT_FIELDS:
             out[name] = torch.empty(n, dtype=torch.int32, device=device)
         elif model.kind == MODEL_TORUS and name in ("intensity", "tau"):
             out[name] = torch.empty((max(nfreq, 1), n), dtype=torch.float64, device=device)
@@ -480,6 +520,23 @@ class Mlp:
         p = np.zeros(self.num_params(), dtype=np.float32)
         self._check(lib().kgrt_mlp_get_params(self._h, p.ctypes.data, p.size))
         return p
+
+    def get_adam(self):
+        """(first moments, second moments, steps taken) of the optimiser."""
+        import numpy as np
+        m = np.zeros(self.num_params(), dtype=np.float32)
+        v = np.zeros(self.num_params(), dtype=np.float32)
+        step = ctypes.c_int64()
+        self._check(lib().kgrt_mlp_get_adam(self._h, m.ctypes.data, v.ctypes.data, m.size, ctypes.byref(step)))
+        return m, v, int(step.value)
+
+    def set_adam(self, m, v, step: int):
+        import numpy as np
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        if m.size != self.num_params() or v.size != self.num_params():
+            raise ValueError("moment vectors must have num_params entries")
+        self._check(lib().kgrt_mlp_set_adam(self._h, m.ctypes.data, v.ctypes.data, m.size, int(step)))
 
     def forward(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         _dev_check(x, torch.float32, (4,), "x")

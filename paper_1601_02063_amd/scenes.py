@@ -16,6 +16,9 @@ sides see identical inputs. Values are plain dicts of floats/ints:
     x, y ~ U[-15, 15] M.
   * projection_image -- the timing workload of the paper's Table 1: a = 0.95,
     inclination 60 deg, first-crossing projection, +-15 M.
+  * hot_spot_frames  -- the orbiting hot spot of section 4.4: a = 0, inclination
+    60 deg, spot of radius 0.5 M on the ISCO, n x n pixels over +-9 M, frames at
+    observer times k dt (by default nframes frames over one orbit at r = 6 M).
 """
 from __future__ import annotations
 
@@ -92,4 +95,20 @@ def render_scenes(seed: int = 1605, nimg: int = 64, n: int = 2048) -> list:
         a = float(rng.uniform(0.0, 0.998))
         inc = float(rng.uniform(1.0, 89.0))
         out.append(thin_disk_image(n, a, inc, 15.0))
+    return out
+
+
+def hot_spot_frames(n: int = 128, nframes: int = 32, a: float = 0.0, incl_deg: float = 60.0, half: float = 9.0,
+                    spot_r: float = 0.0, spot_size: float = 0.5, spot_phi0: float = 0.0, dt: float = 0.0) -> list:
+    """Frames of the hot spot (model kind 4) at observer times k * dt, k = 0 .. nframes - 1.
+    dt <= 0 spreads the frames over 2 pi 6^(3/2) M, one Keplerian orbit at r = 6 M (the ISCO of
+    a = 0, the paper's case)."""
+    if dt <= 0.0:
+        dt = 2.0 * np.pi * 6.0 ** 1.5 / nframes
+    out = []
+    for k in range(nframes):
+        w = thin_disk_image(n, a, incl_deg, half)
+        w["camera"]["t_obs"] = k * dt
+        w["model"] = dict(kind=4, spot_r=spot_r, spot_size=spot_size, spot_phi0=spot_phi0)
+        out.append(w)
     return out

@@ -144,7 +144,9 @@ def train(ctx: K.Context, mlp: K.Mlp, x, t, xv, tv, epochs: int, batch: int = 65
 
 
 def save_checkpoint(path: str, mlp: K.Mlp, meta: Dict):
-    np.savez(path, params=mlp.get_params())
+    """Parameters, the optimiser's moments and its step count (training resumes exactly)."""
+    m, v, step = mlp.get_adam()
+    np.savez(path, params=mlp.get_params(), adam_m=m, adam_v=v, adam_step=np.int64(step))
     with open(os.path.splitext(path)[0] + ".json", "w") as f:
         json.dump(dict(meta, arch=ARCH), f, indent=1)
 
@@ -154,6 +156,8 @@ def load_checkpoint(path: str, mlp: K.Mlp) -> Optional[Dict]:
         return None
     with np.load(path, allow_pickle=False) as z:
         mlp.set_params(z["params"])
+        if "adam_m" in z.files:
+            mlp.set_adam(z["adam_m"], z["adam_v"], int(z["adam_step"]))
     meta_path = os.path.splitext(path)[0] + ".json"
     return json.load(open(meta_path)) if os.path.exists(meta_path) else {}
 

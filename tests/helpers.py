@@ -10,9 +10,9 @@ def oracle_scene(w, **over):
     kw = dict(a=cam["a"], incl_deg=cam["incl_deg"], phi_obs_deg=cam["phi_obs_deg"], r_obs=cam["r_obs"],
               rtol=integ["rtol"], hmax_frac=integ["hmax_frac"], horizon_delta=integ["horizon_delta"],
               max_steps=integ["max_steps"], model=mod["kind"], stop_at_crossing=bool(integ["flags"] & 1),
-              freqs_hz=list(w["freqs"]))
+              freqs_hz=list(w["freqs"]), t_obs=cam.get("t_obs", 0.0))
     for k in ("r_in", "r_out", "n0_cgs", "r_norm", "n_index", "h_over_r", "T0_K", "T_index", "eps_B",
-              "mbh_msun", "r_emit_max"):
+              "mbh_msun", "r_emit_max", "spot_r", "spot_size", "spot_phi0"):
         if k in mod:
             kw[k] = mod[k]
     kw.update(over)

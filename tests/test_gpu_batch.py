@@ -113,11 +113,17 @@ def test_batch_equals_single_images_every_launch_mode(ctx, model):
 
 
 def test_full_scene_batch_sampled_against_oracle(ctx):
-    """The 256-image batch of uneven scenes at 8 frequencies, in its benchmark
-    launch shape (autotuned, graph replay); sampled rays recomputed by the oracle."""
+    """The 256-image batch of uneven scenes at 8 frequencies, in its benchmark launch shape
+    (autotuned, graph replay). A seeded 1/64 of every image's pixels is recomputed by the
+    oracle: capture flags identical except within 1e-6 M of the critical curve, I_nu and tau_nu
+    within 1e-6 on every sampled ray. Rays passing within sin(theta) < 1e-6 of the pole, where
+    the clamp of section 2.1 amplifies last-ulp differences, may exceed that bar only in
+    bounded number and never beyond 1e-4."""
+    import time
     import torch
     import oracle as O
     from paper_1601_02063_amd import kgrt as K
+    from tests.helpers import critical_curve_distance
     ws = scenes.batch_scenes(1603)
     params = [kgrt_params(w) for w in ws]
     _, mod, freqs, integ = params[0]
@@ -132,23 +138,39 @@ def test_full_scene_batch_sampled_against_oracle(ctx):
     assert not np.any(g["status"] == -7)
     assert np.all((g["status"] & 3) != 0)
     rng = np.random.Generator(np.random.PCG64(5))
-    checked = 0
-    for k in rng.choice(len(ws), size=24, replace=False):
-        w = ws[k]
+    sel, rays = [], []
+    for k, w in enumerate(ws):
         cam = w["camera"]
-        idx = rng.choice(cam["nx"] * cam["ny"], size=8, replace=False)
+        n = cam["nx"] * cam["ny"]
+        idx = np.sort(rng.choice(n, size=n // 64, replace=False))
         xy = O.pixel_points(cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"], cam["y_max"])[idx]
-        o = O.trace_points(oracle_scene(w), xy)
-        gi = plan.offsets[k] + idx
-        same = (g["steps"][gi] == o["steps"]) & (g["attempts"][gi] == o["attempts"])
-        regular = o["min_sin"] >= 1e-6
-        assert same[regular].all(), (k, idx[~same])
-        for f in range(8):
-            I_o, I_g = o["I"][:, f], g["intensity"][f, gi]
-            scale = max(np.abs(g["intensity"][f]).max(), 1e-300)
-            err = np.abs(I_g - I_o) / np.maximum(np.abs(I_o), 1e-12 * scale)
-            tol = np.where(same & regular, 1e-6, 1e-4)
-            assert np.all(err <= tol), (k, f, err.max())
-        checked += len(idx)
-    assert checked == 192
+        rays.append(np.column_stack([np.full(len(idx), cam["a"]), np.full(len(idx), cam["incl_deg"]), xy]))
+        sel.append(plan.offsets[k] + idx)
+    rays = np.concatenate(rays)
+    gi = np.concatenate(sel)
+    t0 = time.time()
+    o = O.trace_ray_list(oracle_scene(ws[0]), rays)
+    print(f"oracle: {len(gi)} sampled rays at 8 frequencies in {time.time() - t0:.1f} s", flush=True)
+    st_g = g["status"][gi]
+    same = (g["steps"][gi] == o["steps"]) & (g["attempts"][gi] == o["attempts"])
+    regular = o["min_sin"] >= 1e-6
+    assert same[regular].mean() >= 0.999, same[regular].mean()
+    assert np.array_equal(st_g[same], o["status"][same])
+    bad = np.nonzero((st_g & 1) != (o["status"] & 1))[0]
+    for b in bad:
+        xi, eta = o["L"][b] / o["E"][b], o["Q"][b] / o["E"][b] ** 2
+        assert critical_curve_distance(rays[b, 0], rays[b, 1], [xi], [eta])[0] < 1e-6, b
+    over = np.zeros(len(gi), dtype=bool)
+    for f in range(8):
+        I_o, I_g = o["I"][:, f], g["intensity"][f, gi]
+        scale = max(np.abs(g["intensity"][f]).max(), 1e-300)
+        err = np.abs(I_g - I_o) / np.maximum(np.abs(I_o), 1e-12 * scale)
+        terr = np.abs(g["tau"][f, gi] - o["tau"][:, f]) / np.maximum(np.abs(o["tau"][:, f]), 1e-30)
+        assert np.all(err <= 1e-4) and np.all(terr <= 1e-4), (f, err.max(), terr.max())
+        over |= (err > 1e-6) | (terr > 1e-6)
+    print(f"batch sample: {len(gi)} rays, identical steps {same.mean():.6f}, near-pole {int((~regular).sum())}, "
+          f"over 1e-6 {int(over.sum())}, capture flips {len(bad)}", flush=True)
+    assert not np.any(over & regular), np.nonzero(over & regular)[0][:10]
+    assert over.sum() <= max(8, len(gi) // 20000), int(over.sum())
+    assert (~regular).sum() <= len(gi) // 100
     plan.close()

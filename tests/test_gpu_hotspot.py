@@ -1,0 +1,123 @@
+"""The orbiting hot spot of section 4.4 on the GPU (through the C ABI) against the oracle.
+
+Frames of one orbit are traced as one plan (one persistent launch, each image
+at its own observer time). Each ray ends where it first enters the optically
+thick spot, seen at the emission time t_obs - Delta t; entry point, redshift
+and intensity must match the oracle's, and the spectrogram and lightcurve
+kernels must match their exact-sum references.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import spectra as OS
+from paper_1601_02063_amd import scenes
+from tests.helpers import oracle_scene
+
+pytestmark = pytest.mark.gpu
+
+REL_GEOM = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = K.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.where(a == b, 0.0, np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+
+
+def _frames(n, nframes, a=0.0, incl=60.0, spot_r=0.0):
+    return scenes.hot_spot_frames(n, nframes, a=a, incl_deg=incl, spot_r=spot_r)
+
+
+@pytest.mark.parametrize("a,incl,spot_r,n", [(0.0, 60.0, 0.0, 48), (0.9, 75.0, 8.0, 41)])
+def test_hot_spot_frames_match_oracle(ctx, a, incl, spot_r, n):
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    ws = _frames(n, 6, a, incl, spot_r)
+    cams = [K.Camera(**w["camera"]) for w in ws]
+    mod, integ = K.Model(**ws[0]["model"]), K.Integrator(**ws[0]["integ"])
+    plan = K.Plan(ctx, cams, mod, [], integ)
+    out = plan.alloc_outputs()
+    for t in out.values():
+        t.fill_(-7)
+    plan.launch(out, graph=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert not np.any(g["status"] == -7)
+    hits = flips = 0
+    for k, w in enumerate(ws):
+        lo, hi = plan.offsets[k], plan.offsets[k + 1]
+        gk = {name: v[lo:hi] for name, v in g.items()}
+        cam = w["camera"]
+        o = O.trace_image(oracle_scene(w), cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"],
+                          cam["y_max"]).ravel()
+        ident = (gk["steps"] == o["steps"]) & (gk["attempts"] == o["attempts"])
+        assert ident.mean() >= 0.998, (k, ident.mean())
+        hit_g, hit_o = (gk["status"] & 512) != 0, (o["status"] & 512) != 0
+        flips += int((hit_g != hit_o).sum())
+        both = hit_g & hit_o
+        strict = both & ident
+        hits += int(both.sum())
+        for name in ("r_cross", "phi_cross", "t_cross", "g"):
+            assert rel(gk[name][strict], o[name][strict]).max(initial=0) <= REL_GEOM, (k, name)
+        for name in ("intensity", "i_bol"):  # exp(-d^2/2 r_spot^2) amplifies the entry point's error
+            assert rel(gk[name][strict], o[name][strict]).max(initial=0) <= 100 * REL_GEOM, (k, name)
+        loose = both & ~strict
+        assert rel(gk["r_cross"][loose], o["r_cross"][loose]).max(initial=0) <= 1e-6, k
+        # rays that miss the spot end as the other models' rays do
+        miss = ~hit_g & ~hit_o
+        assert np.all(gk["intensity"][miss] == 0.0) and np.all(gk["r_cross"][miss] == 0.0)
+        assert np.array_equal(gk["status"][miss & ident] & 3, o["status"][miss & ident] & 3)
+        assert not np.any(gk["status"][hit_g] & 3)  # the spot ends the ray
+    print(f"hot spot a={a}: {hits} spot pixels over 6 frames, {flips} hit/miss flips", flush=True)
+    assert hits >= 6 * 20
+    assert flips <= max(2, hits // 500)
+    plan.close()
+
+
+def test_spectrogram_and_lightcurve_kernels(ctx):
+    """One orbit in 16 frames: the spectrogram kernel against the exact-sum reference on the same
+    per-pixel inputs (bit-level agreement up to summation order), repeated calls identical, its
+    rows summed equal to the lightcurve (the frames' frequency-integrated flux), and the
+    lightcurve's peak on the approaching half of the orbit."""
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    ws = _frames(64, 16)
+    cams = [K.Camera(**w["camera"]) for w in ws]
+    mod, integ = K.Model(**ws[0]["model"]), K.Integrator(**ws[0]["integ"])
+    plan = K.Plan(ctx, cams, mod, [], integ)
+    out = plan.alloc_outputs(("status", "g", "i_bol"))
+    plan.launch(out)
+    torch.cuda.synchronize()
+    offs = torch.tensor(plan.offsets, dtype=torch.int64, device=ctx.device)
+    dom = torch.tensor([K.pixel_solid_angle(c, 4e6, 2.5e22) for c in cams], dtype=torch.float64, device=ctx.device)
+    edges = list(np.linspace(0.3, 1.7, 57))
+    sg = K.spot_spectrogram(out["i_bol"], out["g"], offs, dom, edges)
+    sg2 = K.spot_spectrogram(out["i_bol"], out["g"], offs, dom, edges)
+    lc = K.image_spectra(out["i_bol"], offs, dom)[:, 0]
+    torch.cuda.synchronize()
+    sg, sg2, lc = sg.cpu().numpy(), sg2.cpu().numpy(), lc.cpu().numpy()
+    assert np.array_equal(sg, sg2)
+    ib, gg = out["i_bol"].cpu().numpy(), out["g"].cpu().numpy()
+    ref = OS.spot_spectrogram(ib, gg, plan.offsets, dom.cpu().numpy(), edges)
+    np.testing.assert_allclose(sg, ref, rtol=1e-12, atol=1e-15 * ref.max())
+    hit = (out["status"].cpu().numpy() & 512) != 0
+    assert gg[hit].min() > edges[0] and gg[hit].max() < edges[-1]
+    np.testing.assert_allclose(sg.sum(axis=1), lc, rtol=1e-12)
+    k = int(np.argmax(lc))
+    assert lc.max() > 3 * lc.min()
+    lo, hi = plan.offsets[k], plan.offsets[k + 1]
+    assert gg[lo:hi][hit[lo:hi]].max() > 1.0  # blueshifted when brightest
+    plan.close()

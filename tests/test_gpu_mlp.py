@@ -172,3 +172,119 @@ def test_training_reduces_loss(ctx):
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.1 * losses[0], losses
     mlp.close()
+
+
+def _bf16_activation_bound(p, x):
+    """Per-element bound on the outputs' deviation caused by rounding the hidden activations
+    h_1..h_3 (the inputs of the three 256x256 layers) to BF16: first-order propagation of a
+    relative error of 2^-8 (twice BF16's unit roundoff, for the second-order terms and the
+    kernel's SiLU approximations) on every activation, |dy_i| <= 2^-8 sum_l,k |dy_i/dh_lk| |h_lk|."""
+    layers = M.unpack(p.astype(np.float64))
+    _, (hs, zs) = M.forward(p.astype(np.float64), x.astype(np.float64))
+    n = x.shape[0]
+    bound = np.zeros((n, 5))
+    for i in range(5):
+        dh = np.tile(layers[4][0][i], (n, 1))          # dy_i/dh_4
+        for l in (4, 3, 2):                              # to dy_i/dh_{l-1} through layer l
+            dz = dh * M.silu_grad(zs[l - 1])
+            dh = dz @ layers[l - 1][0]
+            bound[:, i] += np.sum(np.abs(dh) * np.abs(hs[l - 1]), axis=1)
+    return 2.0 ** -8 * bound
+
+
+def test_forward_elementwise_within_bf16_bound(ctx):
+    """Every output element of the fused inference kernel lies within the first-order BF16 bound
+    of the reference evaluated on the same BF16 weights (plus a floor of 1e-4 of the column's
+    RMS for the FP32 input layer and head), on a ragged 1000-row batch."""
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(13)
+    rng = np.random.Generator(np.random.PCG64(4))
+    x = rng.uniform(-1, 1, size=(1000, 4)).astype(np.float32)
+    mlp = K.Mlp(ctx, max_batch=1024)
+    mlp.set_params(p)
+    y = mlp.forward(torch.from_numpy(x).to(ctx.device)).cpu().numpy().astype(np.float64)
+    ref, _ = M.forward(p.astype(np.float64), x.astype(np.float64))
+    bound = _bf16_activation_bound(p, x) + 1e-4 * np.sqrt(np.mean(ref ** 2, axis=0))
+    excess = np.abs(y - ref) / bound
+    print(f"forward: max |dy|/bound {excess.max():.3f}, median {np.median(excess):.4f}", flush=True)
+    assert np.all(excess <= 1.0), (np.unravel_index(np.argmax(excess), excess.shape), excess.max())
+    mlp.close()
+
+
+def test_gradients_match_reference_at_production_batch(ctx):
+    """The training batch of the surrogate (65536 gathered rows, so the weight gradients are
+    summed over all 64 split-K chunks of 1024 rows) against the FP64 reference on the same BF16
+    weights: loss and every parameter tensor within 2e-2 (Frobenius)."""
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(17)
+    rng = np.random.Generator(np.random.PCG64(18))
+    n, pool = 65536, 70000
+    x = rng.uniform(-1, 1, size=(pool, 4)).astype(np.float32)
+    t = np.zeros((pool, 6), dtype=np.float32)
+    t[:, 0] = rng.integers(0, 2, pool)
+    t[:, 1:5] = rng.normal(size=(pool, 4))
+    t[:, 5] = rng.integers(0, 2, pool)
+    idx = rng.permutation(pool)[:n].astype(np.int32)
+    mlp = K.Mlp(ctx, max_batch=n)
+    mlp.set_params(p)
+    loss, g = mlp.loss_grads(torch.from_numpy(x).to(ctx.device), torch.from_numpy(t).to(ctx.device),
+                             torch.from_numpy(idx).to(ctx.device))
+    torch.cuda.synchronize()
+    lref, gref = M.loss_and_grads(p.astype(np.float64), x[idx].astype(np.float64), t[idx].astype(np.float64))
+    assert abs(float(loss) - lref) <= REL * abs(lref)
+    g = g.cpu().numpy()
+    k = 0
+    worst = 0.0
+    for li, (i, o) in enumerate(M.LAYERS):
+        for name, size in (("W", i * o), ("b", o)):
+            e = rel_fro(g[k:k + size], gref[k:k + size])
+            worst = max(worst, e)
+            assert e <= REL, (li + 1, name, e)
+            k += size
+    print(f"gradients at n = {n}: worst tensor error {worst:.2e}", flush=True)
+    mlp.close()
+
+
+def test_adam_steps_match_reference(ctx):
+    """Two kgrt_mlp_train_step calls against the FP64 Adam of Kingma & Ba applied to the GPU's own
+    gradients at the same parameters: parameters, moments and step count, element by element."""
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(23)
+    rng = np.random.Generator(np.random.PCG64(24))
+    n = 2048
+    x = torch.from_numpy(rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)).to(ctx.device)
+    tt = np.zeros((n, 6), dtype=np.float32)
+    tt[:, 0] = rng.integers(0, 2, n)
+    tt[:, 1:5] = rng.normal(size=(n, 4))
+    tt[:, 5] = rng.integers(0, 2, n)
+    t = torch.from_numpy(tt).to(ctx.device)
+    lr, b1, b2, eps = 3e-3, 0.9, 0.999, 1e-8
+    mlp = K.Mlp(ctx, max_batch=n)
+    mlp.set_params(p)
+    loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+    P = p.astype(np.float64)
+    m = np.zeros_like(P)
+    v = np.zeros_like(P)
+    for step in (1, 2):
+        _, g = mlp.loss_grads(x, t)
+        g = g.cpu().numpy().astype(np.float64)
+        P_ref, m, v = M.adam_step(P, m, v, g, step, lr, b1, b2, eps)
+        mlp.train_step(x, t, None, n, lr, loss, (b1, b2), eps)
+        P = mlp.get_params().astype(np.float64)
+        gm, gv, gstep = mlp.get_adam()
+        assert gstep == step
+        # the step's own gradient is recomputed (its atomic bias sums may differ in the last
+        # bits), which moves a parameter by at most lr * 1e-3 here; FP32 rounding of P beside it
+        np.testing.assert_allclose(P, P_ref, rtol=3e-7, atol=1e-3 * lr)
+        np.testing.assert_allclose(gm, m, rtol=1e-4, atol=1e-7 * np.abs(g).max())
+        np.testing.assert_allclose(gv, v, rtol=1e-4, atol=1e-9 * (g ** 2).max())
+        m, v = gm.astype(np.float64), gv.astype(np.float64)
+    # the state round-trips through the checkpoint accessors
+    mlp.set_params(p)
+    mlp.set_adam(gm, gv, 2)
+    gm2, gv2, s2 = mlp.get_adam()
+    assert s2 == 2 and np.array_equal(gm2, gm) and np.array_equal(gv2, gv)
+    mlp.close()

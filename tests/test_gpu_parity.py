@@ -11,6 +11,7 @@ last-ulp difference is listed and compared at the method's own error
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_1601_02063_amd import scenes
 from tests.helpers import critical_curve_distance, kgrt_params, oracle_scene
 
@@ -53,7 +54,7 @@ def rel(a, b):
 POLE_SIN = 1e-6  # rays passing closer to the pole run into the clamp sin(theta) >= 1e-8
 
 
-def compare_disk(w, g, o, label):
+def compare_disk(w, g, o, label, order_amp=False):
     """Compare GPU outputs g (dict) with oracle rays o (structured, flat).
 
     Strict set: rays with identical step sequences that neither pass within
@@ -61,7 +62,10 @@ def compare_disk(w, g, o, label):
     Hamiltonian form and amplifies last-ulp differences) nor lie within 1e-6 M of
     the critical curve. On it, disk hits agree to 1e-9 in r_c and g. Every other
     crossing is compared at the method's own accuracy, 1e-6 (g relative to
-    max(g, 1e-3): g -> 0 at the photon orbit, where it is ill-conditioned)."""
+    max(g, 1e-3): g -> 0 at the photon orbit, where it is ill-conditioned).
+
+    order_amp: the bars of a ray that hits the disk at its n-th crossing are multiplied by
+    30^(n - 1) (each half orbit near the photon sphere amplifies a difference by about e^pi)."""
     cam = w["camera"]
     st_o = o["status"]
     st_g = g["status"]
@@ -83,17 +87,38 @@ def compare_disk(w, g, o, label):
     both = ((st_g & 4) != 0) & ((st_o & 4) != 0)
     disk = both & ((st_o & 8) != 0) & ((st_g & 8) != 0)
     strict = disk & ident & regular
+    amp = 30.0 ** np.maximum(o["n_cross"] - 1, 0) if order_amp else np.ones(len(st_o))
     for k in ("r_cross", "g", "phi_cross", "t_cross"):
-        e = rel(g[k][strict], o[k][strict]).max(initial=0)
+        e = (rel(g[k][strict], o[k][strict]) / amp[strict]).max(initial=0)
         assert e <= REL_GEOM, (label, k, e)
     for k in ("intensity", "i_bol"):  # g^3 r^-3 and g^4 r^-3 amplify the geometric error a few times
-        e = rel(g[k][strict], o[k][strict]).max(initial=0)
+        e = (rel(g[k][strict], o[k][strict]) / amp[strict]).max(initial=0)
         assert e <= 10 * REL_GEOM, (label, k, e)
     loose = both & ~strict
-    assert rel(g["r_cross"][loose], o["r_cross"][loose]).max(initial=0) <= REL_RT, label
-    gerr = np.abs(g["g"][loose] - o["g"][loose]) / np.maximum(np.abs(o["g"][loose]), 1e-3)
+    assert (rel(g["r_cross"][loose], o["r_cross"][loose]) / amp[loose]).max(initial=0) <= REL_RT, label
+    gerr = np.abs(g["g"][loose] - o["g"][loose]) / np.maximum(np.abs(o["g"][loose]), 1e-3) / amp[loose]
     assert gerr.max(initial=0) <= REL_RT, (label, gerr.max(initial=0))
     assert np.array_equal((st_g & 4)[regular], (st_o & 4)[regular]), label
+    # intensity on every ray: equal where both hit the disk (the method's accuracy off the
+    # strict set), zero where neither does; a disk-hit flip only for a crossing within
+    # 1e-6 of a disk edge, where a last-ulp difference moves r_c across it
+    hit_g, hit_o = (st_g & 8) != 0, (st_o & 8) != 0
+    both_hit = hit_g & hit_o
+    for k in ("intensity", "i_bol"):
+        e = (rel(g[k][both_hit], o[k][both_hit]) / amp[both_hit]).max(initial=0)
+        assert e <= 10 * REL_RT, (label, k, e)
+    neither = ~hit_g & ~hit_o
+    assert np.all(g["intensity"][neither] == 0.0) and np.all(o["intensity"][neither] == 0.0), label
+    flips = np.nonzero(hit_g != hit_o)[0]
+    if len(flips):
+        r_in = w["model"]["r_in"] if w["model"]["r_in"] > 0 else O.isco(cam["a"])
+        rc = o["r_cross"][flips]
+        edge = np.minimum(np.abs(rc - r_in), np.abs(rc - w["model"]["r_out"])) <= 1e-6 * rc
+        assert edge.all(), (label, flips[~edge][:10])
+    assert len(flips) <= max(1, len(st_o) // 10000), (label, len(flips))
+    # the near-pole exemption covers few rays (at 1 degree inclination, the 4% of the image
+    # around its centre)
+    assert near_pole.sum() <= max(4, len(st_o) // 20), (label, int(near_pole.sum()))
     return frac
 
 
@@ -121,6 +146,30 @@ def test_thin_disk_other_geometries(ctx, a, incl, n, half):
     o = O.trace_image(oracle_scene(w), cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"],
                       cam["y_max"]).ravel()
     compare_disk(w, g, o, f"a={a} incl={incl}")
+
+
+@pytest.mark.parametrize("a,incl,n", [(0.0, 80.0, 64), (0.9, 75.0, 61), (0.998, 85.0, 48)])
+def test_disk_images_through_every_crossing(ctx, a, incl, n):
+    """The thick disk seen through every equatorial crossing (direct and higher-order images):
+    the same bars as the first-crossing disk on the emitting crossing, and the same crossing
+    count wherever the step sequences agree."""
+    w = scenes.thin_disk_image(n, a, incl, 9.0)
+    w["model"]["kind"] = 3
+    w["camera"]["ny"] = n - 5
+    w["camera"]["y_max"] = 8.0
+    g = run_gpu(ctx, w)
+    cam = w["camera"]
+    o = O.trace_image(oracle_scene(w), cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"],
+                      cam["y_max"]).ravel()
+    compare_disk(w, g, o, f"disk images a={a} incl={incl}", order_amp=True)
+    ident = (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
+    assert np.array_equal(g["n_cross"][ident], o["n_cross"][ident])
+    hit = (g["status"] & 8) != 0
+    higher = hit & (g["n_cross"] >= 2)
+    print(f"disk images a={a} incl={incl}: {int(hit.sum())} disk pixels, {int(higher.sum())} of them "
+          f"higher-order, max order {int(g['n_cross'][hit].max()) - 1}", flush=True)
+    assert higher.sum() >= 20
+    assert not np.any(g["status"][hit] & 3)  # the disk ends the ray
 
 
 def test_projection_stop_at_crossing(ctx):
@@ -155,14 +204,46 @@ def test_step_cap_and_empty_image(ctx):
     assert int(out["status"][0]) == -7
 
 
+def test_step_underflow_matches_oracle(ctx):
+    """A capture radius of r_+(1 + 1e-12) lies where the horizon's coordinate singularity drives the
+    step below 1e-12 r: every ray the oracle ends in UNDERFLOW ends so on the GPU, never CAPTURED."""
+    w = scenes.thin_disk_image(12, 0.9, 60.0, 6.0)
+    w["integ"]["horizon_delta"] = 1e-12
+    g = run_gpu(ctx, w)
+    o = O.trace_image(oracle_scene(w), 12, 12, -6, 6, -6, 6).ravel()
+    uf_g, uf_o = (g["status"] & 32) != 0, (o["status"] & 32) != 0
+    assert uf_o.sum() >= 40
+    assert np.array_equal(uf_g, uf_o)
+    assert not np.any(g["status"] & 1)
+    assert np.array_equal(g["status"] & ~0x100, o["status"] & ~0x100)
+    # the crossings recorded before the ray stalls agree as elsewhere
+    both = ((g["status"] & 8) != 0) & ((o["status"] & 8) != 0)
+    assert both.sum() > 20
+    assert rel(g["r_cross"][both], o["r_cross"][both]).max() <= REL_RT
+
+
 # ---------------------------------------------------------------- torus
 
-def compare_torus(g, o, nf, label):
+def assert_capture_classification(st_g, o, a, incl_deg, label):
+    """Capture flags agree on every ray except within 1e-6 M of the critical curve (sky-plane
+    distance from the ray's exact xi, eta); the distance is computed for the disagreeing rays."""
+    bad = np.nonzero((st_g & 1) != (o["status"] & 1))[0]
+    if len(bad):
+        xi = o["L"][bad] / o["E"][bad]
+        eta = o["Q"][bad] / o["E"][bad] ** 2
+        d = critical_curve_distance(a, incl_deg, xi, eta)
+        assert np.all(d < 1e-6), (label, bad[d >= 1e-6][:10], d.max())
+    return len(bad)
+
+
+def compare_torus(g, o, nf, label, cam=None):
     st_o, st_g = o["status"], g["status"]
     assert not np.any(st_g == -7), "some ray was never written"
     same = (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
     assert same.mean() >= 0.995, (label, same.mean())
     assert np.array_equal(st_g[same], st_o[same])
+    if cam is not None:
+        assert_capture_classification(st_g, o, cam["a"], cam["incl_deg"], label)
     for f in range(nf):
         I_g, I_o = g["intensity"][f], o["I"][:, f]
         t_g, t_o = g["tau"][f], o["tau"][:, f]
@@ -180,7 +261,7 @@ def test_torus_image_matches_oracle(ctx):
     w = scenes.torus_image(48)
     g = run_gpu(ctx, w)
     o = O.trace_image(oracle_scene(w), 48, 48, -20, 20, -20, 20).ravel()
-    frac = compare_torus(g, o, 1, "torus 48^2")
+    frac = compare_torus(g, o, 1, "torus 48^2", w["camera"])
     print(f"torus 48^2: identical step sequences {frac:.5f}")
     assert g["intensity"][0].max() > 0
 
@@ -191,33 +272,33 @@ def test_torus_multifrequency_ragged(ctx):
     w["camera"]["ny"] = 29
     g = run_gpu(ctx, w)
     o = O.trace_image(oracle_scene(w), 19, 29, -20, 20, -20, 20).ravel()
-    compare_torus(g, o, 8, "torus 8 freqs")
+    compare_torus(g, o, 8, "torus 8 freqs", w["camera"])
 
 
-@pytest.mark.parametrize("nf", [2, 3, 12])
+@pytest.mark.parametrize("nf", [2, 3, 6, 12])
 def test_torus_frequency_counts(ctx, nf):
-    """Every compiled frequency width (2, 4 and 16 slots, partly filled) against the oracle."""
+    """Every compiled frequency width (2, 4, 8 and 16 slots, partly filled) against the oracle."""
     import oracle as O
     freqs = [86e9 * (690.0 / 86.0) ** (k / max(nf - 1, 1)) for k in range(nf)]
     w = scenes.torus_image(11, a=0.9, incl_deg=40.0, freqs=freqs)
     w["camera"]["ny"] = 7
     g = run_gpu(ctx, w)
     o = O.trace_image(oracle_scene(w), 11, 7, -20, 20, -20, 20).ravel()
-    compare_torus(g, o, nf, f"torus {nf} freqs")
+    compare_torus(g, o, nf, f"torus {nf} freqs", w["camera"])
 
 
-def test_torus_full_resolution_sampled(ctx):
-    """The benchmark configuration (1024^2) in its launch shape; the oracle
-    recomputes a seeded sample of pixels one by one."""
-    import oracle as O
+def test_torus_full_resolution_every_pixel(ctx):
+    """The benchmark configuration (1024^2 torus at 230 GHz) in its launch shape, every pixel
+    recomputed by the oracle: capture flags, I_nu and tau_nu on all 1,048,576 rays."""
+    import time
     w = scenes.torus_image(1024)
     g = run_gpu(ctx, w)
-    idx = scenes.sample_pixels(1024, 1024, 400, seed=77)
-    xy = O.pixel_points(1024, 1024, -20, 20, -20, 20)[idx]
-    o = O.trace_points(oracle_scene(w), xy)
-    gs = {k: (v[..., idx] if v.ndim == 2 else v[idx]) for k, v in g.items()}
-    compare_torus(gs, o, 1, "torus 1024^2 sample")
-    assert not np.any(g["status"] == -7)
+    t0 = time.time()
+    o = O.trace_image(oracle_scene(w), 1024, 1024, -20, 20, -20, 20).ravel()
+    print(f"oracle: 1024^2 torus in {time.time() - t0:.1f} s on {O.default_threads()} threads", flush=True)
+    gs = {k: (v.reshape(1, -1) if k in ("intensity", "tau") else v) for k, v in g.items()}
+    frac = compare_torus(gs, o, 1, "torus 1024^2", w["camera"])
+    print(f"torus 1024^2: identical step sequences {frac:.6f}", flush=True)
     assert np.all((g["status"] & 3) != 0)  # every ray ended by capture or escape
 
 
@@ -290,7 +371,7 @@ def test_eight_frequency_results_independent_of_launch_shape(ctx):
     w["camera"]["ny"] = 17
     ref = run_gpu(ctx, w)
     o = O.trace_image(oracle_scene(w), 24, 17, -20, 20, -20, 20).ravel()
-    compare_torus(ref, o, 8, "torus 8 freqs, default launch")
+    compare_torus(ref, o, 8, "torus 8 freqs, default launch", w["camera"])
     try:
         for block, per_cu, refill in [(64, 0, 1), (64, 3, 4), (128, 0, 8), (128, 1, 1), (256, 2, 16)]:
             ctx.set_launch(block, per_cu, refill)

@@ -69,3 +69,22 @@ def test_pixel_solid_angles_cover_the_image_plane():
     assert nx * ny * dom == pytest.approx(whole, rel=1e-14)
     # halving the pitch quarters the pixel
     assert S.pixel_solid_angle(2 * nx, 2 * ny, *ext, mbh, dist) == pytest.approx(dom / 4, rel=1e-15)
+
+
+def test_spectrogram_bins_and_lightcurve():
+    """Spectrogram rows (section 4.4): each ray's weight lands in the bin [e_b, e_b+1) holding its g,
+    rays outside the edges are dropped, and a frame's bins add up to its lightcurve point (the
+    frequency-integrated flux) whenever every g lies inside the edges."""
+    edges = [0.5, 0.75, 1.0, 1.25, 1.5]
+    # frame 0: g cycles through the four bins' midpoints; frame 1: a bin edge and two outsiders
+    g0 = np.array([0.6, 0.8, 1.1, 1.3] * 5)
+    w0 = 2.0 ** -np.arange(20)
+    g1 = np.array([0.75, 1.0, 1.5, 0.49, 1.25])
+    w1 = np.array([1.0, 10.0, 100.0, 1000.0, 10000.0])
+    Sg = S.spot_spectrogram(np.concatenate([w0, w1]), np.concatenate([g0, g1]), [0, 20, 25], [2.0, 0.5], edges)
+    want0 = [2.0 * sum(w0[b::4]) for b in range(4)]
+    np.testing.assert_allclose(Sg[0], want0, rtol=1e-15)
+    # 0.75 -> bin 1, 1.0 -> bin 2, 1.25 -> bin 3; 1.5 (the last edge) and 0.49 are outside
+    np.testing.assert_allclose(Sg[1], [0.0, 0.5, 5.0, 5000.0], rtol=1e-15)
+    lc = S.image_spectra(w0, [0, 20], [2.0])[0, 0]
+    assert Sg[0].sum() == pytest.approx(lc, rel=1e-15)
