@@ -88,3 +88,73 @@ def test_spectrogram_bins_and_lightcurve():
     np.testing.assert_allclose(Sg[1], [0.0, 0.5, 5.0, 5000.0], rtol=1e-15)
     lc = S.image_spectra(w0, [0, 20], [2.0])[0, 0]
     assert Sg[0].sum() == pytest.approx(lc, rel=1e-15)
+
+
+# ------------------------------------------------- Novikov-Thorne disk (f2)
+
+def _circular_orbit(a, r):
+    """Omega, specific energy E and angular momentum L of prograde circular equatorial orbits (M = 1)."""
+    sr = np.sqrt(r)
+    den = r ** 0.75 * np.sqrt(r ** 1.5 - 3 * sr + 2 * a)
+    return 1 / (r ** 1.5 + a), (r ** 1.5 - 2 * sr + a) / den, (r * r - 2 * a * sr + a * a) / den
+
+
+def _page_thorne_f_quadrature(a, r):
+    """f(r) of Eq. (35) from its defining integral (Page & Thorne 1974): the flux
+    F = Mdot/(4 pi r) (-dOmega/dr) / (E - Omega L)^2 int_{r_ISCO}^r (E - Omega L) dL/dr' dr',
+    over its Newtonian form 3 Mdot / (8 pi r^3); derivatives by complex steps, scipy quadrature."""
+    from scipy.integrate import quad
+    from scipy.optimize import minimize_scalar
+    h = 1e-30
+    dOm = lambda x: (_circular_orbit(a, x + 1j * h)[0]).imag / h
+    dL = lambda x: (_circular_orbit(a, x + 1j * h)[2]).imag / h
+    r_ms = minimize_scalar(lambda x: _circular_orbit(a, x)[1], bounds=(1.0 + 1e-6 + (a > 0.99) * 0.1, 10.0),
+                           method="bounded", options={"xatol": 1e-12}).x
+    def integrand(x):
+        Om, E, L = _circular_orbit(a, x)
+        return (E - Om * L) * dL(x)
+    I, _ = quad(integrand, r_ms, r, epsabs=0, epsrel=1e-13, limit=200)
+    Om, E, L = _circular_orbit(a, r)
+    F_over_mdot = -dOm(r) / (E - Om * L) ** 2 * I / (4 * math.pi * r)
+    return F_over_mdot / (3 / (8 * math.pi * r ** 3))
+
+
+@pytest.mark.parametrize("a", [0.0, 0.5, 0.9, 0.998])
+def test_novikov_thorne_factor_closed_form_vs_integral(a):
+    """Page & Thorne's closed form of f(r) equals their defining integral; f vanishes at the ISCO
+    (zero torque there, section 4.3) and tends to 1 far away (the Newtonian disk)."""
+    checked = 0
+    for r in [1.3, 2.5, 4.0, 7.0, 12.0, 30.0, 100.0, 1e4]:
+        f = float(S.novikov_thorne_f(a, r))
+        if f == 0.0:
+            continue  # inside the ISCO
+        assert f == pytest.approx(_page_thorne_f_quadrature(a, r), rel=1e-7), (a, r)
+        checked += 1
+    assert checked >= 5
+    assert np.all(S.novikov_thorne_f(a, np.array([0.5, 0.9])) == 0.0)
+    assert abs(float(S.novikov_thorne_f(a, 1e10)) - 1.0) < 1e-4
+    # vanishes at the ISCO itself
+    import oracle as O
+    assert abs(float(S.novikov_thorne_f(a, O.isco(a) * (1 + 1e-12)))) < 1e-5
+
+
+def test_disk_spectrum_integrates_to_redshifted_stefan_boltzmann():
+    """Each disk pixel contributes g^3 B_nu(T, nu/g); over all frequencies that is g^4 sigma T^4 / pi
+    (Stefan-Boltzmann with the redshift of I_nu/nu^3), so a frequency quadrature of the spectrum
+    gives domega * sum g^4 sigma T_eff^4 / pi; pixels off the disk contribute nothing."""
+    a, mbh, mdot = 0.9, 10.0, 1e19
+    r = np.array([3.0, 5.0, 9.0, 20.0, 2.0, 40.0])
+    g = np.array([1.2, 0.8, 1.05, 0.9, 0.7, 1.0])
+    hit = np.array([True, True, True, True, False, True])
+    nu = np.geomspace(1e14, 1e20, 6001)
+    F = S.disk_spectrum(r, g, hit, [0, 6], [2.0], nu, [a], mbh, mdot)[0]
+    T = S.novikov_thorne_teff(a, r[hit], mbh, mdot)
+    want = 2.0 * np.sum(g[hit] ** 4 * S.SIGMA_SB * T ** 4 / math.pi)
+    lnu = np.log(nu)
+    got = np.sum(0.5 * (F[1:] * nu[1:] + F[:-1] * nu[:-1]) * np.diff(lnu))
+    assert got == pytest.approx(want, rel=1e-5)
+    # Teff from Eq. (35) in cgs: sigma T^4 = 3 G M Mdot f / (8 pi R^3)
+    rg = S.gravitational_radius_cm(mbh)
+    T5 = S.novikov_thorne_teff(a, 5.0, mbh, mdot)
+    assert S.SIGMA_SB * T5 ** 4 == pytest.approx(
+        3 * S.GM_SUN * mbh * mdot * S.novikov_thorne_f(a, 5.0) / (8 * math.pi * (5.0 * rg) ** 3), rel=1e-12)
