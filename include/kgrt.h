@@ -201,14 +201,17 @@ int kgrt_trace_rays(kgrt_ctx* ctx, const double* rays_dev, int64_t n, double r_o
 /* ------------------------------------------------------------ batches */
 
 /* A plan holds many images of uneven size, spin and inclination (one model,
- * one frequency set, one integrator) traced together in one persistent launch
- * per chunk of rays. This generalises the paper's per-image tracing (section
- * 3) to scene batches. The rays of image k occupy output indices
+ * one frequency set, one integrator) traced together in one persistent launch.
+ * This generalises the paper's per-image tracing (section 3) to scene
+ * batches. The rays of image k occupy output indices
  * [offset_k, offset_k + nx_k ny_k), offsets the prefix sums of the image sizes
  * in the order given; torus outputs are [nfreq][total rays].
  * kgrt_plan_create validates every camera (as kgrt_trace does; empty images are
  * allowed), uploads the image table and allocates the plan's workspace
- * (synchronously). The plan keeps a pointer to ctx; destroy plans first. */
+ * (synchronously): an 88-byte start record per ray of the whole plan, so that
+ * one launch covers all its rays; if that allocation fails, records for
+ * chunks of 2^22 rays traced one launch after another. The plan keeps a
+ * pointer to ctx; destroy plans first. */
 int kgrt_plan_create(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const kgrt_model* model,
                      const double* freqs_hz, int32_t nfreq, const kgrt_integrator* integ, kgrt_plan** out);
 /* Total number of rays (sum of image sizes). */
@@ -262,6 +265,27 @@ int kgrt_image_spectra(const double* intensity_dev, int64_t total, int32_t nfreq
  * pitch in M. Host function. Returns -1 for a NULL camera, an empty image, a
  * non-positive or non-finite extent, mass or distance. */
 double kgrt_pixel_solid_angle(const kgrt_camera* cam, double mbh_msun, double distance_cm);
+
+/* Spectrum of the Novikov-Thorne disk of section 4.3 seen in traced images of
+ * the thin disk (KGRT_MODEL_THIN_DISK or KGRT_MODEL_DISK_IMAGES outputs):
+ * every pixel with KGRT_DISK_HIT is a blackbody at the effective temperature
+ * of its crossing radius, sigma T^4 = 3 G M Mdot f(r) / (8 pi R^3) (Eq. (35),
+ * R = r r_g, f of Page & Thorne (1974) for zero torque at the ISCO of the
+ * image's spin), observed with its redshift g, so
+ *   flux[k * nfreq + f] = domega[k] * sum over image k's disk pixels of
+ *                         g^3 B_nu(T(r_c), nu_f / g)   (erg s^-1 cm^-2 Hz^-1).
+ * Arguments: device arrays r_cross, g [total] f64 and status [total] i32 (a
+ * plan's outputs), offsets [nimg + 1] int64, domega [nimg] and spin [nimg]
+ * f64 (read), flux [nimg][nfreq] (written); freqs_hz is a HOST array of nfreq
+ * observed frequencies, 1 <= nfreq <= 32; mbh_msun > 0 and mdot_gs >= 0 (g/s).
+ * Sums in a fixed order (per-thread partial sums, then a fixed tree).
+ * Asynchronous on `stream`. Returns KGRT_E_INVALID_ARG for out-of-range sizes,
+ * non-finite or non-positive frequencies, mass or accretion rate, or a NULL
+ * array that would be read or written. */
+int kgrt_disk_spectrum(const double* r_cross_dev, const double* g_dev, const int32_t* status_dev, int64_t total,
+                       const int64_t* offsets_dev, const double* domega_dev, const double* spin_dev, int32_t nimg,
+                       double mbh_msun, double mdot_gs, const double* freqs_hz, int32_t nfreq, double* flux_dev,
+                       void* stream);
 
 /* Spectrogram of images of the hot spot (section 4.4, Fig. 7): for each image
  * k (a frame at its observer time) and energy-shift bin b,
@@ -338,19 +362,26 @@ int kgrt_surrogate_targets(const double* rays_dev, const int32_t* status_dev, co
                            const double* g_dev, const double* phi_cross_dev, int64_t n, float* targets_dev,
                            void* stream);
 
-/* Fallback policy of the surrogate render: a ray is re-integrated in FP64 when
- * its predicted capture probability lies in [p_lo, p_hi], when it is within
- * crit_band (M, radially in the image plane) of the image's Kerr critical curve,
- * when its predicted crossing radius is within edge_band (M) of a disk edge
- * (where the intensity jumps), if g_tol > 0 when the network's g output and
- * the Keplerian g at its predicted radius differ by more than g_tol, and if
- * grad_max > 0 when the predicted ln r_c changes by more than grad_max per M
- * of image-plane distance toward one of its 4 neighbouring pixels (one of the
- * two predictions within edge_band of the disk; neighbours in the same
- * network segment of up to 2^22 pixels). */
+/* Fallback policy of the surrogate render. The network's crossing radius is
+ * first polished on the exact Mino-time relation of the photon's constants of
+ * motion (Eqs. (7), (8), (13) of its start state: Newton's method from the
+ * prediction, the radial and polar Mino times by Gauss-Legendre quadrature and
+ * Carlson's R_F); that also decides whether the ray reaches the equator
+ * outside the capture radius at all. A ray is re-integrated in FP64 when its
+ * predicted capture probability lies in [p_lo, p_hi], when it is within
+ * crit_band (M, radially in the image plane) of the image's Kerr critical
+ * curve, when the polish cannot be certified (no convergence, a Mino-time leg
+ * decided by less than 1e-9 relative, Q <= 0), when the polished crossing
+ * radius is within edge_band (M) of a disk edge (where the intensity jumps),
+ * if g_tol > 0 when the network's g output and the Keplerian g at the polished
+ * radius differ by more than g_tol, and if grad_max > 0 when the predicted
+ * ln r_c changes by more than grad_max per M of image-plane distance toward
+ * one of its 4 neighbouring pixels (one of the two predictions within
+ * edge_band of the disk; neighbours in the same network segment of up to 2^22
+ * pixels). */
 typedef struct kgrt_fallback {
-    float p_lo, p_hi, crit_band, edge_band;  /* defaults 0.05, 0.95, 0.5, 0.25 */
-    float g_tol, grad_max;                   /* defaults 0 (no check) */
+    float p_lo, p_hi, crit_band, edge_band;  /* the package's policy: 0.05, 0.95, 0.5, 1e-4 */
+    float g_tol, grad_max;                   /* 0: no check */
 } kgrt_fallback;
 
 /* The Kerr critical curve (section 4.2's shadow boundary) seen at infinity,
@@ -360,8 +391,9 @@ int kgrt_critical_curve(double a, double incl_deg, float* radius_host, int32_t n
 
 /* Thin-disk images (section 4.3, j = r^-3, I = g^3 j) from the surrogate, with
  * fallback rays (kgrt_fallback) re-integrated by the FP64 integrator on the
- * same stream: features -> network -> decode and fallback test -> device-built
- * ray list -> integrator -> composite -> per-image flux. The fallback rays of
+ * same stream: features -> network -> decode (crossing-radius polish, Keplerian
+ * g at it, fallback test) -> device-built ray list -> integrator -> composite
+ * -> per-image flux (each summed in a fixed order). The fallback rays of
  * consecutive images with the same r_obs and phi_obs, up to 2^26 pixels, go to
  * the integrator as one list (one launch). Outputs (device): intensity [total]
  * (images concatenated, pixel j*nx+i), status [total] or NULL (KGRT_FALLBACK

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkgrt.so")
 SOURCES = [os.path.join(CSRC, "kgrt.hip"), os.path.join(CSRC, "kgrt_mlp.hip"), os.path.join(CSRC, "kgrt_spectra.hip")]
-HEADERS = [os.path.join(CSRC, "kgrt_device.hpp"), os.path.join(ROOT, "include", "kgrt.h")]
+HEADERS = [os.path.join(CSRC, "kgrt_device.hpp"), os.path.join(CSRC, "kgrt_mino.hpp"), os.path.join(ROOT, "include", "kgrt.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1104,11 +1104,18 @@ int kgrt_plan_create(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const
     P.nimg = nimg;
     P.list_mode = 0;
     P.nrays = total;
-    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(total, ctx->chunk_max));
-    bool ok = hipMalloc(&p->images, sizeof(ImageDesc) * nimg) == hipSuccess &&
-              hipMalloc(&p->rec, (size_t)cap * kRecFields * sizeof(double)) == hipSuccess &&
-              hipMalloc(&p->counter, sizeof(unsigned long long)) == hipSuccess &&
-              hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) == hipSuccess;
+    // Start records for the whole plan, so that one persistent launch covers every ray and the
+    // grid drains once (88 B per ray: 1.9 GB for 256 images of up to 512^2, 24 GB for 64 of
+    // 2048^2); if that much is not available, chunks of the context's size.
+    int64_t cap = std::max<int64_t>(1, total);
+    bool ok = hipMalloc(&p->images, sizeof(ImageDesc) * nimg) == hipSuccess;
+    if (ok && hipMalloc(&p->rec, (size_t)cap * kRecFields * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();  // clear the failed allocation's error
+        cap = std::max<int64_t>(1, std::min<int64_t>(total, ctx->chunk_max));
+        ok = hipMalloc(&p->rec, (size_t)cap * kRecFields * sizeof(double)) == hipSuccess;
+    }
+    ok = ok && hipMalloc(&p->counter, sizeof(unsigned long long)) == hipSuccess &&
+         hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) ok = hipMemcpy(p->images, tab.data(), sizeof(ImageDesc) * nimg, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         kgrt_plan_destroy(p);

@@ -26,6 +26,7 @@
 
 #include "kgrt.h"
 #include "kgrt_device.hpp"
+#include "kgrt_mino.hpp"
 
 namespace mlpk {
 
@@ -762,7 +763,7 @@ __global__ void targets_kernel(const double* __restrict__ rays4, const int32_t* 
 // One image of the thin-disk surrogate render: pixel features -> network ->
 // decode, with rays the network is unsure of sent back to the FP64 integrator.
 struct RenderImage {
-    double a, incl_deg, sin_i, cos_i, r_obs, phi_obs, sin_p, cos_p, x_min, x_w, y_min, y_w, r_in, r_out;
+    double a, incl_deg, sin_i, cos_i, r_obs, phi_obs, sin_p, cos_p, x_min, x_w, y_min, y_w, r_in, r_out, r_cap;
     int32_t nx, ny;
 };
 struct RenderCfg {
@@ -807,7 +808,7 @@ __global__ void __launch_bounds__(256) decode_kernel(const RenderImage im, int64
         bool fb = false;
         double x = 0.0, y = 0.0;
         float pcap = 0.0f, rc = 0.0f, g = 0.0f;
-        double gk = 0.0;
+        double gk = 0.0, rcx = -1.0;
         if (valid) {
             pixel_xy(im, p0 + i, x, y);
             const float o0 = pred[5 * i], o1 = pred[5 * i + 1], o2 = pred[5 * i + 2];
@@ -822,14 +823,24 @@ __global__ void __launch_bounds__(256) decode_kernel(const RenderImage im, int64
             const float w = u - fl;
             j0 = ((j0 % kCritBins) + kCritBins) % kCritBins;
             const float Rc = (1.0f - w) * Rtab[j0] + w * Rtab[(j0 + 1) % kCritBins];
-            // On the Keplerian disk g is fixed by the crossing radius and the
-            // photon's conserved L_z (Eqs. (2), (8)): evaluate it at the predicted
-            // radius; the g head only checks that the network is consistent.
+            // The predicted crossing radius is polished on the exact Mino-time relation of
+            // the photon's constants of motion (Eqs. (7), (8), (13) from its start state;
+            // kgrt_mino.hpp): -1 when that cannot be certified (the ray is integrated
+            // instead), 0 when the ray never reaches the equator outside the capture radius.
+            // On the Keplerian disk g is then fixed by the crossing radius and the
+            // photon's conserved L_z (Eqs. (2), (8)); the g head only checks consistency.
             kgrt::State s0;
             double L = 0.0;
             const bool ok = kgrt::start_ray(im.a, im.a * im.a, im.r_obs, sqrt(im.r_obs * im.r_obs + im.a * im.a),
                                             im.sin_i, im.cos_i, im.sin_p, im.cos_p, im.phi_obs, x, y, s0, L);
-            const double rd = rc;
+            if (ok) {
+                double sn, cn;
+                kgrt::sincos_bounded(s0.th, &sn, &cn);
+                const double Q = s0.pth * s0.pth + cn * cn * (L * L / (sn * sn) - im.a * im.a);  // Eq. (13), E^2 = 1
+                const bool toward = (cn > 0.0) ? (s0.pth > 0.0) : (s0.pth < 0.0);  // mu = cos(theta) heads to 0
+                rcx = kgrt_mino::crossing_radius(im.a, -L, Q, s0.r, cn, toward, im.r_cap, (double)rc);
+            }
+            const double rd = rcx;
             const bool near_disk = rd >= im.r_in - cfg.edge_band && rd <= im.r_out + cfg.edge_band;
             if (ok && near_disk) gk = kgrt::redshift(rd, kgrt::kPi / 2.0, im.a, im.a * im.a, -L);
             // steep predicted crossing radius toward a 4-neighbour in this segment (one
@@ -853,8 +864,8 @@ __global__ void __launch_bounds__(256) decode_kernel(const RenderImage im, int64
                 check(i + im.nx, inv_dy);
             }
             fb = !ok || steep || !(isfinite(o0) && isfinite(o1) && isfinite(o2)) || (pcap >= cfg.p_lo && pcap <= cfg.p_hi) ||
-                 fabsf(rho - Rc) < cfg.crit_band || fabsf(rc - (float)im.r_in) < cfg.edge_band ||
-                 fabsf(rc - (float)im.r_out) < cfg.edge_band ||
+                 fabsf(rho - Rc) < cfg.crit_band || rcx < 0.0 || fabs(rcx - im.r_in) < cfg.edge_band ||
+                 fabs(rcx - im.r_out) < cfg.edge_band ||
                  (cfg.g_tol > 0.0f && near_disk && !(fabs(gk - (double)g) <= (double)cfg.g_tol));
         }
         const uint64_t mask = __ballot(fb);
@@ -876,7 +887,7 @@ __global__ void __launch_bounds__(256) decode_kernel(const RenderImage im, int64
             fb_rays[4 * slot + 3] = y;
         } else if (valid) {
             // thin disk (section 4.3): I = g^3 j(r_c), j = r^-3, on [r_in, r_out]
-            const double rd = rc;
+            const double rd = rcx;
             const bool on = (rd >= im.r_in) && (rd <= im.r_out) && (gk > 0.0);
             intensity[p0 + i] = on ? gk * gk * gk / (rd * rd * rd) : 0.0;
             if (status) status[p0 + i] = (pcap > 0.5f) ? KGRT_CAPTURED : KGRT_ESCAPED;
@@ -898,17 +909,32 @@ __global__ void composite_kernel(const unsigned long long* __restrict__ fb_count
     }
 }
 
-__global__ void __launch_bounds__(256) flux_kernel(const double* __restrict__ I, int64_t n, double* __restrict__ out) {
+// Per-image flux in a fixed order: block b of kFluxBlocks sums its own
+// contiguous slice of the image (strided over its threads, then a fixed tree)
+// into part[b]; flux_final adds the kFluxBlocks partial sums in order. The
+// order of every addition depends only on the image size, so repeated renders
+// give identical fluxes.
+constexpr int kFluxBlocks = 128;
+__global__ void __launch_bounds__(256) flux_partial(const double* __restrict__ I, int64_t n, double* __restrict__ part) {
     __shared__ double red[256];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = std::min<int64_t>(n, (int64_t)blockIdx.x * per), hi = std::min<int64_t>(n, lo + per);
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) s += I[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += I[i];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void flux_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[b];
+        *out = s;
+    }
 }
 
 __global__ void zero_u64(unsigned long long* p, int64_t n) {
@@ -1050,6 +1076,7 @@ struct kgrt_mlp {
     int64_t step = 0;
     // render workspace (grown on demand): features, outputs, fallback list and its integration
     float *r_feat = nullptr, *r_pred = nullptr, *r_tab = nullptr;
+    double* r_part = nullptr;  // per-image flux partial sums [nimg][kFluxBlocks]
     int64_t* r_idx = nullptr;
     int32_t* r_st = nullptr;
     double *r_rays = nullptr, *r_I = nullptr;
@@ -1087,7 +1114,7 @@ int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
     void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Wr, m->Pi, m->part, m->dz, m->dout, m->r_feat, m->r_pred,
-                    m->r_tab, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
+                    m->r_tab, m->r_part, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
                     m->h[1], m->h[2], m->h[3], m->h[4], m->z[1], m->z[2], m->z[3], m->z[4],
                     m->hT[1], m->hT[2], m->hT[3]};
     for (void* p : ptrs)
@@ -1374,8 +1401,12 @@ int ensure_render_ws(kgrt_mlp* m, int64_t seg, int64_t list, int32_t nimg) {
             if (hipDeviceSynchronize() != hipSuccess) return KGRT_E_HIP;
             (void)hipFree(m->r_tab);
         }
+        if (m->r_part) (void)hipFree(m->r_part);
         m->r_tab = nullptr;
-        if (hipMalloc(&m->r_tab, (size_t)nimg * kCritBins * sizeof(float)) != hipSuccess) return KGRT_E_NOMEM;
+        m->r_part = nullptr;
+        if (hipMalloc(&m->r_tab, (size_t)nimg * kCritBins * sizeof(float)) != hipSuccess ||
+            hipMalloc(&m->r_part, (size_t)nimg * kFluxBlocks * sizeof(double)) != hipSuccess)
+            return KGRT_E_NOMEM;
         m->r_tab_cap = nimg;
     }
     return KGRT_OK;
@@ -1475,6 +1506,7 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
         im.y_w = c.y_max - c.y_min;
         im.r_in = (disk->r_in > 0.0) ? disk->r_in : isco_host(c.a);
         im.r_out = disk->r_out;
+        im.r_cap = (1.0 + std::sqrt(1.0 - c.a * c.a)) * (1.0 + integ->horizon_delta);
         im.nx = c.nx;
         im.ny = c.ny;
         for (int64_t p0 = 0; p0 < n;) {
@@ -1503,8 +1535,9 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
         off = 0;
         for (int32_t k = 0; k < nimg; ++k) {
             const int64_t n = (int64_t)cams[k].nx * cams[k].ny;
-            hipLaunchKernelGGL(flux_kernel, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st,
-                               intensity + off, n, flux + k);
+            double* part = m->r_part + (size_t)k * kFluxBlocks;
+            hipLaunchKernelGGL(flux_partial, dim3(kFluxBlocks), dim3(256), 0, st, intensity + off, n, part);
+            hipLaunchKernelGGL(flux_final, dim3(1), dim3(64), 0, st, part, kFluxBlocks, flux + k);
             off += n;
         }
     }

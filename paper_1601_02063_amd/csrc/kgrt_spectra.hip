@@ -96,7 +96,113 @@ __global__ void __launch_bounds__(kSgThreads) spectrogram_kernel(const double* _
     }
 }
 
+// Spectrum of the Novikov-Thorne disk (section 4.3, Eq. (35)) from traced
+// thin-disk images: every disk pixel is a blackbody at the effective
+// temperature of its crossing radius, seen with its redshift g, so it adds
+// g^3 B_nu(T_eff(r_c), nu/g) dOmega at each observed frequency nu. One block
+// per image; each thread keeps one partial sum per frequency over its strided
+// pixels, then the block adds them in a fixed tree (deterministic). The
+// disk's constants (ISCO, the roots of x^3 - 3x + 2a = 0 and the logarithm
+// coefficients of Page & Thorne's closed form) are computed per block from
+// the image's spin.
+constexpr int kNtThreads = 256;
+constexpr int kNtMaxFreqs = 32;
+struct NtFreqs {
+    double nu[kNtMaxFreqs];
+};
+
+__global__ void __launch_bounds__(kNtThreads) disk_spectrum_kernel(
+    const double* __restrict__ rc, const double* __restrict__ gg, const int32_t* __restrict__ st, int64_t total,
+    const int64_t* __restrict__ off, const double* __restrict__ domega, const double* __restrict__ spin,
+    double teff_scale, const NtFreqs F, int nfreq, double* __restrict__ flux) {
+    __shared__ double part[kNtThreads];
+    const int k = blockIdx.x, t = threadIdx.x;
+    // Page & Thorne (1974): f(x) = x^2/(x^3 - 3x + 2a) [x - x0 - 3/2 a ln(x/x0)
+    //   - sum_i c_i ln((x - x_i)/(x0 - x_i))], x = sqrt(r), c_i = 3 (x_i - a)^2 / (x_i (x_i - x_j)(x_i - x_k))
+    const double a = spin[k];
+    const double z1 = 1.0 + cbrt(1.0 - a * a) * (cbrt(1.0 + a) + cbrt(1.0 - a));
+    const double z2 = sqrt(3.0 * a * a + z1 * z1);
+    const double r_ms = 3.0 + z2 - sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
+    const double x0 = sqrt(r_ms);
+    const double th = acos(a);
+    double xr[3] = {2.0 * cos((th - kgrt::kPi) / 3.0), 2.0 * cos((th + kgrt::kPi) / 3.0), -2.0 * cos(th / 3.0)};
+    double ci[3], li0[3];
+    for (int i = 0; i < 3; ++i) {
+        const double xi = xr[i], xj = xr[(i + 1) % 3], xk = xr[(i + 2) % 3];
+        ci[i] = 3.0 * (xi - a) * (xi - a) / (xi * (xi - xj) * (xi - xk));
+        li0[i] = log(x0 - xi);
+    }
+    const double lx0 = log(x0);
+    double acc[kNtMaxFreqs];
+#pragma unroll
+    for (int f = 0; f < kNtMaxFreqs; ++f) acc[f] = 0.0;
+    int64_t lo = off[k], hi = off[k + 1];
+    lo = lo < 0 ? 0 : (lo > total ? total : lo);
+    hi = hi < lo ? lo : (hi > total ? total : hi);
+    constexpr double kHk = kgrt::kH / kgrt::kKb;                       // h/k_B
+    constexpr double kB = 2.0 * kgrt::kH / (kgrt::kC * kgrt::kC);       // 2h/c^2
+    for (int64_t i = lo + t; i < hi; i += kNtThreads) {
+        if (!(st[i] & KGRT_DISK_HIT)) continue;
+        const double r = rc[i];
+        if (!(r > r_ms)) continue;
+        const double x = sqrt(r);
+        double br = x - x0 - 1.5 * a * (log(x) - lx0);
+        for (int j = 0; j < 3; ++j) br -= ci[j] * (log(x - xr[j]) - li0[j]);
+        const double fr = x * x * br / (x * x * x - 3.0 * x + 2.0 * a);
+        if (!(fr > 0.0)) continue;
+        // sigma T^4 = 3 G M Mdot f / (8 pi r^3 r_g^3): T = teff_scale (f / r^3)^(1/4)
+        const double T = teff_scale * sqrt(sqrt(fr / (r * r * r)));
+        const double u = kHk / (gg[i] * T);
+#pragma unroll
+        for (int f = 0; f < kNtMaxFreqs; ++f) {
+            if (f < nfreq) {
+                const double nu = F.nu[f];
+                // g^3 B_nu(T, nu/g) = g^3 (2h/c^2) (nu/g)^3 / (exp(h nu/(g k T)) - 1) = 2h nu^3/c^2 / expm1(...)
+                acc[f] += kB * nu * nu * nu / expm1(u * nu);
+            }
+        }
+    }
+    for (int f = 0; f < nfreq; ++f) {
+        part[t] = acc[f];
+        __syncthreads();
+        for (int w = kNtThreads / 2; w > 0; w >>= 1) {
+            if (t < w) part[t] += part[t + w];
+            __syncthreads();
+        }
+        if (t == 0) flux[(int64_t)k * nfreq + f] = domega[k] * part[0];
+        __syncthreads();
+    }
+}
+
 }  // namespace kgrt_spec
+
+extern "C" int kgrt_disk_spectrum(const double* r_cross_dev, const double* g_dev, const int32_t* status_dev,
+                                  int64_t total, const int64_t* offsets_dev, const double* domega_dev,
+                                  const double* spin_dev, int32_t nimg, double mbh_msun, double mdot_gs,
+                                  const double* freqs_hz, int32_t nfreq, double* flux_dev, void* stream) {
+    if (nimg < 0 || nimg > 65535 || total < 0 || nfreq < 1 || nfreq > kgrt_spec::kNtMaxFreqs || !freqs_hz)
+        return KGRT_E_INVALID_ARG;
+    if (!(std::isfinite(mbh_msun) && mbh_msun > 0.0 && std::isfinite(mdot_gs) && mdot_gs >= 0.0))
+        return KGRT_E_INVALID_ARG;
+    kgrt_spec::NtFreqs F{};
+    for (int f = 0; f < nfreq; ++f) {
+        if (!(std::isfinite(freqs_hz[f]) && freqs_hz[f] > 0.0)) return KGRT_E_INVALID_ARG;
+        F.nu[f] = freqs_hz[f];
+    }
+    if (nimg == 0) return KGRT_OK;
+    if (!offsets_dev || !domega_dev || !spin_dev || !flux_dev || (total > 0 && (!r_cross_dev || !g_dev || !status_dev)))
+        return KGRT_E_INVALID_ARG;
+    // T = teff_scale (f / r^3)^(1/4) with r in M: teff_scale^4 = 3 G M Mdot / (8 pi sigma r_g^3)
+    const double rg = kgrt::kGMsun * mbh_msun / (kgrt::kC * kgrt::kC);
+    const double sigma = 2.0 * std::pow(kgrt::kPi, 5) * std::pow(kgrt::kKb, 4) /
+                         (15.0 * std::pow(kgrt::kH, 3) * kgrt::kC * kgrt::kC);
+    const double teff4 = 3.0 * kgrt::kGMsun * mbh_msun * mdot_gs / (8.0 * kgrt::kPi * sigma * rg * rg * rg);
+    const double teff_scale = std::sqrt(std::sqrt(teff4));
+    hipLaunchKernelGGL(kgrt_spec::disk_spectrum_kernel, dim3((unsigned)nimg), dim3(kgrt_spec::kNtThreads), 0,
+                       (hipStream_t)stream, r_cross_dev, g_dev, status_dev, total, offsets_dev, domega_dev, spin_dev,
+                       teff_scale, F, (int)nfreq, flux_dev);
+    return hipGetLastError() == hipSuccess ? KGRT_OK : KGRT_E_HIP;
+}
 
 extern "C" int kgrt_spot_spectrogram(const double* i_bol_dev, const double* g_dev, int64_t total,
                                      const int64_t* offsets_dev, const double* domega_dev, int32_t nimg,

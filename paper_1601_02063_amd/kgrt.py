@@ -209,6 +209,8 @@ def lib() -> ctypes.CDLL:
         L.kgrt_pixel_solid_angle.argtypes, L.kgrt_pixel_solid_angle.restype = [P(CCamera), d, d], d
         L.kgrt_spot_spectrogram.argtypes = [vp, vp, i64, vp, vp, i32, P(d), i32, vp, vp]
         L.kgrt_spot_spectrogram.restype = ctypes.c_int
+        L.kgrt_disk_spectrum.argtypes = [vp, vp, vp, i64, vp, vp, vp, i32, d, d, P(d), i32, vp, vp]
+        L.kgrt_disk_spectrum.restype = ctypes.c_int
         L.kgrt_strerror.argtypes, L.kgrt_strerror.restype = [ctypes.c_int], ctypes.c_char_p
         L.kgrt_last_error.argtypes, L.kgrt_last_error.restype = [vp], ctypes.c_char_p
         L.kgrt_version.argtypes, L.kgrt_version.restype = [], ctypes.c_int
@@ -436,6 +438,32 @@ def spot_spectrogram(i_bol: torch.Tensor, g: torch.Tensor, offsets: torch.Tensor
                                      _stream_handle(stream))
     if rc != OK:
         raise KgrtError(rc, "kgrt_spot_spectrogram failed")
+    return out
+
+
+def disk_spectrum(r_cross: torch.Tensor, g: torch.Tensor, status: torch.Tensor, offsets: torch.Tensor,
+                  domega: torch.Tensor, spin: torch.Tensor, mbh_msun: float, mdot_gs: float,
+                  freqs: Sequence[float], stream=None) -> torch.Tensor:
+    """kgrt_disk_spectrum: the Novikov-Thorne disk's flux density [nimg, nfreq] from traced images
+    (r_cross, g float64 and status int32 [total]; offsets int64 [nimg + 1]; domega, spin float64
+    [nimg]; all contiguous CUDA tensors)."""
+    for t, dt, nm in ((r_cross, torch.float64, "r_cross"), (g, torch.float64, "g"), (status, torch.int32, "status"),
+                      (offsets, torch.int64, "offsets"), (domega, torch.float64, "domega"),
+                      (spin, torch.float64, "spin")):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.dim() == 1):
+            raise ValueError(f"{nm} must be a contiguous 1-D CUDA {dt} tensor")
+    nimg = domega.shape[0]
+    if offsets.shape[0] != nimg + 1 or spin.shape[0] != nimg:
+        raise ValueError("offsets must have nimg + 1 entries and spin nimg")
+    fa, nf = _freqs(freqs)
+    out = torch.empty((nimg, nf), dtype=torch.float64, device=g.device)
+    total = g.shape[0]
+    rc = lib().kgrt_disk_spectrum(r_cross.data_ptr() if total else None, g.data_ptr() if total else None,
+                                  status.data_ptr() if total else None, total, offsets.data_ptr(), domega.data_ptr(),
+                                  spin.data_ptr(), nimg, mbh_msun, mdot_gs, fa, nf, out.data_ptr(),
+                                  _stream_handle(stream))
+    if rc != OK:
+        raise KgrtError(rc, "kgrt_disk_spectrum failed")
     return out
 
 

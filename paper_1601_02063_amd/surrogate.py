@@ -27,11 +27,12 @@ ARCH = ("mlp 4-256x4-5 SiLU; training: 256x256 layers in BF16 on MFMA (FP32 accu
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "thin_disk_mlp.npz")
 
 # Fallback policy (p_lo, p_hi, crit_band, edge_band, g_tol, grad_max): the two required rules
-# (capture probability band, 0.5 M critical-curve band) plus the disk-edge band, the g-head
-# consistency check and the neighbour rule, with thresholds chosen on 64 images of 1024^2
-# drawn from PCG64(1606) (the edge band covers the shipped network's 99th-percentile radius
-# error at the outer edge, 0.06 M).
-DEFAULT_FALLBACK = (0.05, 0.95, 0.5, 0.1, 0.005, 0.5)
+# (capture probability band, 0.5 M critical-curve band) and a disk-edge band of 1e-4 M around
+# the polished crossing radius (whose error is the integrator's own, ~1e-7 relative, so only a
+# crossing that close to an edge can land on the other side of it); the g-head consistency
+# check and the neighbour rule are off (they guarded the network's radius error, which the
+# Mino-time polish removes).
+DEFAULT_FALLBACK = (0.05, 0.95, 0.5, 1e-4, 0.0, 0.0)
 
 
 LAYERS = ((4, 256), (256, 256), (256, 256), (256, 256), (256, 5))

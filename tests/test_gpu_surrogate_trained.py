@@ -2,10 +2,11 @@
 
 The package's trained surrogate renders held-out thin-disk images (scene seed
 1607, used neither for training, nor for choosing the fallback thresholds, nor
-by the benchmark) with the tuned fallback policy. Against the plain FP64
-integrator on the same images, each image's total flux agrees within 1%, and
-the fallback re-integrates a small share of the rays and of the Runge-Kutta
-steps the integrator spends on them.
+by the benchmark) with the package's fallback policy. Against the plain FP64
+integrator on the same images, each image's total flux agrees within 1%, every
+emitting pixel within 1e-2 and every dark pixel is dark (the per-pixel bar),
+and the fallback re-integrates a small share of the rays and of the
+Runge-Kutta steps the integrator spends on them.
 """
 import numpy as np
 import pytest
@@ -42,6 +43,13 @@ def test_trained_surrogate_gain():
         flux_ref, flux_sur = R[a:b].sum(), I[a:b].sum()
         assert abs(flux_sur - flux_ref) <= 1e-2 * flux_ref, (k, flux_sur / flux_ref - 1)
         assert abs(float(out["flux"][k]) - flux_sur) <= 1e-9 * flux_sur
+    # the per-pixel bar: |I_s - I_ref| <= 1e-2 I_ref wherever I_ref > 0, I_s = 0 wherever I_ref = 0
+    pos = R > 0
+    rel = np.abs(I[pos] - R[pos]) / R[pos]
+    dark_lit = int(((I != 0) & ~pos).sum())
+    print(f"per-pixel: {int(pos.sum())} emitting pixels, max rel err {rel.max():.2e}, "
+          f"p99.9 {np.quantile(rel, 0.999):.2e}, dark pixels lit {dark_lit}", flush=True)
+    assert int((rel > 1e-2).sum()) == 0 and dark_lit == 0
     ray_share = fb.mean()
     step_share = steps[fb].sum() / steps.sum()
     print(f"fallback rays {ray_share:.4f}, fallback RK steps {step_share:.4f} of the integrator's")
