@@ -4,8 +4,10 @@ A plain, slow, obviously-correct reference of the method of Pu, Yun, Younsi &
 Yoon (2016, "Odyssey"): rays traced backwards from a flat image plane through
 Kerr spacetime with an adaptive fifth-order Runge-Kutta scheme (section 2.1),
 initial conditions of section 2.2, radiative transfer of section 2.3, thin
-Keplerian disk (section 4.3) and a thermal-synchrotron torus (section 4.5
-emissivity, Eqs. (37)-(39)).
+Keplerian disk (section 4.3, also optically thick through every crossing), the
+orbiting hot spot (section 4.4), a thermal-synchrotron torus (section 4.5
+emissivity, Eqs. (37)-(39)) and the same emissivity from a gridded plasma
+snapshot of the kind GRMHD simulations produce (section 6).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package. The GPU library never does, and this
@@ -33,7 +35,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 CAPTURED, ESCAPED, CROSSED, DISK_HIT = 1, 2, 4, 8
 MAXSTEPS, UNDERFLOW, NONFINITE, REFINE_UNCONVERGED, SPOT_HIT = 16, 32, 64, 256, 512
 
-MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT = 0, 1, 2, 3, 4
+MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT, MODEL_GRID = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = False) -> str:
@@ -62,6 +64,10 @@ class _Scene(ctypes.Structure):
         ("spot_r", ctypes.c_double), ("spot_size", ctypes.c_double), ("spot_phi0", ctypes.c_double),
         ("t_obs", ctypes.c_double),
         ("pr_form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("grid", ctypes.c_void_p),
+        ("grid_nr", ctypes.c_int32), ("grid_nth", ctypes.c_int32), ("grid_nph", ctypes.c_int32),
+        ("grid_reserved", ctypes.c_int32),
+        ("grid_r_min", ctypes.c_double), ("grid_r_max", ctypes.c_double),
     ]
 
 
@@ -108,18 +114,35 @@ class Scene:
     spot_phi0: float = 0.0   # azimuth of the spot centre at t = 0
     t_obs: float = 0.0       # observer time of the image
     pr_form: int = 0   # 0: Eq. (14) before the null condition is substituted; 1: as printed
+    # gridded plasma (model 5): float32 [nr][nth][nph][4] of (ln n_e, ln T_e, ln B, Omega) on the
+    # nodes ln r_i (uniform from ln grid_r_min to ln grid_r_max), theta_j = j pi/(nth - 1),
+    # phi_k = 2 pi k/nph
+    grid: np.ndarray | None = None
+    grid_r_min: float = 1.0
+    grid_r_max: float = 1000.0
 
     def _c(self) -> _Scene:
         if len(self.freqs_hz) > 16:
             raise ValueError("at most 16 frequencies")
         s = _Scene()
         for name, _ in _Scene._fields_:
-            if name in ("freqs_hz", "nfreq", "reserved"):
+            if name in ("freqs_hz", "nfreq", "reserved") or name.startswith("grid"):
                 continue
             setattr(s, name, getattr(self, name) if name != "stop_at_crossing" else int(self.stop_at_crossing))
         s.nfreq = len(self.freqs_hz)
         for i, f in enumerate(self.freqs_hz):
             s.freqs_hz[i] = float(f)
+        if self.grid is not None:
+            g = self.grid
+            if g.dtype != np.float32 or not g.flags.c_contiguous or g.ndim != 4 or g.shape[3] != 4:
+                raise ValueError("grid must be a C-contiguous float32 array [nr][nth][nph][4]")
+            if g.shape[0] < 2 or g.shape[1] < 2 or g.shape[2] < 1:
+                raise ValueError("grid needs nr >= 2, nth >= 2, nph >= 1")
+            s.grid = g.ctypes.data
+            s.grid_nr, s.grid_nth, s.grid_nph = g.shape[:3]
+            s.grid_r_min, s.grid_r_max = self.grid_r_min, self.grid_r_max
+        elif self.model == MODEL_GRID:
+            raise ValueError("the gridded model needs a grid")
         return s
 
 
@@ -138,6 +161,9 @@ def lib():
         L.orc_synchrotron_j.argtypes, L.orc_synchrotron_j.restype = [d, d, d, d], d
         L.orc_redshift.argtypes, L.orc_redshift.restype = [P(_Scene), d, d, d], d
         L.orc_spot_redshift.argtypes, L.orc_spot_redshift.restype = [P(_Scene), d, d, d], d
+        L.orc_redshift_omega.argtypes, L.orc_redshift_omega.restype = [P(_Scene), d, d, d, d], d
+        L.orc_grid_sample.argtypes, L.orc_grid_sample.restype = [P(_Scene), d, d, d, vp], ctypes.c_int
+        L.orc_grid_coeffs.argtypes, L.orc_grid_coeffs.restype = [P(_Scene), d, d, d, d, d, P(d), P(d), P(d)], None
         L.orc_torus_coeffs.argtypes, L.orc_torus_coeffs.restype = [P(_Scene), d, d, d, d, P(d), P(d)], None
         L.orc_rhs.argtypes, L.orc_rhs.restype = [P(_Scene), vp, vp, vp], None
         L.orc_initial_state.argtypes, L.orc_initial_state.restype = [P(_Scene), d, d, vp, vp], ctypes.c_int
@@ -258,3 +284,24 @@ def torus_coeffs(scene: Scene, r: float, th: float, g: float, nu: float):
 def spot_redshift(scene: Scene, r: float, th: float, xi: float) -> float:
     s = scene._c()
     return lib().orc_spot_redshift(ctypes.byref(s), r, th, xi)
+
+
+def redshift_omega(scene: Scene, r: float, th: float, xi: float, omega: float) -> float:
+    s = scene._c()
+    return lib().orc_redshift_omega(ctypes.byref(s), r, th, xi, omega)
+
+
+def grid_sample(scene: Scene, r: float, th: float, ph: float):
+    """(inside, [ln n_e, ln T_e, ln B, Omega]) of the gridded plasma at (r, theta, phi)."""
+    v = np.zeros(4)
+    s = scene._c()
+    ok = lib().orc_grid_sample(ctypes.byref(s), r, th, ph, _ptr(v))
+    return bool(ok), v
+
+
+def grid_coeffs(scene: Scene, r: float, th: float, ph: float, xi: float, nu: float):
+    """(a_lambda, e_lambda, g) of the gridded plasma for a ray with xi = L/E at frequency nu."""
+    s = scene._c()
+    a, e, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_grid_coeffs(ctypes.byref(s), r, th, ph, xi, nu, ctypes.byref(a), ctypes.byref(e), ctypes.byref(g))
+    return a.value, e.value, g.value

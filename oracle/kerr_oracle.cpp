@@ -41,7 +41,7 @@ typedef struct orc_scene {
     double horizon_delta; // capture when r <= r_plus * (1 + horizon_delta)
     int32_t max_steps;    // accepted-step cap
     int32_t model;        // 0 = geodesic only, 1 = thin disk, 2 = torus, 3 = thick thin disk through every
-                          // crossing, 4 = orbiting hot spot
+                          // crossing, 4 = orbiting hot spot, 5 = gridded plasma
     int32_t stop_at_crossing; // terminate at the first equatorial crossing (projection workload)
     int32_t nfreq;        // number of observing frequencies (torus)
     double freqs_hz[16];  // observing frequencies
@@ -57,6 +57,14 @@ typedef struct orc_scene {
     // (default, see orc_rhs), 1 = as printed (kappa form).
     int32_t pr_form;
     int32_t reserved;
+    // gridded plasma (model 5): a snapshot of the kind GRMHD simulations write out (section 6),
+    // float32 values grid[((i * grid_nth + j) * grid_nph + k) * 4 + q] on the nodes
+    //   ln r_i = ln grid_r_min + i (ln grid_r_max - ln grid_r_min) / (grid_nr - 1),
+    //   theta_j = j pi / (grid_nth - 1),  phi_k = 2 pi k / grid_nph (periodic in phi),
+    // q = 0: ln n_e (cm^-3), 1: ln T_e (K), 2: ln B (G), 3: the flow's angular velocity Omega (1/M)
+    const float* grid;
+    int32_t grid_nr, grid_nth, grid_nph, grid_reserved;
+    double grid_r_min, grid_r_max;
 } orc_scene;
 
 typedef struct orc_ray {
@@ -311,6 +319,88 @@ void orc_torus_coeffs(const orc_scene* s, double r, double th, double g, double 
     *e_lam = rg * g * g * j;
 }
 
+// ------------------------------------------------------ gridded plasma
+
+// Redshift (Eq. (2)) of matter circulating with angular velocity Omega at (r, theta),
+// u = u^t (1, 0, 0, Omega) with u^t from u.u = -1; the zero-angular-momentum
+// observer where that motion is not timelike. xi = L_z/E of the ray.
+double orc_redshift_omega(const orc_scene* s, double r, double th, double xi, double Omega) {
+    const double M = s->mass, a = s->a;
+    const double sn = clamped_sin(th), cs = std::cos(th);
+    const double Sigma = r * r + a * a * cs * cs;
+    const double gtt = -(1.0 - 2.0 * M * r / Sigma);
+    const double gtp = -2.0 * M * a * r * sn * sn / Sigma;
+    const double gpp = (r * r + a * a + 2.0 * M * a * a * r * sn * sn / Sigma) * sn * sn;
+    double arg = -(gtt + 2.0 * Omega * gtp + Omega * Omega * gpp);
+    if (!(arg > 0.0)) {
+        Omega = -gtp / gpp;
+        arg = -(gtt + 2.0 * Omega * gtp + Omega * Omega * gpp);
+    }
+    const double ut = 1.0 / std::sqrt(arg);
+    return 1.0 / (ut * (1.0 - xi * Omega));
+}
+
+// The plasma of a simulation snapshot sampled at (r, theta, phi). reading: the
+// snapshot is frozen while the light crosses it (the "fast light" reading of
+// section 6); values between the nodes are the trilinear interpolation in
+// (ln r, theta, phi) of the stored values, phi periodic, theta clamped to
+// [0, pi]; there is no plasma outside [grid_r_min, grid_r_max] nor at or
+// inside the capture radius. Writes the four interpolated values (ln n_e,
+// ln T_e, ln B, Omega) to v; returns 0 where there is no plasma, else 1.
+int orc_grid_sample(const orc_scene* s, double r, double th, double ph, double* v) {
+    for (int q = 0; q < 4; ++q) v[q] = 0.0;
+    const double rcap = horizon_radius(s) * (1.0 + s->horizon_delta);
+    if (!(r > rcap) || r < s->grid_r_min || r > s->grid_r_max) return 0;
+    const int nr = s->grid_nr, nt = s->grid_nth, np = s->grid_nph;
+    // fractional node coordinates along each axis
+    double u1 = (std::log(r) - std::log(s->grid_r_min)) / (std::log(s->grid_r_max) - std::log(s->grid_r_min))
+                * (nr - 1);
+    double u2 = th / PI * (nt - 1);
+    if (u2 < 0.0) u2 = 0.0;
+    if (u2 > nt - 1) u2 = nt - 1;
+    const double u3 = ph / (2.0 * PI) * np;
+    int i0 = (int)std::floor(u1);
+    if (i0 > nr - 2) i0 = nr - 2;
+    if (i0 < 0) i0 = 0;
+    int j0 = (int)std::floor(u2);
+    if (j0 > nt - 2) j0 = nt - 2;
+    const double k0f = std::floor(u3);
+    const double w1 = u1 - i0, w2 = u2 - j0, w3 = u3 - k0f;
+    int k0 = (int)std::fmod(k0f, (double)np);
+    if (k0 < 0) k0 += np;
+    const int k1 = (k0 + 1) % np;
+    const int ii[2] = {i0, i0 + 1}, jj[2] = {j0, j0 + 1}, kk[2] = {k0, k1};
+    const double wi[2] = {1.0 - w1, w1}, wj[2] = {1.0 - w2, w2}, wk[2] = {1.0 - w3, w3};
+    for (int ia = 0; ia < 2; ++ia)
+        for (int jb = 0; jb < 2; ++jb)
+            for (int kc = 0; kc < 2; ++kc) {
+                const double w = wi[ia] * wj[jb] * wk[kc];
+                const float* node = s->grid + ((int64_t)(ii[ia] * nt + jj[jb]) * np + kk[kc]) * 4;
+                for (int q = 0; q < 4; ++q) v[q] += w * (double)node[q];
+            }
+    return 1;
+}
+
+// Emission and absorption per unit affine parameter from the gridded plasma
+// (Eqs. (30)-(31)), as for the torus: thermal synchrotron j_0 of Eqs. (37)-(39)
+// per steradian and Kirchhoff absorption at nu_0 = nu/g, with g of matter
+// moving with the gridded Omega. Also returns that g (0 where there is no plasma).
+void orc_grid_coeffs(const orc_scene* s, double r, double th, double ph, double xi, double nu,
+                     double* a_lam, double* e_lam, double* g_out) {
+    double v[4];
+    *a_lam = 0.0; *e_lam = 0.0; *g_out = 0.0;
+    if (!orc_grid_sample(s, r, th, ph, v)) return;
+    const double ne = std::exp(v[0]), Te = std::exp(v[1]), B = std::exp(v[2]);
+    const double g = orc_redshift_omega(s, r, th, xi, v[3]);
+    const double nu0 = nu / g;
+    const double j = orc_synchrotron_j(nu0, ne, Te, B);
+    const double alpha = (j > 0.0) ? j / planck(nu0, Te) : 0.0;
+    const double rg = GM_SUN * s->mbh_msun / (C_LIGHT * C_LIGHT);
+    *a_lam = rg * alpha / g;
+    *e_lam = rg * g * g * j;
+    *g_out = g;
+}
+
 // ----------------------------------------------------------- hot spot
 
 // The orbiting hot spot of section 4.4. reading: its centre moves on the
@@ -413,6 +503,19 @@ static bool all_finite(const double* y) {
 
 // ---------------------------------------------------------------- tracer
 
+// Transfer coefficients at the point y of a ray with xi = L_z/E: the torus
+// (model 2) or the gridded plasma (model 5).
+static void point_coeffs(const orc_scene* s, const double* y, double xi, double nu, double* a_lam,
+                         double* e_lam) {
+    if (s->model == 5) {
+        double g;
+        orc_grid_coeffs(s, y[0], y[1], y[2], xi, nu, a_lam, e_lam, &g);
+        return;
+    }
+    const double g = orc_redshift(s, y[0], y[1], xi);
+    orc_torus_coeffs(s, y[0], y[1], g, nu, a_lam, e_lam);
+}
+
 // Traces one ray from image-plane point (x, y). If path != nullptr the state
 // after every accepted step is appended (up to path_cap rows of 7 doubles:
 // lambda, y[6]).
@@ -430,8 +533,8 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
     const double rplus = horizon_radius(s);
     const double rcap = rplus * (1.0 + s->horizon_delta);
     const double r_in = (s->r_in > 0.0) ? s->r_in : orc_isco(s->a);
-    const int nf = (s->model == 2) ? s->nfreq : 0;
-    const bool want_cross = (s->model != 2 && s->model != 4);
+    const int nf = (s->model == 2 || s->model == 5) ? s->nfreq : 0;
+    const bool want_cross = (s->model != 2 && s->model != 4 && s->model != 5);
     // model 3: the disk of section 4.3 is optically thick and the ray is followed
     // through every equatorial crossing until one lands on it (the direct image and
     // the higher-order images the hole's lensing makes of the same disk)
@@ -448,8 +551,7 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
     //   dtau = h (a_k + a_k+1)/2,  dI = exp(-tau_k) h (e_k + e_k+1)/2 * (1 - exp(-dtau))/dtau.
     double a_prev[16], e_prev[16];
     for (int f = 0; f < nf; ++f) {
-        double g0 = orc_redshift(s, y[0], y[1], xi);
-        orc_torus_coeffs(s, y[0], y[1], g0, s->freqs_hz[f], &a_prev[f], &e_prev[f]);
+        point_coeffs(s, y, xi, s->freqs_hz[f], &a_prev[f], &e_prev[f]);
         out->I[f] = 0.0; out->tau[f] = 0.0;
     }
 
@@ -540,10 +642,9 @@ static void trace_one(const orc_scene* s, double x, double yimg, orc_ray* out,
             }
             // radiative transfer over the accepted step (Eqs. (30)-(31))
             if (nf > 0) {
-                const double g1 = orc_redshift(s, y[0], y[1], xi);
                 for (int f = 0; f < nf; ++f) {
                     double a1, e1;
-                    orc_torus_coeffs(s, y[0], y[1], g1, s->freqs_hz[f], &a1, &e1);
+                    point_coeffs(s, y, xi, s->freqs_hz[f], &a1, &e1);
                     const double dtau = hdone * (a_prev[f] + a1) / 2.0;
                     const double phi = (dtau > 0.0) ? -std::expm1(-dtau) / dtau : 1.0;
                     out->I[f] += std::exp(-out->tau[f]) * hdone * (e_prev[f] + e1) / 2.0 * phi;
