@@ -73,9 +73,11 @@ def spot_spectrogram(i_bol, g, offsets: Sequence[int], domega: Sequence[float], 
 
 # ----------------------------------------------------- Novikov-Thorne disk
 
-SIGMA_SB = 5.670374419e-5  # Stefan-Boltzmann constant, erg cm^-2 s^-1 K^-4 (CODATA 2018)
-H_PLANCK = 6.62607015e-27  # erg s
-K_BOLTZ = 1.380649e-16     # erg K^-1
+H_PLANCK = 6.62607015e-27  # erg s (exact, SI 2019)
+K_BOLTZ = 1.380649e-16     # erg K^-1 (exact, SI 2019)
+# Stefan-Boltzmann constant, erg cm^-2 s^-1 K^-4: its definition 2 pi^5 k^4 / (15 h^3 c^2), exact
+# with the exact h, k and c (the printed CODATA 2018 value 5.670374419e-5 is this, truncated)
+SIGMA_SB = 2.0 * math.pi ** 5 * K_BOLTZ ** 4 / (15.0 * H_PLANCK ** 3 * C_LIGHT ** 2)
 
 
 def novikov_thorne_f(a: float, r):

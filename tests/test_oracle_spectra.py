@@ -138,6 +138,14 @@ def test_novikov_thorne_factor_closed_form_vs_integral(a):
     assert abs(float(S.novikov_thorne_f(a, O.isco(a) * (1 + 1e-12)))) < 1e-5
 
 
+def test_stefan_boltzmann_constant():
+    """sigma from its definition agrees with the printed CODATA 2018 value (5.670374419e-8 W m^-2
+    K^-4, truncated to ten digits) and with scipy's."""
+    from scipy import constants as C
+    assert S.SIGMA_SB == pytest.approx(5.670374419e-5, rel=2e-10)
+    assert S.SIGMA_SB == pytest.approx(C.Stefan_Boltzmann * 1e3, rel=2e-10)  # W m^-2 K^-4 -> erg cm^-2 s^-1 K^-4
+
+
 def test_disk_spectrum_integrates_to_redshifted_stefan_boltzmann():
     """Each disk pixel contributes g^3 B_nu(T, nu/g); over all frequencies that is g^4 sigma T^4 / pi
     (Stefan-Boltzmann with the redshift of I_nu/nu^3), so a frequency quadrature of the spectrum
