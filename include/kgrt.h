@@ -65,6 +65,10 @@ extern "C" {
                                    ends where it first enters the spot, seen at the emission time
                                    t_obs - Delta t (camera.t_obs); r_cross, phi_cross, t_cross, g,
                                    intensity (g^3 j) and i_bol (g^4 j) describe that entry point */
+#define KGRT_MODEL_GRID 5       /* thermal-synchrotron plasma read from a simulation snapshot on a
+                                   (ln r, theta, phi) grid (the GRMHD data of section 6, sampled along each
+                                   ray): the transfer of Eqs. (30)-(31) with the emissivity of
+                                   Eqs. (37)-(39) as for the torus; outputs as for the torus */
 
 /* Integrator flags. */
 #define KGRT_STOP_AT_CROSSING 1u /* terminate each ray at its first equatorial crossing */
@@ -105,6 +109,24 @@ typedef struct kgrt_model {
      * moves rigidly with the centre (u = u^t (1, 0, 0, Omega), the zero-angular-momentum observer
      * where that is not timelike). spot_size > 0. */
     double spot_r, spot_size, spot_phi0;
+    /* gridded plasma (KGRT_MODEL_GRID; section 6): grid_dev is a DEVICE array of float32 values
+     * grid_dev[((i * grid_nth + j) * grid_nph + k) * 4 + q], owned by the caller and read during the
+     * trace, on the nodes
+     *   ln r_i = ln grid_r_min + i (ln grid_r_max - ln grid_r_min) / (grid_nr - 1),  0 <= i < grid_nr,
+     *   theta_j = j pi / (grid_nth - 1),  0 <= j < grid_nth,
+     *   phi_k = 2 pi k / grid_nph,  0 <= k < grid_nph (periodic in phi),
+     * with q = 0: ln n_e (n_e in cm^-3), 1: ln T_e (K), 2: ln B (G), 3: the angular velocity Omega
+     * (1/M) of the plasma, which moves on circles, u = u^t (1, 0, 0, Omega) (the zero-angular-
+     * momentum observer where that is not timelike). Values between nodes: trilinear interpolation
+     * in (ln r, theta, phi), theta clamped to [0, pi]. No plasma outside [grid_r_min, grid_r_max]
+     * or at or inside the capture radius. The snapshot is frozen while light crosses it. mbh_msun
+     * sets r_g as for the torus; the other torus fields are ignored. grid_nr >= 2, grid_nth >= 2,
+     * grid_nph >= 1, grid_nr * grid_nth * grid_nph < 2^31, 0 < grid_r_min < grid_r_max, grid_dev
+     * 16-byte aligned (one node, four floats, is read as one 16-byte load),
+     * grid_reserved = 0; the other models ignore these fields (grid_dev may be NULL). */
+    const float* grid_dev;
+    int32_t grid_nr, grid_nth, grid_nph, grid_reserved;
+    double grid_r_min, grid_r_max;
 } kgrt_model;
 
 /* Adaptive Runge-Kutta controls (section 2.1). */

@@ -58,6 +58,7 @@ struct KParams {
     double r_in_cfg, r_out;
     double spot_r_cfg, spot_phi0, spot_cut2, spot_inv_2s2;  // hot spot: orbit (<= 0: ISCO), phase, (4 r_spot)^2, 1/(2 r_spot^2)
     TorusParams torus;
+    GridParams grid;  // gridded plasma (snapshot) model
     // integrator
     double rtol, hmax_frac, horizon_delta;
     int32_t max_steps;
@@ -219,10 +220,14 @@ constexpr int kMinRaysPerLane = 3;
 #ifndef KGRT_WAVES_SPOT
 #define KGRT_WAVES_SPOT 3
 #endif
+// the models that carry the transfer of Eqs. (30)-(31) along the ray
+template <int MODEL> struct Transfer {
+    static constexpr bool value = (MODEL == KGRT_MODEL_TORUS || MODEL == KGRT_MODEL_GRID);
+};
 template <int MODEL, int NF> struct WavesPerEU {
     static constexpr int value =
         (MODEL == KGRT_MODEL_HOT_SPOT) ? KGRT_WAVES_SPOT
-        : (MODEL != KGRT_MODEL_TORUS)
+        : !Transfer<MODEL>::value
             ? KGRT_WAVES_DISK
             : (NF == 1 ? KGRT_WAVES_TORUS
                        : ((AccInLds<NF>::value || RayCountResidency<NF>::value) ? 3 : KGRT_WAVES_TORUS_MULTI));
@@ -232,14 +237,39 @@ template <int NF> constexpr size_t acc_lds_bytes(int block) {
     return AccInLds<NF>::value ? (size_t)3 * NF * block * sizeof(double) : 0;
 }
 
+// Frequency-independent transfer quantities at the point y (sy, cy: its clamped
+// sin and cos of theta) of a ray with L_z = L: the redshift g (ig = 1/g) of the
+// emitting matter and the plasma there. The torus flows on Keplerian circles;
+// the snapshot's plasma moves with its gridded Omega.
+template <int MODEL>
+__device__ __forceinline__ Plasma point_plasma(const KParams& PR, const State& y, double sy, double cy, double a,
+                                               double a2, double L, double r_cap, double& g, double& ig) {
+    if constexpr (MODEL == KGRT_MODEL_GRID) {
+        double v[4];
+        if (!grid_sample(PR.grid, y.r, y.th, y.ph, r_cap, v)) {
+            Plasma q;
+            q.emits = false;
+            q.ne = q.Te = q.inv_nu_c = q.jpref = q.hkT = 0.0;
+            g = ig = 1.0;
+            return q;
+        }
+        g = redshift_omega_sc(y.r, sy, cy, a, a2, -L, v[3], ig);
+        return grid_plasma(PR.grid, PR.torus.cJ, v);
+    } else {
+        return torus_plasma(PR.torus, y.r, cy, r_cap);
+    }
+}
+
 // Persistent integrator over the rays of one chunk. MODEL selects the
-// crossing-tracking models (geodesic, thin disk) or the transfer model
-// (torus); NF bounds the number of frequencies carried in registers.
+// crossing-tracking models (geodesic, thin disk, disk images, hot spot) or a
+// transfer model (torus, gridded plasma); NF bounds the number of frequencies
+// carried in registers.
 template <int MODEL, int NF>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WavesPerEU<MODEL, NF>::value, WavesPerEU<MODEL, NF>::value)))
 trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restrict__ rec, int64_t cap) {
-    constexpr bool kDisk = (MODEL != KGRT_MODEL_TORUS);
+    constexpr bool kRT = Transfer<MODEL>::value;
+    constexpr bool kDisk = !kRT;
     // an optically thick disk seen through every crossing: refine each equatorial
     // crossing, end the ray at the first one on the disk (direct or higher-order image)
     constexpr bool kEvery = (MODEL == KGRT_MODEL_DISK_IMAGES);
@@ -337,11 +367,11 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                         sy = clamp_sin(sy);
                         if (isfinite(y.r)) {
                             active = true;
-                            if (MODEL == KGRT_MODEL_TORUS) {
-                                double ig0;
-                                const double g0 = redshift_sc(y.r, sy, cy, a, a2, -L, ig0);
+                            if (kRT) {
+                                double ig0, g0 = 0.0;
+                                if constexpr (MODEL == KGRT_MODEL_TORUS) g0 = redshift_sc(y.r, sy, cy, a, a2, -L, ig0);
                                 const KParams& PR = reread_params();
-                                const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
+                                const Plasma q = point_plasma<MODEL>(PR, y, sy, cy, a, a2, L, r_cap, g0, ig0);
 #pragma unroll
                                 for (int f = 0; f < NF; ++f) {
                                     if constexpr (kLds) {
@@ -367,7 +397,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                             if (O.t_cross) O.t_cross[rid] = 0.0;
                             if (O.i_bol) O.i_bol[rid] = 0.0;
                             if (kEvery && O.n_cross) O.n_cross[rid] = 0;
-                            if (MODEL == KGRT_MODEL_TORUS) {
+                            if (kRT) {
                                 for (int f = 0; f < nf; ++f) {
                                     if (O.intensity) O.intensity[(int64_t)f * nall + rid] = 0.0;
                                     if (O.tau) O.tau[(int64_t)f * nall + rid] = 0.0;
@@ -542,13 +572,13 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                     sy = sn;
                     cy = cn;
                     check_end = true;
-                    if (MODEL == KGRT_MODEL_TORUS) {
+                    if (kRT) {
                         // transfer over the accepted step (Eqs. (30)-(31)): coefficients at
                         // each accepted endpoint, exponential-trapezoid increment
-                        double ig1;
-                        const double g1 = redshift_sc(y.r, sy, cy, a, a2, -L, ig1);
+                        double ig1, g1 = 0.0;
+                        if constexpr (MODEL == KGRT_MODEL_TORUS) g1 = redshift_sc(y.r, sy, cy, a, a2, -L, ig1);
                         const KParams& PR = reread_params();
-                        const Plasma q = torus_plasma(PR.torus, y.r, cy, r_cap);
+                        const Plasma q = point_plasma<MODEL>(PR, y, sy, cy, a, a2, L, r_cap, g1, ig1);
 #pragma unroll
                         for (int f = 0; f < NF; ++f) {
                             if (f < nf) {
@@ -599,7 +629,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
             if (O.steps) O.steps[rid] = steps;
             if (O.attempts) O.attempts[rid] = attempts;
             if (kEvery && O.n_cross) O.n_cross[rid] = ncross;
-            if (MODEL == KGRT_MODEL_TORUS) {
+            if (kRT) {
                 for (int f = 0; f < NF; ++f) {
                     if (f < nf) {
                         const double If = kLds ? lds_t[(3 * f + 1) * blockDim.x] : Iacc[kLds ? 0 : f];
@@ -615,7 +645,7 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
                 if (O.phi_cross) O.phi_cross[rid] = 0.0;
                 if (O.t_cross) O.t_cross[rid] = 0.0;
                 if (O.i_bol) O.i_bol[rid] = 0.0;
-                if (MODEL != KGRT_MODEL_TORUS && O.intensity) O.intensity[rid] = 0.0;
+                if (!kRT && O.intensity) O.intensity[rid] = 0.0;
             }
             active = false;
         }
@@ -674,6 +704,18 @@ int check(std::string& msg, const kgrt_camera* cam, const kgrt_model* m, const d
             if (!(is_finite(m->r_out) && m->r_out > 0.0)) { msg = "model.r_out must be finite and > 0"; return KGRT_E_INVALID_ARG; }
             if (!is_finite(m->r_in) || (m->r_in > 0.0 && !(m->r_in < m->r_out))) { msg = "model.r_in must be <= 0 or < r_out"; return KGRT_E_INVALID_ARG; }
         }
+    } else if (m->kind == KGRT_MODEL_GRID) {
+        if (!m->grid_dev) { msg = "model.grid_dev is NULL"; return KGRT_E_INVALID_ARG; }
+        if ((uintptr_t)m->grid_dev % 16 != 0) { msg = "model.grid_dev must be 16-byte aligned"; return KGRT_E_INVALID_ARG; }
+        if (m->grid_reserved != 0) { msg = "model.grid_reserved must be 0"; return KGRT_E_INVALID_ARG; }
+        if (m->grid_nr < 2 || m->grid_nth < 2 || m->grid_nph < 1) { msg = "grid needs grid_nr >= 2, grid_nth >= 2, grid_nph >= 1"; return KGRT_E_INVALID_ARG; }
+        if ((int64_t)m->grid_nr * m->grid_nth * m->grid_nph >= (int64_t(1) << 31)) { msg = "grid has 2^31 or more nodes"; return KGRT_E_INVALID_ARG; }
+        if (!(is_finite(m->grid_r_min) && is_finite(m->grid_r_max) && m->grid_r_min > 0.0 && m->grid_r_min < m->grid_r_max)) { msg = "grid radii must satisfy 0 < grid_r_min < grid_r_max"; return KGRT_E_INVALID_ARG; }
+        if (!(is_finite(m->mbh_msun) && m->mbh_msun > 0.0)) { msg = "model.mbh_msun must be finite and > 0"; return KGRT_E_INVALID_ARG; }
+        if (nfreq < 1 || nfreq > 16) { msg = "the gridded plasma needs 1 <= nfreq <= 16"; return KGRT_E_INVALID_ARG; }
+        if (!freqs) { msg = "freqs_hz is NULL"; return KGRT_E_INVALID_ARG; }
+        for (int f = 0; f < nfreq; ++f)
+            if (!(is_finite(freqs[f]) && freqs[f] > 0.0)) { msg = "frequencies must be finite and > 0"; return KGRT_E_INVALID_ARG; }
     } else if (m->kind == KGRT_MODEL_TORUS) {
         const double v[9] = {m->n0_cgs, m->r_norm, m->n_index, m->h_over_r, m->T0_K, m->T_index, m->eps_B, m->mbh_msun, m->r_emit_max};
         for (double x : v) if (!is_finite(x)) { msg = "torus parameters must be finite"; return KGRT_E_INVALID_ARG; }
@@ -732,7 +774,7 @@ void set_outputs(KParams& P, const kgrt_outputs* o) {
 void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t nfreq, const kgrt_integrator* in,
                  const kgrt_outputs* o, const kgrt_ctx* ctx) {
     P.model = m->kind;
-    P.nf = (m->kind == KGRT_MODEL_TORUS) ? nfreq : 0;
+    P.nf = (m->kind == KGRT_MODEL_TORUS || m->kind == KGRT_MODEL_GRID) ? nfreq : 0;
     for (int f = 0; f < 16; ++f) P.freqs[f] = (f < P.nf) ? freqs[f] : 0.0;
     P.r_in_cfg = m->r_in;
     P.r_out = m->r_out;
@@ -760,6 +802,24 @@ void fill_common(KParams& P, const kgrt_model* m, const double* freqs, int32_t n
     T.cH = (T.T0 > 0.0) ? kH / (kKb * T.T0) : 0.0;
     T.cBnu = kC * kC / (2.0 * kH);
     for (int f = 0; f < 16; ++f) P.inv_freqs[f] = (f < P.nf && freqs[f] > 0.0) ? 1.0 / freqs[f] : 0.0;
+    GridParams& G = P.grid;
+    G = GridParams{};
+    if (m->kind == KGRT_MODEL_GRID) {
+        G.nodes = (const float4*)m->grid_dev;
+        G.nr = m->grid_nr;
+        G.nth = m->grid_nth;
+        G.nph = m->grid_nph;
+        G.r_min = m->grid_r_min;
+        G.r_max = m->grid_r_max;
+        G.ln_rmin = std::log(m->grid_r_min);
+        G.u1_scale = (m->grid_nr - 1) / (std::log(m->grid_r_max) - std::log(m->grid_r_min));
+        G.u2_scale = (m->grid_nth - 1) / kPi;
+        G.u3_scale = m->grid_nph / (2.0 * kPi);
+        G.inv_nph = 1.0 / m->grid_nph;
+        G.ln_theta1 = std::log(kKb / (kMe * kC * kC));
+        G.inv_cnu = 1.0 / T.cNu;
+        G.h_mec2 = kH / (kMe * kC * kC);
+    }
     P.rtol = in->rtol;
     P.hmax_frac = in->hmax_frac;
     P.horizon_delta = in->horizon_delta;
@@ -806,7 +866,7 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
     if (per_cu <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, shmem) != hipSuccess || per_cu <= 0)
             per_cu = 1;
-        if (RayCountResidency<NF>::value && MODEL == KGRT_MODEL_TORUS) {
+        if (RayCountResidency<NF>::value && Transfer<MODEL>::value) {
             // the residency of two waves per SIMD when three would leave too few rays per lane
             const int64_t rays = (env.limit >= 0) ? std::min<int64_t>(env.limit, P.nrays) : P.nrays;
             const int two_waves = std::max(1, (2 * 4 * 64) / block);  // blocks per CU at two waves per SIMD
@@ -837,6 +897,13 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
 int dispatch_env(kgrt_ctx* ctx, const LaunchEnv& env, const KParams& P, hipStream_t st) {
     if (P.model == KGRT_MODEL_DISK_IMAGES) return launch_one<KGRT_MODEL_DISK_IMAGES, 1>(ctx, env, P, st);
     if (P.model == KGRT_MODEL_HOT_SPOT) return launch_one<KGRT_MODEL_HOT_SPOT, 1>(ctx, env, P, st);
+    if (P.model == KGRT_MODEL_GRID) {
+        if (P.nf <= 1) return launch_one<KGRT_MODEL_GRID, 1>(ctx, env, P, st);
+        if (P.nf <= 2) return launch_one<KGRT_MODEL_GRID, 2>(ctx, env, P, st);
+        if (P.nf <= 4) return launch_one<KGRT_MODEL_GRID, 4>(ctx, env, P, st);
+        if (P.nf <= 8) return launch_one<KGRT_MODEL_GRID, 8>(ctx, env, P, st);
+        return launch_one<KGRT_MODEL_GRID, 16>(ctx, env, P, st);
+    }
     if (P.model != KGRT_MODEL_TORUS) return launch_one<KGRT_MODEL_THIN_DISK, 1>(ctx, env, P, st);
     if (P.nf <= 1) return launch_one<KGRT_MODEL_TORUS, 1>(ctx, env, P, st);
     if (P.nf <= 2) return launch_one<KGRT_MODEL_TORUS, 2>(ctx, env, P, st);
@@ -873,6 +940,7 @@ struct DeviceGuard {
     explicit DeviceGuard(int dev) {
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
         ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+        if (!ok) (void)hipGetLastError();  // leave no sticky error behind for the caller's runtime
     }
     ~DeviceGuard() {
         if (prev >= 0) (void)hipSetDevice(prev);
@@ -883,7 +951,7 @@ struct DeviceGuard {
 
 extern "C" {
 
-int kgrt_version(void) { return 100; }
+int kgrt_version(void) { return 200; }
 
 const char* kgrt_strerror(int code) {
     switch (code) {
@@ -903,14 +971,21 @@ int kgrt_kernel_info_get(kgrt_ctx* ctx, int32_t model, int32_t nfreq, int32_t bl
     if (!ctx || !out) return KGRT_E_INVALID_ARG;
     if (block == 0) block = 256;
     if (block != 64 && block != 128 && block != 256) return fail(ctx, KGRT_E_INVALID_ARG, "block must be 64, 128 or 256");
-    if (model < KGRT_MODEL_GEODESIC || model > KGRT_MODEL_HOT_SPOT) return fail(ctx, KGRT_E_INVALID_ARG, "unknown model");
-    if (model == KGRT_MODEL_TORUS && (nfreq < 1 || nfreq > 16)) return fail(ctx, KGRT_E_INVALID_ARG, "nfreq must be 1..16");
+    if (model < KGRT_MODEL_GEODESIC || model > KGRT_MODEL_GRID) return fail(ctx, KGRT_E_INVALID_ARG, "unknown model");
+    if ((model == KGRT_MODEL_TORUS || model == KGRT_MODEL_GRID) && (nfreq < 1 || nfreq > 16))
+        return fail(ctx, KGRT_E_INVALID_ARG, "nfreq must be 1..16");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
     int rc;
     if (model == KGRT_MODEL_DISK_IMAGES) rc = kernel_info<KGRT_MODEL_DISK_IMAGES, 1>(block, out);
     else if (model == KGRT_MODEL_HOT_SPOT) rc = kernel_info<KGRT_MODEL_HOT_SPOT, 1>(block, out);
-    else if (model != KGRT_MODEL_TORUS) rc = kernel_info<KGRT_MODEL_THIN_DISK, 1>(block, out);
+    else if (model == KGRT_MODEL_GRID) {
+        if (nfreq <= 1) rc = kernel_info<KGRT_MODEL_GRID, 1>(block, out);
+        else if (nfreq <= 2) rc = kernel_info<KGRT_MODEL_GRID, 2>(block, out);
+        else if (nfreq <= 4) rc = kernel_info<KGRT_MODEL_GRID, 4>(block, out);
+        else if (nfreq <= 8) rc = kernel_info<KGRT_MODEL_GRID, 8>(block, out);
+        else rc = kernel_info<KGRT_MODEL_GRID, 16>(block, out);
+    } else if (model != KGRT_MODEL_TORUS) rc = kernel_info<KGRT_MODEL_THIN_DISK, 1>(block, out);
     else if (nfreq <= 1) rc = kernel_info<KGRT_MODEL_TORUS, 1>(block, out);
     else if (nfreq <= 2) rc = kernel_info<KGRT_MODEL_TORUS, 2>(block, out);
     else if (nfreq <= 4) rc = kernel_info<KGRT_MODEL_TORUS, 4>(block, out);
@@ -1039,6 +1114,7 @@ int kgrt_trace_rays_dev(kgrt_ctx* ctx, const double* rays_dev, const int64_t* n_
 
 struct kgrt_plan {
     kgrt_ctx* ctx = nullptr;
+    int device = 0;  // the context's device, kept so that destroying the plan never reads ctx
     KParams P{};
     ImageDesc* images = nullptr;
     double* rec = nullptr;
@@ -1097,6 +1173,7 @@ int kgrt_plan_create(kgrt_ctx* ctx, const kgrt_camera* cams, int32_t nimg, const
     auto* p = new (std::nothrow) kgrt_plan();
     if (!p) return fail(ctx, KGRT_E_NOMEM, "plan allocation failed");
     p->ctx = ctx;
+    p->device = ctx->device;
     p->launch = ctx->launch;
     KParams& P = p->P;
     fill_common(P, model, freqs_hz, nfreq, integ, nullptr, ctx);
@@ -1228,7 +1305,7 @@ int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, k
 
 int kgrt_plan_destroy(kgrt_plan* plan) {
     if (!plan) return KGRT_OK;
-    DeviceGuard g(plan->ctx->device);
+    DeviceGuard g(plan->device);
     if (plan->capture_stream) (void)hipStreamSynchronize(plan->capture_stream);
     drop_graph(plan);
     if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);

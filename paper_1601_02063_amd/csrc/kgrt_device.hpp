@@ -394,10 +394,11 @@ __device__ __forceinline__ double redshift_sc(double r, double s, double c, doub
 }
 
 // As redshift_sc for matter moving with a given angular velocity Om0 (the hot
-// spot of section 4.4 moves rigidly with its centre), the zero-angular-momentum
-// observer where that motion is not timelike.
-__device__ __forceinline__ double redshift_omega(double r, double s, double c, double a, double a2, double xi,
-                                                 double Om0) {
+// spot of section 4.4 moves rigidly with its centre; a simulation snapshot
+// gives the plasma's own Omega), the zero-angular-momentum observer where that
+// motion is not timelike. Returns g and sets ig = 1/g.
+__device__ __forceinline__ double redshift_omega_sc(double r, double s, double c, double a, double a2, double xi,
+                                                    double Om0, double& ig) {
     const double s2 = s * s;
     const double Sigma = r * r + a2 * c * c;
     const double iS = fm::rcp(Sigma);
@@ -410,7 +411,14 @@ __device__ __forceinline__ double redshift_omega(double r, double s, double c, d
         Om = -gtp * fm::rcp(gpp);
         arg = -(gtt + 2.0 * Om * gtp + Om * Om * gpp);
     }
-    return fm::rcp((1.0 - xi * Om) * fm::rsqrt(arg));
+    ig = (1.0 - xi * Om) * fm::rsqrt(arg);
+    return fm::rcp(ig);
+}
+
+__device__ __forceinline__ double redshift_omega(double r, double s, double c, double a, double a2, double xi,
+                                                 double Om0) {
+    double ig;
+    return redshift_omega_sc(r, s, c, a, a2, xi, Om0, ig);
 }
 
 __device__ __forceinline__ double redshift(double r, double th, double a, double a2, double xi) {
@@ -560,6 +568,82 @@ __device__ inline void torus_coeffs(const Plasma& q, const TorusParams& P, doubl
     }
     a_lam = P.rg * alpha * ig;
     e_lam = P.rg * g * g * j;
+}
+
+// A plasma snapshot of the kind GRMHD simulations write out (section 6), in the
+// form the integrator reads it: nodes[(i nth + j) nph + k] = (ln n_e, ln T_e,
+// ln B, Omega) at ln r_i = ln r_min + i dlnr, theta_j = j pi/(nth - 1),
+// phi_k = 2 pi k/nph (periodic). One node is one 16-byte load.
+struct GridParams {
+    const float4* nodes;
+    int32_t nr, nth, nph, pad;
+    double r_min, r_max, ln_rmin;
+    double u1_scale;    // (nr - 1)/(ln r_max - ln r_min)
+    double u2_scale;    // (nth - 1)/pi
+    double u3_scale;    // nph/(2 pi)
+    double inv_nph;     // 1/nph
+    double ln_theta1;   // ln(k_B/(m_e c^2)): ln Theta_e = ln T_e + ln_theta1
+    double inv_cnu;     // 1/cNu: 1/nu_c = Theta_e^-2 B^-1/cNu (nu_c as for the torus)
+    double h_mec2;      // h/(m_e c^2): h/(k_B T_e) = h_mec2/Theta_e
+};
+
+// The snapshot at (r, theta, phi): trilinear interpolation in (ln r, theta, phi)
+// of the node values (theta clamped to [0, pi], phi periodic). No plasma at or
+// inside the capture radius nor outside [r_min, r_max]: returns false and
+// leaves v alone. Cell indices are clamped into the grid, so every load stays
+// inside the nr nth nph nodes whatever r, theta and phi are.
+__device__ inline bool grid_sample(const GridParams& G, double r, double th, double ph, double r_cap, double v[4]) {
+    if (!(r > r_cap) || !(r >= G.r_min) || !(r <= G.r_max)) return false;
+    const double u3 = ph * G.u3_scale;
+    if (!(fabs(u3) < 1e15)) return false;  // a non-finite or absurd azimuth: no sample
+    const double u1 = (fm::log(r) - G.ln_rmin) * G.u1_scale;
+    const double u2 = fmin(fmax(th * G.u2_scale, 0.0), (double)(G.nth - 1));
+    const int i0 = min(max((int)floor(u1), 0), G.nr - 2);
+    const int j0 = min(max((int)floor(u2), 0), G.nth - 2);
+    const double k0f = floor(u3);
+    const double w1 = u1 - i0, w2 = u2 - j0, w3 = u3 - k0f;
+    int k0 = (int)(k0f - (double)G.nph * floor(k0f * G.inv_nph));  // k0f mod nph
+    if (k0 >= G.nph) k0 -= G.nph;
+    if (k0 < 0) k0 += G.nph;
+    k0 = min(max(k0, 0), G.nph - 1);
+    const int k1 = (k0 + 1 == G.nph) ? 0 : k0 + 1;
+    const int64_t row0 = ((int64_t)i0 * G.nth + j0) * G.nph;  // (i0, j0); +nph: j0 + 1; +nth nph: i0 + 1
+    const int64_t sj = G.nph, si = (int64_t)G.nth * G.nph;
+    const float4* __restrict__ n = G.nodes;
+    const float4 c000 = n[row0 + k0], c001 = n[row0 + k1];
+    const float4 c010 = n[row0 + sj + k0], c011 = n[row0 + sj + k1];
+    const float4 c100 = n[row0 + si + k0], c101 = n[row0 + si + k1];
+    const float4 c110 = n[row0 + si + sj + k0], c111 = n[row0 + si + sj + k1];
+    const double wk0 = 1.0 - w3, wj0 = 1.0 - w2, wi0 = 1.0 - w1;
+#define KGRT_TRILERP(q)                                                                                    \
+    {                                                                                                       \
+        const double e00 = wk0 * (double)c000.q + w3 * (double)c001.q;                                      \
+        const double e01 = wk0 * (double)c010.q + w3 * (double)c011.q;                                      \
+        const double e10 = wk0 * (double)c100.q + w3 * (double)c101.q;                                      \
+        const double e11 = wk0 * (double)c110.q + w3 * (double)c111.q;                                      \
+        v[q##_i] = wi0 * (wj0 * e00 + w2 * e01) + w1 * (wj0 * e10 + w2 * e11);                              \
+    }
+    constexpr int x_i = 0, y_i = 1, z_i = 2, w_i = 3;
+    KGRT_TRILERP(x) KGRT_TRILERP(y) KGRT_TRILERP(z) KGRT_TRILERP(w)
+#undef KGRT_TRILERP
+    return true;
+}
+
+// Frequency-independent synchrotron quantities (as torus_plasma) from the sampled
+// ln n_e, ln T_e, ln B: Theta_e = k_B T_e/(m_e c^2), K_2 at 1/Theta_e,
+// 1/nu_c = 1/(cNu B Theta_e^2), h/(k_B T_e). cJ is the torus's emissivity prefactor.
+__device__ inline Plasma grid_plasma(const GridParams& G, double cJ, const double v[4]) {
+    Plasma q;
+    q.emits = true;
+    q.ne = fm::exp(v[0]);
+    const double lnth = v[1] + G.ln_theta1;  // ln Theta_e
+    const double th = fm::exp(lnth);         // Theta_e
+    const double x = fm::rcp(th);            // 1/Theta_e
+    q.Te = 0.0;                              // not used by the coefficients
+    q.inv_nu_c = x * x * fm::exp(-v[2]) * G.inv_cnu;
+    q.jpref = q.ne * cJ * fm::rcp(bessel_k2(x, th, -lnth - 0.69314718055994531));  // ln(x/2)
+    q.hkT = G.h_mec2 * x;
+    return q;
 }
 
 }  // namespace kgrt

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass, field, fields
 from typing import Dict, Iterable, Optional, Sequence
 
@@ -20,7 +21,9 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "kgrt.h")
 OK, E_INVALID_ARG, E_HIP, E_NOMEM, E_NO_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 CAPTURED, ESCAPED, CROSSED, DISK_HIT = 1, 2, 4, 8
 MAXSTEPS, UNDERFLOW, NONFINITE, FALLBACK, REFINE_UNCONVERGED, SPOT_HIT = 16, 32, 64, 128, 256, 512
-MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT = 0, 1, 2, 3, 4
+MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT, MODEL_GRID = 0, 1, 2, 3, 4, 5
+# models whose outputs carry the transfer: intensity and tau are [nfreq][n]
+TRANSFER_MODELS = (MODEL_TORUS, MODEL_GRID)
 STOP_AT_CROSSING = 1
 
 
@@ -43,7 +46,10 @@ class CModel(ctypes.Structure):
                 ("n0_cgs", ctypes.c_double), ("r_norm", ctypes.c_double), ("n_index", ctypes.c_double),
                 ("h_over_r", ctypes.c_double), ("T0_K", ctypes.c_double), ("T_index", ctypes.c_double),
                 ("eps_B", ctypes.c_double), ("mbh_msun", ctypes.c_double), ("r_emit_max", ctypes.c_double),
-                ("spot_r", ctypes.c_double), ("spot_size", ctypes.c_double), ("spot_phi0", ctypes.c_double)]
+                ("spot_r", ctypes.c_double), ("spot_size", ctypes.c_double), ("spot_phi0", ctypes.c_double),
+                ("grid_dev", ctypes.c_void_p), ("grid_nr", ctypes.c_int32), ("grid_nth", ctypes.c_int32),
+                ("grid_nph", ctypes.c_int32), ("grid_reserved", ctypes.c_int32),
+                ("grid_r_min", ctypes.c_double), ("grid_r_max", ctypes.c_double)]
 
 
 class CIntegrator(ctypes.Structure):
@@ -125,11 +131,23 @@ class Model:
     spot_r: float = 0.0       # hot spot orbit radius (<= 0: ISCO)
     spot_size: float = 0.5    # r_spot
     spot_phi0: float = 0.0    # azimuth of the spot centre at t = 0 (radians)
+    # gridded plasma (MODEL_GRID): a contiguous CUDA float32 tensor [nr, nth, nph, 4] of
+    # (ln n_e, ln T_e, ln B, Omega) on the (ln r, theta, phi) nodes, and its radial range
+    grid: Optional[torch.Tensor] = None
+    grid_r_min: float = 1.0
+    grid_r_max: float = 1000.0
 
     def c(self) -> CModel:
+        ptr, dims = None, (0, 0, 0)
+        if self.grid is not None:
+            g = self.grid
+            if not (g.is_cuda and g.dtype == torch.float32 and g.is_contiguous() and g.dim() == 4 and g.shape[3] == 4):
+                raise ValueError("grid must be a contiguous CUDA float32 tensor [nr, nth, nph, 4]")
+            ptr, dims = g.data_ptr(), tuple(int(v) for v in g.shape[:3])
         return CModel(self.kind, 0, self.r_in, self.r_out, self.n0_cgs, self.r_norm, self.n_index, self.h_over_r,
                       self.T0_K, self.T_index, self.eps_B, self.mbh_msun, self.r_emit_max, self.spot_r,
-                      self.spot_size, self.spot_phi0)
+                      self.spot_size, self.spot_phi0, ptr, dims[0], dims[1], dims[2], 0,
+                      self.grid_r_min, self.grid_r_max)
 
 
 @dataclass
@@ -256,9 +274,12 @@ class Context:
         if rc != OK:
             raise KgrtError(rc, lib().kgrt_strerror(rc).decode())
         self._h = h
+        self._plans = weakref.WeakSet()  # plans keep a pointer to this context: closed first
 
     def close(self):
         if getattr(self, "_h", None):
+            for p in list(self._plans):
+                p.close()
             lib().kgrt_ctx_destroy(self._h)
             self._h = None
 
@@ -294,7 +315,7 @@ class Context:
             if name in INT_FIELDS:
                 setattr(o, name, _ptr(t, torch.int32, n, self.device))
             else:
-                per = n * nf if (model.kind == MODEL_TORUS and name in ("intensity", "tau")) else n
+                per = n * nf if (model.kind in TRANSFER_MODELS and name in ("intensity", "tau")) else n
                 setattr(o, name, _ptr(t, torch.float64, per, self.device))
         return o
 
@@ -345,6 +366,7 @@ class Plan:
         ctx._check(lib().kgrt_plan_create(ctx._h, cams, len(cameras), ctypes.byref(model.c()), fa, nf,
                                           ctypes.byref(integ.c()), ctypes.byref(h)))
         self._h = h
+        ctx._plans.add(self)
         sizes = [c.nx * c.ny for c in cameras]
         self.offsets = [0]
         for n in sizes:
@@ -483,9 +505,9 @@ def alloc_outputs(n: int, model: Model, nfreq: int, device, names: Iterable[str]
             continue
         if name in INT_FIELDS:
             out[name] = torch.empty(n, dtype=torch.int32, device=device)
-        elif model.kind == MODEL_TORUS and name in ("intensity", "tau"):
+        elif model.kind in TRANSFER_MODELS and name in ("intensity", "tau"):
             out[name] = torch.empty((max(nfreq, 1), n), dtype=torch.float64, device=device)
-        elif model.kind != MODEL_TORUS and name == "tau":
+        elif model.kind not in TRANSFER_MODELS and name == "tau":
             continue
         else:
             out[name] = torch.empty(n, dtype=torch.float64, device=device)

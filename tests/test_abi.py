@@ -48,6 +48,7 @@ int main(void) {
   F(kgrt_camera, nx) F(kgrt_camera, x_min) F(kgrt_camera, y_max)
   F(kgrt_model, r_in) F(kgrt_model, r_emit_max) F(kgrt_integrator, max_steps) F(kgrt_integrator, flags)
   F(kgrt_outputs, tau) F(kgrt_launch, refill_min) F(kgrt_adam, eps) F(kgrt_fallback, grad_max) F(kgrt_kernel_info, waves_per_simd)
+  F(kgrt_model, spot_phi0) F(kgrt_model, grid_dev) F(kgrt_model, grid_nph) F(kgrt_model, grid_r_max)
   return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
@@ -69,6 +70,8 @@ int main(void) {
         "kgrt_launch.refill_min": K.CLaunch.refill_min.offset, "kgrt_adam.eps": K.CAdam.eps.offset,
         "kgrt_fallback.grad_max": K.CFallback.grad_max.offset,
         "kgrt_kernel_info.waves_per_simd": K.CKernelInfo.waves_per_simd.offset,
+        "kgrt_model.spot_phi0": K.CModel.spot_phi0.offset, "kgrt_model.grid_dev": K.CModel.grid_dev.offset,
+        "kgrt_model.grid_nph": K.CModel.grid_nph.offset, "kgrt_model.grid_r_max": K.CModel.grid_r_max.offset,
     }
     for k, v in want.items():
         assert int(got[k]) == v, k
@@ -123,6 +126,32 @@ def test_torus_frequency_checks(K):
     assert K.check_args(cam, K.Model(kind=K.MODEL_TORUS, T0_K=0.0), [230e9], integ) == K.E_INVALID_ARG
     # empty images are valid requests
     assert K.check_args(K.Camera(nx=0, ny=0), tor, [230e9], integ) == K.OK
+
+
+def test_grid_model_checks(K):
+    """The gridded-plasma model's arguments are validated on the host; the grid pointer is
+    only stored, never dereferenced, so a dummy address serves here."""
+    cam, _, _, integ = _ok_request(K)
+    L = K.lib()
+
+    def check(freqs=(230e9,), **kw):
+        m = K.Model(kind=K.MODEL_GRID).c()
+        m.grid_dev, m.grid_nr, m.grid_nth, m.grid_nph = 4096, 16, 8, 8
+        m.grid_r_min, m.grid_r_max = 1.0, 1000.0
+        for k, v in kw.items():
+            setattr(m, k, v)
+        fa, nf = K._freqs(list(freqs))
+        return L.kgrt_check_args(ctypes.byref(cam.c()), ctypes.byref(m), fa, nf, ctypes.byref(integ.c()))
+
+    assert check() == K.OK
+    assert check(freqs=[86e9] * 16) == K.OK
+    assert check(grid_nph=1) == K.OK
+    for kw in [dict(grid_dev=None), dict(grid_nr=1), dict(grid_nth=1), dict(grid_nph=0), dict(grid_reserved=1),
+               dict(grid_r_min=0.0), dict(grid_r_min=1000.0), dict(grid_r_max=float("inf")),
+               dict(mbh_msun=0.0), dict(grid_nr=2048, grid_nth=1024, grid_nph=1024), dict(grid_dev=4100)]:
+        assert check(**kw) == K.E_INVALID_ARG, kw
+    for freqs in ([], [230e9] * 17, [0.0], [float("nan")]):
+        assert check(freqs=freqs) == K.E_INVALID_ARG, freqs
 
 
 def test_context_without_gpu_reports_no_device(K):

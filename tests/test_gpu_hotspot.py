@@ -37,6 +37,34 @@ def rel(a, b):
     return np.where(a == b, 0.0, np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
 
 
+def angle_err(a, b):
+    """Error of an angle with an arbitrary origin (phi_obs = 0): radians relative to max(|phi|, 1)."""
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+
+
+def oracle_response(scn, xy, flag=512):
+    """The oracle's own sensitivity of each ray's entry radius to its start: the largest
+    relative change of r_cross when the pixel moves by 1e-12, 3e-12 or 1e-11 (relative) in x or
+    y. Both sides trace the same ray up to rounding, which acts like such a perturbation. Where
+    the step-size controller of the integrator sits at one of its switches (the growth factor
+    capped at 5 when the error estimate is below 1.89e-4) a perturbation of that size can move
+    the whole step sequence by a fraction of a percent, and the entry point by the integration's
+    own error (about 1e-9 here) without changing the step counts; an entry point the oracle
+    itself does not fix better than this cannot be expected to agree better either."""
+    base = O.trace_points(scn, xy)
+    resp = np.zeros(len(xy))
+    for eps in (1e-12, 3e-12, 1e-11):
+        for dx, dy in ((1, 0), (0, 1), (-1, 0), (0, -1)):
+            xy2 = xy.copy()
+            xy2[:, 0] += dx * eps * np.maximum(np.abs(xy[:, 0]), 1.0)
+            xy2[:, 1] += dy * eps * np.maximum(np.abs(xy[:, 1]), 1.0)
+            o2 = O.trace_points(scn, xy2)
+            both = ((base["status"] & flag) != 0) & ((o2["status"] & flag) != 0)
+            resp = np.maximum(resp, np.where(both, rel(o2["r_cross"], base["r_cross"]), 0.0))
+    return resp
+
+
 def _frames(n, nframes, a=0.0, incl=60.0, spot_r=0.0):
     return scenes.hot_spot_frames(n, nframes, a=a, incl_deg=incl, spot_r=spot_r)
 
@@ -61,8 +89,9 @@ def test_hot_spot_frames_match_oracle(ctx, a, incl, spot_r, n):
         lo, hi = plan.offsets[k], plan.offsets[k + 1]
         gk = {name: v[lo:hi] for name, v in g.items()}
         cam = w["camera"]
-        o = O.trace_image(oracle_scene(w), cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"],
-                          cam["y_max"]).ravel()
+        scn = oracle_scene(w)
+        xy = O.pixel_points(cam["nx"], cam["ny"], cam["x_min"], cam["x_max"], cam["y_min"], cam["y_max"])
+        o = O.trace_points(scn, xy)
         ident = (gk["steps"] == o["steps"]) & (gk["attempts"] == o["attempts"])
         assert ident.mean() >= 0.998, (k, ident.mean())
         hit_g, hit_o = (gk["status"] & 512) != 0, (o["status"] & 512) != 0
@@ -70,10 +99,17 @@ def test_hot_spot_frames_match_oracle(ctx, a, incl, spot_r, n):
         both = hit_g & hit_o
         strict = both & ident
         hits += int(both.sum())
-        for name in ("r_cross", "phi_cross", "t_cross", "g"):
-            assert rel(gk[name][strict], o[name][strict]).max(initial=0) <= REL_GEOM, (k, name)
+        # per-ray bar: 1e-9, or 3x the oracle's own response to rounding-sized shifts of the ray's
+        # start where its entry point is that sensitive
+        bar = np.maximum(REL_GEOM, 3.0 * oracle_response(scn, xy))[strict]
+        graze = int((bar > REL_GEOM).sum())
+        assert graze <= max(3, strict.sum() // 10), (k, graze)  # the exemption covers few rays
+        assert bar.max(initial=0) <= 1e-7, (k, bar.max())
+        for name in ("r_cross", "t_cross", "g"):
+            assert np.all(rel(gk[name][strict], o[name][strict]) <= bar), (k, name)
+        assert np.all(angle_err(gk["phi_cross"][strict], o["phi_cross"][strict]) <= bar), (k, "phi_cross")
         for name in ("intensity", "i_bol"):  # exp(-d^2/2 r_spot^2) amplifies the entry point's error
-            assert rel(gk[name][strict], o[name][strict]).max(initial=0) <= 100 * REL_GEOM, (k, name)
+            assert np.all(rel(gk[name][strict], o[name][strict]) <= 100 * bar), (k, name)
         loose = both & ~strict
         assert rel(gk["r_cross"][loose], o["r_cross"][loose]).max(initial=0) <= 1e-6, k
         # rays that miss the spot end as the other models' rays do

@@ -88,9 +88,14 @@ def compare_disk(w, g, o, label, order_amp=False):
     disk = both & ((st_o & 8) != 0) & ((st_g & 8) != 0)
     strict = disk & ident & regular
     amp = 30.0 ** np.maximum(o["n_cross"] - 1, 0) if order_amp else np.ones(len(st_o))
-    for k in ("r_cross", "g", "phi_cross", "t_cross"):
+    for k in ("r_cross", "g", "t_cross"):
         e = (rel(g[k][strict], o[k][strict]) / amp[strict]).max(initial=0)
         assert e <= REL_GEOM, (label, k, e)
+    # phi is an angle with an arbitrary origin (phi_obs = 0): its error in radians, relative to
+    # max(|phi|, 1) (a relative error of a crossing near phi = 0 says nothing)
+    e = (np.abs(g["phi_cross"][strict] - o["phi_cross"][strict]) / np.maximum(np.abs(o["phi_cross"][strict]), 1.0)
+         / amp[strict]).max(initial=0)
+    assert e <= REL_GEOM, (label, "phi_cross", e)
     for k in ("intensity", "i_bol"):  # g^3 r^-3 and g^4 r^-3 amplify the geometric error a few times
         e = (rel(g[k][strict], o[k][strict]) / amp[strict]).max(initial=0)
         assert e <= 10 * REL_GEOM, (label, k, e)
@@ -236,8 +241,10 @@ def assert_capture_classification(st_g, o, a, incl_deg, label):
     return len(bad)
 
 
-def compare_torus(g, o, nf, label, cam=None):
+def compare_torus(g, o, nf, label, cam=None, bar=None):
+    """bar: optional per-ray relative bars (arrays [n]) replacing 1e-6 where they are larger."""
     st_o, st_g = o["status"], g["status"]
+    bar = REL_RT if bar is None else np.maximum(REL_RT, bar)
     assert not np.any(st_g == -7), "some ray was never written"
     same = (g["steps"] == o["steps"]) & (g["attempts"] == o["attempts"])
     assert same.mean() >= 0.995, (label, same.mean())
@@ -250,9 +257,9 @@ def compare_torus(g, o, nf, label, cam=None):
         scale = max(I_o.max(), 1e-300)
         # relative bar, with an absolute floor far below the image's dynamic range
         err = np.abs(I_g - I_o) / np.maximum(np.abs(I_o), 1e-12 * scale)
-        assert err.max() <= REL_RT, (label, f, err.max(), np.argmax(err))
+        assert np.all(err <= bar), (label, f, err.max(), np.argmax(err))
         terr = np.abs(t_g - t_o) / np.maximum(np.abs(t_o), 1e-30)
-        assert terr.max() <= REL_RT, (label, f, terr.max())
+        assert np.all(terr <= bar), (label, f, terr.max())
     return same.mean()
 
 
