@@ -213,6 +213,24 @@ int kgrt_check_args(const kgrt_camera* cam, const kgrt_model* model, const doubl
 int kgrt_trace(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz,
                int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): kgrt_trace with the
+ * same kernels and results, but its scratch (the work-queue counter and the
+ * 88-byte start record of each ray) lives in a static device array of the
+ * library instead of the context's workspace, so the call allocates nothing.
+ * The array holds KGRT_NOALLOC_MAX_RAYS rays (about 23 MB, held on each device
+ * the library runs on until the process ends); an image with more rays
+ * (nx * ny > KGRT_NOALLOC_MAX_RAYS) is rejected with KGRT_E_INVALID_ARG.
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (different streams, threads or contexts) race and give
+ * undefined results; calls ordered on one stream are safe (the counter is
+ * cleared by a kernel at the start of each call). Returns KGRT_E_HIP if the
+ * array's device address could not be obtained when the context was created.
+ * Arguments, outputs and other errors as kgrt_trace. */
+#define KGRT_NOALLOC_MAX_RAYS 262144
+int kgrt_trace_noalloc(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz,
+                       int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out, void* stream);
+
 /* Traces a list of independent rays, each with its own spin, inclination and
  * image-plane point: rays_dev is a device array [n][4] of (a, incl_deg, x, y);
  * r_obs and phi_obs are shared. n >= 0 (0 is a no-op). Outputs have n entries. */

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -658,9 +659,22 @@ trace_kernel(const KParams P, int64_t base, int64_t count, const double* __restr
 
 using namespace kgrt;
 
+// Scratch of the allocation-free trace (kgrt_trace_noalloc): the work-queue
+// counter in the first 256 bytes, then the ray-start records of at most
+// KGRT_NOALLOC_MAX_RAYS rays, [kRecFields][KGRT_NOALLOC_MAX_RAYS]. Every device
+// the library is loaded on holds its own copy until the process ends (23 MB).
+// Host code never uses the array's name as an address: its device address is
+// taken once per device with hipGetSymbolAddress (noalloc_scratch below).
+namespace kgrt {
+constexpr int64_t kNoAllocLead = 32;  // doubles before the records (the counter's 256 bytes)
+static_assert(KGRT_NOALLOC_MAX_RAYS % 64 == 0, "record planes stay 512-byte aligned");
+__device__ __align__(256) double scratch[kNoAllocLead + kRecFields * (int64_t)KGRT_NOALLOC_MAX_RAYS];
+}  // namespace kgrt
+
 struct kgrt_ctx {
     int device = 0;
     int num_cus = 0;
+    double* scratch = nullptr;  // this device's copy of kgrt::scratch (device address), or NULL
     unsigned long long* counter = nullptr;
     double* rec = nullptr;  // ray start records of one chunk, [kRecFields][rec_cap]
     int64_t rec_cap = 0;
@@ -934,6 +948,24 @@ int kernel_info(int block, kgrt_kernel_info* out) {
     return KGRT_OK;
 }
 
+// The device address of this device's copy of the no-alloc scratch, looked up
+// once per device (the caller has made `device` current). NULL if the lookup
+// failed; the allocation-free entry point then reports the error.
+double* noalloc_scratch(int device) {
+    static std::mutex mu;
+    static double* addr[256] = {};
+    static bool tried[256] = {};
+    if (device < 0 || device >= 256) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tried[device]) {
+        tried[device] = true;
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(kgrt::scratch)) == hipSuccess) addr[device] = (double*)p;
+        else (void)hipGetLastError();  // clear the failed lookup's error
+    }
+    return addr[device];
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -1014,6 +1046,7 @@ int kgrt_ctx_create(int device, kgrt_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return KGRT_E_HIP; }
     ctx->num_cus = prop.multiProcessorCount;
+    ctx->scratch = noalloc_scratch(device);
     if (hipMalloc(&ctx->counter, sizeof(unsigned long long)) != hipSuccess) { delete ctx; return KGRT_E_NOMEM; }
     *out = ctx;
     return KGRT_OK;
@@ -1066,6 +1099,37 @@ int kgrt_trace(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, c
     P.nrays = n;
     fill_common(P, model, freqs_hz, nfreq, integ, out, ctx);
     return dispatch(ctx, P, (hipStream_t)stream);
+}
+
+int kgrt_trace_noalloc(kgrt_ctx* ctx, const kgrt_camera* cam, const kgrt_model* model, const double* freqs_hz,
+                       int32_t nfreq, const kgrt_integrator* integ, const kgrt_outputs* out, void* stream) {
+    if (!ctx) return KGRT_E_INVALID_ARG;
+    if (!cam) return fail(ctx, KGRT_E_INVALID_ARG, "camera is NULL");
+    if (!out) return fail(ctx, KGRT_E_INVALID_ARG, "outputs is NULL");
+    std::string msg;
+    int rc = check(msg, cam, model, freqs_hz, nfreq, integ);
+    if (rc != KGRT_OK) return fail(ctx, rc, msg);
+    const int64_t n = (int64_t)cam->nx * (int64_t)cam->ny;
+    if (n > KGRT_NOALLOC_MAX_RAYS)
+        return fail(ctx, KGRT_E_INVALID_ARG, "kgrt_trace_noalloc: the image has " + std::to_string(n) +
+                                                 " rays, more than the scratch holds (KGRT_NOALLOC_MAX_RAYS = " +
+                                                 std::to_string((long long)KGRT_NOALLOC_MAX_RAYS) + ")");
+    if (!ctx->scratch) return fail(ctx, KGRT_E_HIP, "kgrt_trace_noalloc: no device address for the scratch array");
+    if (n == 0) return KGRT_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, KGRT_E_HIP, "hipSetDevice failed");
+    KParams P{};
+    P.image0 = make_image(cam, model, integ->horizon_delta, 0);
+    P.images = nullptr;
+    P.nimg = 1;
+    P.list_mode = 0;
+    P.nrays = n;
+    fill_common(P, model, freqs_hz, nfreq, integ, out, ctx);
+    // the same kernels as kgrt_trace, on the static scratch: the counter is cleared by a
+    // kernel and the start records are written before they are read, on `stream`
+    const LaunchEnv env{ctx->scratch + kNoAllocLead, KGRT_NOALLOC_MAX_RAYS, (unsigned long long*)ctx->scratch,
+                        ctx->launch, ctx->num_cus, -1};
+    return dispatch_env(ctx, env, P, (hipStream_t)stream);
 }
 
 int kgrt_trace_rays_dev(kgrt_ctx* ctx, const double* rays_dev, const int64_t* n_dev, int64_t n_max, double r_obs,

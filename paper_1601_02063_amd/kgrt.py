@@ -24,6 +24,7 @@ MAXSTEPS, UNDERFLOW, NONFINITE, FALLBACK, REFINE_UNCONVERGED, SPOT_HIT = 16, 32,
 MODEL_GEODESIC, MODEL_THIN_DISK, MODEL_TORUS, MODEL_DISK_IMAGES, MODEL_HOT_SPOT, MODEL_GRID = 0, 1, 2, 3, 4, 5
 # models whose outputs carry the transfer: intensity and tau are [nfreq][n]
 TRANSFER_MODELS = (MODEL_TORUS, MODEL_GRID)
+NOALLOC_MAX_RAYS = 262144  # KGRT_NOALLOC_MAX_RAYS
 STOP_AT_CROSSING = 1
 
 
@@ -187,6 +188,8 @@ def lib() -> ctypes.CDLL:
         L.kgrt_check_args.restype = ctypes.c_int
         L.kgrt_trace.argtypes = [vp, P(CCamera), P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
         L.kgrt_trace.restype = ctypes.c_int
+        L.kgrt_trace_noalloc.argtypes = [vp, P(CCamera), P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
+        L.kgrt_trace_noalloc.restype = ctypes.c_int
         L.kgrt_trace_rays.argtypes = [vp, vp, i64, d, d, P(CModel), P(d), i32, P(CIntegrator), P(COutputs), vp]
         L.kgrt_trace_rays.restype = ctypes.c_int
         L.kgrt_plan_create.argtypes = [vp, vp, i32, P(CModel), P(d), i32, P(CIntegrator), P(vp)]
@@ -327,6 +330,16 @@ class Context:
         o = self._outputs(outs, n, max(nf, 1), model)
         self._check(lib().kgrt_trace(self._h, ctypes.byref(camera.c()), ctypes.byref(model.c()), fa, nf,
                                      ctypes.byref(integ.c()), ctypes.byref(o), _stream_handle(stream)))
+
+    def trace_noalloc(self, camera: Camera, model: Model, freqs: Sequence[float], integ: Integrator,
+                      outs: Dict[str, torch.Tensor], stream=None):
+        """kgrt_trace_noalloc: as trace, with the library's static scratch (no device allocation;
+        at most NOALLOC_MAX_RAYS rays; calls overlapping on one device race)."""
+        n = camera.nx * camera.ny
+        fa, nf = _freqs(freqs)
+        o = self._outputs(outs, n, max(nf, 1), model)
+        self._check(lib().kgrt_trace_noalloc(self._h, ctypes.byref(camera.c()), ctypes.byref(model.c()), fa, nf,
+                                             ctypes.byref(integ.c()), ctypes.byref(o), _stream_handle(stream)))
 
     def trace_rays(self, rays: torch.Tensor, model: Model, freqs: Sequence[float], integ: Integrator,
                    outs: Dict[str, torch.Tensor], r_obs: float = 1000.0, phi_obs_deg: float = 0.0, stream=None):
