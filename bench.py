@@ -17,6 +17,7 @@ Prints ONE JSON line. Other workloads (--workload):
   infer                   the fused surrogate network alone, 2^24 samples
   render                  64 surrogate+fallback thin-disk images of 2048^2 vs the integrator
   table1                  the paper's Table 1 sweep (projection, N = 2 ... 2048)
+  grid                    the torus camera over a 256x128x128 GRMHD-like plasma snapshot (1024^2, 230 GHz)
 Extra modes:
   --calibrate RAY   trace copies of one ray (no divergence) so a rocprofv3
                     --pmc run can count FP64 VALU instructions per step.
@@ -44,9 +45,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # profiles/trace_kernel_flop_calibration.md (the thin-disk figure, from three disk
 # rays, also serves the projection workload, which runs the same kernel; the
 # batch figure is the eight-frequency torus kernel's, from the torus rays traced
-# at the batch's eight frequencies).
+# at the batch's eight frequencies; the grid figure is the gridded-plasma kernel's,
+# from the torus rays traced through the 256x128x128 snapshot).
 FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "calibrated"),
-                     "projection": (852.0, "calibrated"), "batch": (2173.0, "calibrated")}
+                     "projection": (852.0, "calibrated"), "batch": (2173.0, "calibrated"),
+                     "grid": (1356.0, "calibrated")}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
@@ -87,6 +90,10 @@ CALIBRATION_RAYS = {
     "disk_hit": (0.9, 60.0, 6.0, 3.0),
     "disk_far": (0.9, 60.0, 14.0, 12.0),
     "disk_captured": (0.9, 60.0, 0.5, 0.5),
+    # the gridded plasma (the torus camera over the 256x128x128 snapshot): the torus rays
+    "grid_captured": (0.94, 17.0, 1.5, 2.0),
+    "grid_escaping": (0.94, 17.0, 7.0, -5.0),
+    "grid_far": (0.94, 17.0, 18.0, 15.0),
 }
 
 
@@ -101,6 +108,10 @@ def workload(name: str, n: int | None):
     if name == "projection":
         return scenes.projection_image(n or 1024), f"first-crossing projection, a=0.95, incl=60 deg, " \
             f"{n or 1024}x{n or 1024} rays over +-15 M, rtol 1e-8"
+    if name == "grid":
+        return scenes.grid_image(n or 1024), "thermal-synchrotron plasma sampled from a GRMHD-like snapshot " \
+            "(256x128x128 (ln r, theta, phi) nodes over 1-1000 M, seed 1610), a=0.94, incl=17 deg, " \
+            f"{n or 1024}x{n or 1024} rays over +-20 M, 230 GHz, rtol 1e-8, step cap 0.02 r"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -128,7 +139,7 @@ def cpu_baseline(w, nsample: int, seed: int = 2024):
     sc = O.Scene(a=cam["a"], incl_deg=cam["incl_deg"], r_obs=cam["r_obs"], rtol=w["integ"]["rtol"],
                  hmax_frac=w["integ"]["hmax_frac"], horizon_delta=w["integ"]["horizon_delta"],
                  max_steps=w["integ"]["max_steps"], model=w["model"]["kind"],
-                 stop_at_crossing=bool(w["integ"]["flags"] & 1), freqs_hz=list(w["freqs"]),
+                 stop_at_crossing=bool(w["integ"]["flags"] & 1), freqs_hz=list(w["freqs"]), grid=w.get("grid"),
                  **{k: v for k, v in w["model"].items() if k != "kind"})
     threads = O.default_threads()
     t0 = time.perf_counter()
@@ -154,7 +165,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus",
-                    choices=["torus", "thin_disk", "projection", "batch", "train", "infer", "render", "table1"])
+                    choices=["torus", "thin_disk", "projection", "batch", "train", "infer", "render", "table1",
+                             "grid"])
     ap.add_argument("--train-rays", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--ckpt", default=None,
@@ -228,6 +240,8 @@ def main():
 
     w, desc = workload(args.workload, args.n)
     cam, mod, freqs = K.Camera(**w["camera"]), K.Model(**w["model"]), list(w["freqs"])
+    if "grid" in w:
+        mod.grid = torch.from_numpy(w["grid"]).to(dev)
     integ = K.Integrator(**w["integ"])
     n = cam.nx * cam.ny
     out = K.alloc_outputs(n, mod, len(freqs), dev, names=("status", "steps", "attempts", "intensity", "tau",
@@ -253,8 +267,8 @@ def main():
     attempts = int(out["attempts"].to(torch.int64).sum())
     st = out["status"]
     ns_per_step = ms_mean * 1e6 / steps
-    fpa, basis = FLOPS_PER_ATTEMPT[args.workload]
-    achieved = fpa * attempts / (ms_mean * 1e-3) / 1e12
+    fpa, basis = FLOPS_PER_ATTEMPT.get(args.workload, (None, None))
+    achieved = fpa * attempts / (ms_mean * 1e-3) / 1e12 if fpa else None
     tr = TRAFFIC.get(args.workload)
     traffic = tr["bytes"] if (tr and cam.nx == 1024 and cam.ny == 1024 and tr["source_md5"] == kernel_source_md5()) \
         else None
@@ -289,11 +303,20 @@ def main():
         "ns_per_rhs_eval": round(ms_mean * 1e6 / (6 * attempts), 6),
         "captured_frac": round(float(((st & 1) != 0).float().mean()), 5),
         "kernel": dict(kinfo, lane_utilisation=lane_util),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4) if fpa else None,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5) if fpa else None, "traffic": traffic,
                      "flops_per_attempt": fpa, "flops_basis": basis,
-                     "kernel": "trace_kernel<torus,1>" if args.workload == "torus" else "trace_kernel<disk,1>"},
+                     "kernel": {"torus": "trace_kernel<torus,1>", "grid": "trace_kernel<grid,1>"}.get(
+                         args.workload, "trace_kernel<disk,1>")},
     }
+    if args.workload == "grid":
+        # one trilinear sample (8 nodes x 16 B) per accepted point, the start point included,
+        # mostly served by the caches (the snapshot is 64 MiB)
+        gb = 128 * (steps + n)
+        line["grid_samples"] = {"bytes": gb, "node_bytes_per_sample": 128,
+                                "achieved_GBs": round(gb / (ms_mean * 1e-3) / 1e9, 1),
+                                "snapshot_bytes": int(w["grid"].nbytes)}
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     if args.workload == "torus" and args.surrogate_images > 0:
@@ -601,9 +624,13 @@ def calibrate(ctx, which: str, dev, nfreq: int = 1):
     from paper_1601_02063_amd import scenes
     if which.startswith("disk_"):
         w = scenes.thin_disk_image(16)
+    elif which.startswith("grid_"):
+        w = scenes.grid_image(16, freqs=(230e9,) if nfreq == 1 else scenes.batch_frequencies())
     else:
         w = scenes.torus_image(16, freqs=(230e9,) if nfreq == 1 else scenes.batch_frequencies())
     mod, freqs, integ = K.Model(**w["model"]), list(w["freqs"]), K.Integrator(**w["integ"])
+    if "grid" in w:
+        mod.grid = torch.from_numpy(w["grid"]).to(dev)
     nrays = 256 * 1024
     ray = torch.tensor(CALIBRATION_RAYS[which], dtype=torch.float64, device=dev)
     rays = ray.repeat(nrays, 1).contiguous()
