@@ -41,10 +41,6 @@ constexpr int64_t kW3 = kB2 + kH, kB3 = kW3 + kH * kH;
 constexpr int64_t kW4 = kB3 + kH, kB4 = kW4 + kH * kH;
 constexpr int64_t kW5 = kB4 + kH, kB5 = kW5 + kOut * kH;
 constexpr int64_t kNumParams = kB5 + kOut;  // 199941
-// the packed BF16 weights of the training kernels, Wf: W2..W4 [3][out][in], then
-// W5 split into hi and lo parts [2][16][256] (outputs 5..15 zero)
-constexpr int64_t kW5SplitU = 3 * kH * kH, kW5Rows = 16;
-constexpr int64_t kWfSize = kW5SplitU + 2 * kW5Rows * kH;
 // Inference folds the base-2 exponential's scale c = log2(e) into the weights:
 // with W1, b1..b4 scaled by -c and W5 by -1/c, every hidden layer computes
 // ht = -c SiLU(z) directly from zt = -c z as zt / (1 + 2^zt) (W2..W4 are
@@ -60,22 +56,6 @@ constexpr float kWCap = 1.0f, kWLogR = 10.0f, kWG = 10.0f, kWPhi = 1.0f;
 __device__ __forceinline__ float sigmoidf_(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
-
-// Tiles of the training kernels: 64 samples per block, activations in one LDS
-// buffer (64 x 256 BF16, rows padded by 8 elements against bank conflicts); a
-// wave computes 16 RI rows x 16 UJ units of a layer (RI x UJ MFMA tiles, so
-// each weight fragment serves RI row tiles); the block has (4 / RI) x
-// (16 / UJ) waves. Both passes fit two blocks per CU (four waves per SIMD), so
-// one block's MFMA work overlaps the other's element-wise phases and barriers.
-constexpr int kTileRows = 64, kLdsStride = kH + 8;
-#ifndef KGRT_MLP_RI
-#define KGRT_MLP_RI 4
-#endif
-#ifndef KGRT_MLP_UJ
-#define KGRT_MLP_UJ 2
-#endif
-constexpr int kTrainRI = KGRT_MLP_RI, kTrainUJ = KGRT_MLP_UJ;
-constexpr int kTrainThreads = 64 * (4 / kTrainRI) * (16 / kTrainUJ);
 
 // ------------------------------------------- row-parallel fused inference
 // Each wave owns 16 RB rows and computes every unit of every layer for them,
@@ -255,364 +235,509 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
     }
 }
 
-// ------------------------------------------------------- fused training
-// One training step in four kernels over 64-sample tiles of the batch
-// (gathered through idx):
-//  train_fwd: the network in unscaled form on 64-row tiles whose activations
-//    pass between layers through LDS (the tile shape above); stores each
-//    layer's SiLU'(z) and activation h (layers 1..4) feature-major [256][ld]
-//    in BF16, dL/do [B][5] (FP32) and the loss;
-//  train_bwd: dz4 = (dL/do W5) SiLU'(z4), then dh_{l-1} = dz_l W_l on MFMA
-//    (with W_l^T) and dz_{l-1} = dh_{l-1} SiLU'(z_{l-1}) in a column pass that
-//    also stores dz feature-major and sums the gradients of b1..b4, W1, W5, b5
-//    (per block, one atomic per value at the end);
-//  train_dw: dW_l = sum_b dz_l[b] h_{l-1}[b]^T (l = 2..4) on MFMA as partial
-//    sums over row chunks, added up by train_dw_reduce.
-constexpr int kDwChunks = 64;
-
 // Per-sample arrays of the training step are stored tile-major,
 // [B/64][256 units][64 rows] BF16: a tile's values for one unit are 128
 // contiguous bytes, and the whole tile is one 32 KB block.
 __device__ __forceinline__ int64_t tm_index(int u, int64_t b) { return (b >> 6) * (kH * 64) + u * 64 + (b & 63); }
 
+// The weight-gradient products dL/dW_l = sum_b dz_l[b] h_{l-1}[b]^T (l = 2..4) over
+// row chunks (train_dw), added up in chunk order by train_dw_reduce.
+constexpr int kDwChunks = 64;
 struct TrainBufs {
-    __bf16* sT[4];   // SiLU'(z) of layers 1..4
     __bf16* hT[4];   // h of layers 1..4
-    __bf16* dzT[4];  // dL/dz of layers 1..4 (layers 2..4 used)
+    __bf16* dzT[4];  // dL/dz of layers 1..4
+};
+
+// ------------------------------------------ row-parallel fused training
+// Forward and backward of one 16-row tile per wave in one kernel, in the form
+// of the inference kernel: a layer's activations stay in the wave's
+// registers (the MFMA result of a 16-unit block, lane (r, g) holding units
+// 4g..4g+3 of row r, is a quarter of the next product's B operand once the
+// weights are stored in permuted fragment order). A hidden layer's weight
+// fragments reach LDS in two halves of 64 KB by direct global-to-LDS loads,
+// double-buffered: the next half loads while the waves multiply with the
+// other, and a barrier per half layer is the only one between the waves. Per tile:
+//   forward: z1 = W1 x + b1 (FP32 operands as BF16 hi + lo parts), then
+//     z_l = W_l h_{l-1} + b_l (l = 2..4, BF16 x BF16, FP32 accumulation);
+//     h_l = SiLU(z_l) stays in registers, SiLU'(z_l) (BF16) too for layer 4
+//     and, for layers 2 and 3, goes to global memory in the accumulator
+//     layout (8 bytes per lane and unit block, read back by the same lane;
+//     the registers would not hold it); the head o = W5 h4 + b5 (W5 as
+//     hi + lo), the loss and dL/do;
+//   backward: dh4 = dL/do W5 (both as hi + lo), dz_l = dh_l SiLU'(z_l),
+//     dh_{l-1} = dz_l W_l on MFMA with W_l^T fragments (l = 4..2), SiLU'(z1)
+//     recomputed from x.
+// h1..h4 and dz1..dz4 go to global memory tile-major (transposed through a
+// per-wave LDS scratch, 4 rows of one unit per lane), dL/do row-major: every
+// sum over the batch (the weight and bias gradients) is taken by train_dw and
+// train_small over row chunks, with the chunks added in a fixed order, so a
+// step's gradient does not depend on the order blocks run in.
+//
+// Training fragment array Wt (BF16, 1 KB fragments, unscaled weights):
+//   W1 hi + lo [jb 16][lane][8] (as the inference kernel's input layer);
+//   head W5 hi, lo [s 8][part 2][lane][8]: lane (r, g) element e W5[r][kperm(s, g, e)];
+//   W5^T hi, lo [jb 16][part 2][lane][8]: lane (m, 0) element e < 5 W5[e][16 jb + m];
+//   backward hidden W_l^T [l 3][jb 16][s 8][lane][8]: lane (r, g) element e
+//     W_{l+2}[kperm(s, g, e)][16 jb + r].
+// The forward hidden fragments are the inference kernel's (Wr, unscaled).
+constexpr int64_t kWtW1 = 0, kWtW5 = kWtW1 + 16 * kWrFrag, kWtW5T = kWtW5 + 16 * kWrFrag;
+constexpr int64_t kWtBwd = kWtW5T + 32 * kWrFrag, kWtSize = kWtBwd + 3 * 16 * 8 * kWrFrag;
+constexpr int kTrWaves = 8, kTrThreads = 64 * kTrWaves, kTrRows = 16 * kTrWaves;
+
+__global__ void __launch_bounds__(256) pack_train(const float* __restrict__ P, __bf16* __restrict__ Wt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kWtSize; i += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(i % 8), lane = (int)((i / 8) % 64), r = lane % 16, g = lane / 16;
+        const int64_t f = i / kWrFrag;
+        float v = 0.0f;
+        if (i < kWtW5) {
+            // k 0..3 W1hi.xhi, 4..7 W1hi.xlo, 8..11 W1lo.xhi: lane group 0 holds W1hi twice, group 1 W1lo
+            const int jb = (int)f;
+            const float w = P[kW1 + (16 * jb + r) * kIn + (e & 3)];
+            const float hi = (float)(__bf16)w;
+            v = (g == 0) ? hi : ((g == 1 && e < 4) ? w - hi : 0.0f);
+        } else if (i < kWtW5T) {
+            const int64_t ff = f - kWtW5 / kWrFrag;
+            const int s = (int)(ff / 2), part = (int)(ff % 2);
+            const float w = (r < kOut) ? P[kW5 + r * kH + kperm(s, g, e)] : 0.0f;
+            const float hi = (float)(__bf16)w;
+            v = part == 0 ? hi : w - hi;
+        } else if (i < kWtBwd) {
+            const int64_t ff = f - kWtW5T / kWrFrag;
+            const int jb = (int)(ff / 2), part = (int)(ff % 2);
+            const float w = (g == 0 && e < kOut) ? P[kW5 + e * kH + 16 * jb + r] : 0.0f;
+            const float hi = (float)(__bf16)w;
+            v = part == 0 ? hi : w - hi;
+        } else {
+            const int64_t ff = f - kWtBwd / kWrFrag;
+            const int l = (int)(ff / 128), jb = (int)((ff / 8) % 16), s = (int)(ff % 8);
+            const float* W = P + (l == 0 ? kW2 : (l == 1 ? kW3 : kW4));
+            v = W[kperm(s, g, e) * kH + 16 * jb + r];
+        }
+        Wt[i] = (__bf16)v;
+    }
+}
+
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+struct TrainRowsArgs {
+    const float* x;
+    const int32_t* idx;
+    const float* t;
+    int64_t n;
+    const float* P;
+    const __bf16* Wr;
+    const __bf16* Wt;
+    __bf16* hT[4];   // h1..h4, tile-major [B/64][256][64]
+    __bf16* dzT[4];  // dL/dz of layers 1..4, tile-major
+    __bf16* spF[2];  // SiLU'(z) of layers 2 and 3 in the accumulator layout [B/16][jb 16][lane 64][4]
     float* dout;     // dL/do [B][5]
     float* loss;
     float inv_n;
 };
 
-template <int RI, int UJ>
-__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
-train_fwd(const float* __restrict__ x, const int32_t* __restrict__ idx, const float* __restrict__ t, int64_t n,
-          const float* __restrict__ P, const __bf16* __restrict__ Wf, const TrainBufs B) {
-    constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
-    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-    __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
-    __shared__ float xs[kTileRows * kIn];
-    __shared__ float os[kTileRows * 8];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / WU, wu = wave % WU;
-    const int lr = lane & 15, lg = lane >> 4;
-    auto split = [](float v, __bf16& hi, __bf16& lo) {
-        hi = (__bf16)v;
-        lo = (__bf16)(v - (float)hi);
-    };
-    const __bf16 z16 = (__bf16)0.0f;
-    bf16x8 w1f[UJ];
-#pragma unroll
-    for (int j = 0; j < UJ; ++j) {
-        const float* w = P + kW1 + (16 * (UJ * wu + j) + lr) * kIn;
-        bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
-        __bf16 hi[kIn], lo[kIn];
-#pragma unroll
-        for (int c = 0; c < kIn; ++c) split(w[c], hi[c], lo[c]);
-#pragma unroll
-        for (int c = 0; c < kIn; ++c) {
-            if (lg == 0) {
-                f[c] = hi[c];
-                f[4 + c] = hi[c];
-            } else if (lg == 1) {
-                f[c] = lo[c];
-            }
-        }
-        w1f[j] = f;
+__global__ void __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+train_rows(const TrainRowsArgs A) {
+    __shared__ bf16x8 wb[2][8 * 8 * 64];                // two half layers of fragments (2 x 64 KB)
+    __shared__ bf16x8 w1l[16 * 64];                     // the input layer's fragments (16 KB)
+    __shared__ __align__(16) float bl[4][kH];           // b1..b4
+    __shared__ __align__(16) __bf16 trs[kTrWaves][16 * 16];  // per-wave transposition scratch
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    auto cat = [](const bf16x4& a, const bf16x4& b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); };
+    auto mfma = [](bf16x8 a, bf16x8 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); };
+    const float* Pp = A.P;
+    for (int i = tid; i < 4 * kH; i += kTrThreads) {
+        const int L = i / kH;
+        bl[L][i % kH] = Pp[(L == 0 ? kB1 : (L == 1 ? kB2 : (L == 2 ? kB3 : kB4))) + i % kH];
     }
-    auto init = [&](f32x4 (&acc)[RI][UJ], int64_t boff) {
+    for (int i = tid; i < 16 * 64; i += kTrThreads) w1l[i] = reinterpret_cast<const bf16x8*>(A.Wt)[kWtW1 / 8 + i];
+    // bias of layer L + 1 for the units lane group g holds in unit block jb
+    auto bias = [&](int L, int jb) { return *reinterpret_cast<const f32x4*>(&bl[L][16 * jb + 4 * g]); };
+    // the eight weight fragments of unit block jb, all read before the products that use them
+    // (jb 0..7 from the first half buffer, 8..15 from the second)
+    auto frags = [&](int jb, bf16x8 (&w)[8]) {
 #pragma unroll
-        for (int j = 0; j < UJ; ++j) {
-            const f32x4 b = *reinterpret_cast<const f32x4*>(P + boff + 16 * (UJ * wu + j) + 4 * lg);
+        for (int s = 0; s < 8; ++s) w[s] = wb[jb >> 3][((jb & 7) * 8 + s) * 64 + lane];
+    };
+    // The six hidden-layer fragment sets a block of rows uses, in order: forward W2..W4
+    // (lam = 0..2), backward W4^T..W2^T (lam = 3..5). Each set goes to LDS in two halves
+    // (unit blocks 0..7 and 8..15, 64 KB each) by direct global-to-LDS loads: one half
+    // loads while the other is in use. issue() starts half h of set lam (each wave moves 8
+    // fragments of 1 KB); half_barrier() waits for the wave's own loads, then for every wave,
+    // so the half just loaded is complete and the other buffer is free.
+    typedef const __attribute__((address_space(1))) bf16x8 GW;
+    auto issue = [&](int lam, int h) {
+        GW* set = (lam < 3) ? (GW*)A.Wr + kWrHid / 8 + lam * (16 * 8 * 64)
+                            : (GW*)A.Wt + kWtBwd / 8 + (5 - lam) * (16 * 8 * 64);
 #pragma unroll
-            for (int i = 0; i < RI; ++i) acc[i][j] = b;
+        for (int i = 0; i < 8; ++i) {
+            const int f = wave + kTrWaves * i;  // fragment of the half
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(set + (h * 64 + f) * 64 + lane),
+                                             (__attribute__((address_space(3))) void*)&wb[h][f * 64], 16, 0, 0);
         }
     };
-    // h = SiLU(z) into the activation buffer; SiLU'(z) and h to global
-    auto store = [&](const f32x4 (&acc)[RI][UJ], int layer, int64_t row0) {
+    auto half_barrier = [&]() {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    };
+    static_assert(kTrWaves == 8, "each wave moves 8 of a half layer's 64 fragments");
+    // lane (r, g) holds X[row r][unit 4g + e] of a 16-unit block; returns, for lane
+    // (u = r, q = g), X[rows 4q .. 4q + 3][unit u] (LDS operations of one wave run in order)
+    __bf16* const tr = trs[wave];
+    auto transpose = [&](const bf16x4& v) {
 #pragma unroll
-        for (int j = 0; j < UJ; ++j) {
-            const int u = 16 * (UJ * wu + j) + 4 * lg;
-#pragma unroll
-            for (int i = 0; i < RI; ++i) {
-                const int r = 16 * (RI * wr + i) + lr;
-                const int64_t b = row0 + r;
-                bf16x4 v;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float z = acc[i][j][e];
-                    const float sg = sigmoidf_(z);
-                    const float h = z * sg;
-                    v[e] = (__bf16)h;
-                    if (b < n) {
-                        B.sT[layer][tm_index(u + e, b)] = (__bf16)(sg * (1.0f + z * (1.0f - sg)));
-                        B.hT[layer][tm_index(u + e, b)] = (__bf16)h;
-                    }
-                }
-                *reinterpret_cast<bf16x4*>(act + r * kLdsStride + u) = v;
-            }
-        }
+        for (int e = 0; e < 4; ++e) tr[(4 * g + e) * 16 + r] = v[e];
+        return *reinterpret_cast<const bf16x4*>(tr + r * 16 + 4 * g);
     };
     float lacc = 0.0f;
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row0 = tile * kTileRows;
-        __syncthreads();
-        for (int i = tid; i < kTileRows * kIn; i += NT) {
-            const int64_t b = row0 + i / kIn;
-            xs[i] = (b < n) ? x[(idx ? (int64_t)idx[b] : b) * kIn + i % kIn] : 0.0f;
+    const int64_t nblk = (A.n + kTrRows - 1) / kTrRows;
+    if (blockIdx.x < nblk) issue(0, 0);
+    __syncthreads();  // b1..b4 and the input layer's fragments staged
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const bool more = blk + gridDim.x < nblk;  // another block of rows follows
+        // fragment and parameter pointers opaque per block of rows, so their loads are not hoisted
+        GW* Wr = (GW*)A.Wr;
+        GW* Wt = (GW*)A.Wt;
+        asm volatile("" : "+s"(Wr), "+s"(Wt), "+s"(Pp));
+        // this wave's 16 rows: n is a multiple of 32, so a tile is all valid or all beyond n
+        const int64_t row0 = __builtin_amdgcn_readfirstlane((int)(blk * kTrRows + 16 * wave));
+        const bool tile_ok = row0 < A.n;
+        const int64_t row = row0 + r;
+        const int64_t src = tile_ok ? (A.idx ? (int64_t)A.idx[row] : row) : 0;
+        f32x4 xv = {0.f, 0.f, 0.f, 0.f};
+        if (tile_ok && g <= 1) xv = *reinterpret_cast<const f32x4*>(A.x + src * kIn);
+        bf16x8 xf;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const __bf16 hi = (__bf16)xv[c];
+            xf[c] = hi;
+            xf[4 + c] = (g == 0) ? (__bf16)(xv[c] - (float)hi) : (__bf16)0.0f;
         }
-        __syncthreads();
-        {
-            f32x4 acc[RI][UJ];
-            init(acc, kB1);
+        // the tile's h_l or dz_l, transposed, to a tile-major array (4 rows per lane)
+        const int64_t tmo = tm_index(r, row0 + 4 * g);
+        auto store_t = [&](const bf16x4& v, __bf16* dst, int jb) {
+            const bf16x4 vt = transpose(v);
+            if (tile_ok) *reinterpret_cast<bf16x4*>(dst + tmo + 16 * 64 * jb) = vt;
+        };
+        // SiLU'(z) of this wave's tile, layers 2 and 3, in the accumulator layout
+        const int64_t spo = ((row0 >> 4) * 16 * 64 + lane) * 4;
+        // ---------------- forward
+        bf16x4 act[16], nxt[16], sp4[16];
 #pragma unroll
-            for (int i = 0; i < RI; ++i) {
-                const float* xr = xs + (16 * (RI * wr + i) + lr) * kIn;
-                bf16x8 f = {z16, z16, z16, z16, z16, z16, z16, z16};
-                __bf16 hi[kIn], lo[kIn];
+        for (int jb = 0; jb < 16; ++jb) {
+            const f32x4 z = mfma(w1l[jb * 64 + lane], xf, bias(0, jb));
 #pragma unroll
-                for (int c = 0; c < kIn; ++c) split(xr[c], hi[c], lo[c]);
-#pragma unroll
-                for (int c = 0; c < kIn; ++c) {
-                    if (lg <= 1) f[c] = hi[c];
-                    if (lg == 0) f[4 + c] = lo[c];
-                }
-#pragma unroll
-                for (int j = 0; j < UJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[j], f, acc[i][j], 0, 0, 0);
-            }
-            store(acc, 0, row0);
+            for (int e = 0; e < 4; ++e) act[jb][e] = (__bf16)(z[e] * sigmoidf_(z[e]));
+            store_t(act[jb], A.hT[0], jb);
         }
-        __syncthreads();
+#pragma unroll 1
         for (int l = 0; l < 3; ++l) {
-            const __bf16* W = Wf + (int64_t)l * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
-            const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
-            f32x4 acc[RI][UJ];
-            init(acc, l == 0 ? kB2 : (l == 1 ? kB3 : kB4));
-#pragma unroll 1
-            for (int s = 0; s < kH / 32; ++s) {
-                const int k = 32 * s + 8 * lg;
-                bf16x8 af[UJ], bfg[RI];
+            asm volatile("" : "+s"(Wr), "+s"(Pp));  // no loads hoisted out of this loop
+            half_barrier();  // first half of set l in; second buffer free
+            issue(l, 1);
+            __bf16* spdst = A.spF[l < 2 ? l : 0] + spo;
 #pragma unroll
-                for (int j = 0; j < UJ; ++j) af[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + k);
-#pragma unroll
-                for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
-#pragma unroll
-                for (int i = 0; i < RI; ++i)
-#pragma unroll
-                    for (int j = 0; j < UJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
-            }
-            __syncthreads();
-            store(acc, l + 1, row0);
-            __syncthreads();
-        }
-        // output head (W5 as hi + lo BF16 parts) into os[row][0..4]
-        for (int rt = wave; rt < kTileRows / 16; rt += NT / 64) {
-            const __bf16* Wh = Wf + kW5SplitU + lr * kH;
-            const __bf16* A = act + (16 * rt + lr) * kLdsStride;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int s = 0; s < kH / 32; ++s) {
-                const int k = 32 * s + 8 * lg;
-                const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + k);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + k), hv, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(Wh + kW5Rows * kH + k), hv,
-                                                              acc, 0, 0, 0);
-            }
-            const int r = 16 * rt + lr;
-            if (lg == 0) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) os[r * 8 + e] = acc[e] + P[kB5 + e];
-            } else if (lg == 1) {
-                os[r * 8 + 4] = acc[0] + P[kB5 + 4];
-            }
-        }
-        __syncthreads();
-        // loss and dL/do, one thread per row
-        if (tid < kTileRows) {
-            const int64_t b = row0 + tid;
-            if (b < n) {
-                const float* o = os + tid * 8;
-                const float* tr = t + (idx ? (int64_t)idx[b] : b) * 6;
-                const float cap = tr[0], m = tr[5];
-                const float sp = (o[0] > 0.0f) ? o[0] + log1pf(__expf(-o[0])) : log1pf(__expf(o[0]));
-                const float e1 = o[1] - tr[1], e2 = o[2] - tr[2], e3 = o[3] - tr[3], e4 = o[4] - tr[4];
-                lacc += kWCap * (sp - cap * o[0]) + kWLogR * e1 * e1 + kWG * e2 * e2 + kWPhi * m * (e3 * e3 + e4 * e4);
-                float* d = B.dout + b * kOut;
-                d[0] = kWCap * (sigmoidf_(o[0]) - cap) * B.inv_n;
-                d[1] = 2.0f * kWLogR * e1 * B.inv_n;
-                d[2] = 2.0f * kWG * e2 * B.inv_n;
-                d[3] = 2.0f * kWPhi * m * e3 * B.inv_n;
-                d[4] = 2.0f * kWPhi * m * e4 * B.inv_n;
-            }
-        }
-    }
-    if (tid < 64) {
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) lacc += __shfl_xor(lacc, d);
-        if (tid == 0) atomicAdd(B.loss, lacc * B.inv_n);
-    }
-}
-
-template <int RI, int UJ>
-__global__ void __launch_bounds__(64 * (4 / RI) * (16 / UJ)) __attribute__((amdgpu_waves_per_eu(4, 4)))
-train_bwd(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t n, const float* __restrict__ P,
-          const __bf16* __restrict__ Wb, const TrainBufs B, float* __restrict__ G) {
-    constexpr int WU = 16 / UJ, NT = 64 * (4 / RI) * WU;
-    constexpr int PH = NT / kH, RPT = kTileRows / PH;  // column pass: threads per unit, rows per thread
-    static_assert(NT % kH == 0 && RPT % 8 == 0, "column pass shape");
-    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-    __shared__ __align__(16) __bf16 act[kTileRows * kLdsStride];
-    __shared__ float xs[kTileRows * kIn];
-    __shared__ float ds[kTileRows * kOut];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / WU, wu = wave % WU;
-    const int lr = lane & 15, lg = lane >> 4;
-    // column pass: lanes take adjacent units (adjacent LDS words; 128-byte rows of
-    // the tile-major arrays), the PH row blocks go to different waves
-    const int cu = tid % kH, ch = tid / kH;
-    float w5[kOut], gw5[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb5[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < kOut; ++j) w5[j] = P[kW5 + j * kH + cu];
-    float gb[4] = {0.f, 0.f, 0.f, 0.f}, gw1[kIn] = {0.f, 0.f, 0.f, 0.f};
-    // dz of layer L (1..4) for this thread's unit and rows: dh from the head
-    // (L = 4) or from the activation buffer, times SiLU'(z_L) saved by the
-    // forward kernel; stored to the buffer (for the next product) and, for
-    // L >= 2, feature-major to global
-    auto column = [&](int L, int64_t row0) {
-        const int rbeg = ch * RPT;
-        // the thread's SiLU'(z) (and, for L = 4, h) loads are all issued before
-        // the first is used; the rows are then processed in a loop that is not
-        // unrolled (unrolled, its LDS reads are hoisted and spill)
-        bf16x8 svq[RPT / 8], hvq[RPT / 8];
-#pragma unroll
-        for (int q = 0; q < RPT / 8; ++q) {
-            const int64_t b8 = row0 + rbeg + 8 * q;
-            svq[q] = bf16x8{};
-            hvq[q] = bf16x8{};
-            if (b8 < n) {
-                svq[q] = *reinterpret_cast<const bf16x8*>(B.sT[L - 1] + tm_index(cu, b8));
-                if (L == 4) hvq[q] = *reinterpret_cast<const bf16x8*>(B.hT[3] + tm_index(cu, b8));
-            }
-        }
-#pragma unroll 1
-        for (int q = 0; q < RPT / 8; ++q) {
-            const int r8 = rbeg + 8 * q;
-            const int64_t b8 = row0 + r8;
-            if (b8 >= n) break;  // n is a multiple of 32: groups of 8 rows are whole
-            const bf16x8 sv = svq[0], hv = hvq[0];
-#pragma unroll
-            for (int k = 0; k + 1 < RPT / 8; ++k) {
-                svq[k] = svq[k + 1];
-                hvq[k] = hvq[k + 1];
-            }
-            bf16x8 out;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int r = r8 + e;
-                float dh;
-                if (L == 4) {
-                    dh = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < kOut; ++j) dh += ds[r * kOut + j] * w5[j];
-                } else {
-                    dh = (float)act[r * kLdsStride + cu];
+            for (int jb = 0; jb < 16; ++jb) {
+                if (jb == 8) {
+                    half_barrier();  // second half in; first buffer free
+                    issue(l + 1, 0);
                 }
-                const float dz = dh * (float)sv[e];
-                if (L == 4) {
-                    const float h = (float)hv[e];
+                bf16x8 w[8];
+                frags(jb, w);
+                f32x4 z = bias(l + 1, jb);
 #pragma unroll
-                    for (int j = 0; j < kOut; ++j) {
-                        gw5[j] += ds[r * kOut + j] * h;
-                        gb5[j] += ds[r * kOut + j];
+                for (int s = 0; s < 8; ++s) z = mfma(w[s], cat(act[2 * s], act[2 * s + 1]), z);
+                bf16x4 spv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float sg = sigmoidf_(z[e]);
+                    nxt[jb][e] = (__bf16)(z[e] * sg);
+                    spv[e] = (__bf16)(sg * (1.0f + z[e] * (1.0f - sg)));
+                }
+                if (l == 2) sp4[jb] = spv;
+                else if (tile_ok) *reinterpret_cast<bf16x4*>(spdst + jb * 64 * 4) = spv;
+                store_t(nxt[jb], A.hT[l + 1], jb);
+            }
+#pragma unroll
+            for (int jb = 0; jb < 16; ++jb) act[jb] = nxt[jb];
+        }
+        asm volatile("" : "+s"(Wt), "+s"(Pp));
+        // ---------------- head, loss, dL/do (lane (r, 0): outputs 0..3, lane (r, 1): output 4)
+        f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const bf16x8 hv = cat(act[2 * s], act[2 * s + 1]);
+            o = mfma(Wt[kWtW5 / 8 + (2 * s) * 64 + lane], hv, o);
+            o = mfma(Wt[kWtW5 / 8 + (2 * s + 1) * 64 + lane], hv, o);
+        }
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        if (tile_ok && g <= 1) {
+            const float* tt = A.t + src * 6;
+            const float m = tt[5];
+            if (g == 0) {
+                const float o0 = o[0] + Pp[kB5], o1 = o[1] + Pp[kB5 + 1], o2 = o[2] + Pp[kB5 + 2], o3 = o[3] + Pp[kB5 + 3];
+                const float cap = tt[0];
+                const float sp = (o0 > 0.0f) ? o0 + log1pf(__expf(-o0)) : log1pf(__expf(o0));
+                const float e1 = o1 - tt[1], e2 = o2 - tt[2], e3 = o3 - tt[3];
+                lacc += kWCap * (sp - cap * o0) + kWLogR * e1 * e1 + kWG * e2 * e2 + kWPhi * m * e3 * e3;
+                d[0] = kWCap * (sigmoidf_(o0) - cap) * A.inv_n;
+                d[1] = 2.0f * kWLogR * e1 * A.inv_n;
+                d[2] = 2.0f * kWG * e2 * A.inv_n;
+                d[3] = 2.0f * kWPhi * m * e3 * A.inv_n;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) A.dout[row * kOut + e] = d[e];
+            } else {
+                const float e4 = o[0] + Pp[kB5 + 4] - tt[4];
+                lacc += kWPhi * m * e4 * e4;
+                d[0] = 2.0f * kWPhi * m * e4 * A.inv_n;
+                A.dout[row * kOut + 4] = d[0];
+            }
+        }
+        // B operands of dh4 = dL/do W5: lane (r, 0) holds dL/do of row r (hi and lo parts);
+        // output 4 comes from lane (r, 1)
+        const float d4 = __shfl(d[0], r + 16);
+        bf16x8 dhi, dlo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float v = (g == 0 && e < kOut) ? (e < 4 ? d[e] : d4) : 0.0f;
+            const __bf16 hi = (__bf16)v;
+            dhi[e] = hi;
+            dlo[e] = (__bf16)(v - (float)hi);
+        }
+        // ---------------- backward
+        asm volatile("" : "+s"(Wt), "+s"(Pp));
+        bf16x4 dz[16], ndz[16];
+        // dz4 = (dL/do W5) SiLU'(z4)
+#pragma unroll
+        for (int jb = 0; jb < 16; ++jb) {
+            const bf16x8 wh = Wt[kWtW5T / 8 + (2 * jb) * 64 + lane], wo = Wt[kWtW5T / 8 + (2 * jb + 1) * 64 + lane];
+            f32x4 h = mfma(wh, dhi, f32x4{0.f, 0.f, 0.f, 0.f});
+            h = mfma(wo, dhi, h);
+            h = mfma(wh, dlo, h);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dz[jb][e] = (__bf16)(h[e] * (float)sp4[jb][e]);
+            store_t(dz[jb], A.dzT[3], jb);
+        }
+        // dh_{L-1} = dz_L W_L for L = 4, 3, 2 (fragment set li = L - 2), dz_{L-1} = dh_{L-1} SiLU'(z_{L-1})
+#pragma unroll 1
+        for (int li = 2; li >= 0; --li) {
+            asm volatile("" : "+s"(Wt), "+s"(Pp));  // no loads hoisted out of this loop
+            const int lam = 5 - li;
+            half_barrier();
+            issue(lam, 1);
+            const __bf16* spsrc = A.spF[li > 0 ? li - 1 : 0] + spo;
+#pragma unroll
+            for (int jb = 0; jb < 16; ++jb) {
+                if (jb == 8) {
+                    half_barrier();
+                    if (lam < 5) issue(lam + 1, 0);
+                    else if (more) issue(0, 0);  // the next block of rows' first set
+                }
+                bf16x8 w[8];
+                frags(jb, w);
+                f32x4 h = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 8; ++s) h = mfma(w[s], cat(dz[2 * s], dz[2 * s + 1]), h);
+                bf16x4 spv;
+                if (li > 0) {
+                    spv = *reinterpret_cast<const bf16x4*>(spsrc + jb * 64 * 4);
+                } else {
+                    // layer 1: SiLU'(z1) recomputed from x
+                    const f32x4 z = mfma(w1l[jb * 64 + lane], xf, bias(0, jb));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float sg = sigmoidf_(z[e]);
+                        spv[e] = (__bf16)(sg * (1.0f + z[e] * (1.0f - sg)));
                     }
                 }
-                gb[L - 1] += dz;
-                if (L == 1) {
 #pragma unroll
-                    for (int c = 0; c < kIn; ++c) gw1[c] += dz * xs[r * kIn + c];
-                }
-                const __bf16 dzb = (__bf16)dz;
-                out[e] = dzb;
-                act[r * kLdsStride + cu] = dzb;
+                for (int e = 0; e < 4; ++e) ndz[jb][e] = (__bf16)(h[e] * (float)spv[e]);
+                store_t(ndz[jb], A.dzT[li], jb);
             }
-            if (L >= 2) *reinterpret_cast<bf16x8*>(B.dzT[L - 1] + tm_index(cu, b8)) = out;
+#pragma unroll
+            for (int jb = 0; jb < 16; ++jb) dz[jb] = ndz[jb];
+        }
+    }
+#pragma unroll
+    for (int dd = 32; dd > 0; dd >>= 1) lacc += __shfl_xor(lacc, dd);
+    if (lane == 0) atomicAdd(A.loss, lacc * A.inv_n);
+}
+
+// The gradients that sum over the batch besides dL/dW2..dL/dW4, as MFMA
+// products over chunks of kSmChunk rows, A = a per-sample array (256 units x
+// rows, tile-major), B = 16 columns built from the chunk's rows in LDS:
+//   task 0: A = dz1, B = [x hi (4), x lo (4), 1]: dL/dW1[u][c] = D[u][c] + D[u][4 + c], dL/db1 = D[u][8];
+//   tasks 1..3: A = dz2..dz4, B = [1]: dL/db2..b4 = D[u][0];
+//   task 4: A = h4, B = [dL/do hi (5), 0 (3), dL/do lo (5)]: dL/dW5[o][u] = D[u][o] + D[u][8 + o],
+//     and dL/db5 = sum dL/do by the block's threads.
+// One block of 4 waves per (task, chunk), a wave 64 units; partial sums
+// [task][chunk][256][16] and [chunk][8], added over the chunks in order by
+// train_small_reduce.
+constexpr int kSmChunk = 1024, kSmTasks = 5;
+constexpr int kSmVals = 4 * kH + kH * kIn + kOut * kH + kOut;  // b1..b4, W1, W5, b5
+__global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, const int32_t* __restrict__ idx,
+                                                   int64_t n, const TrainRowsArgs A, float* __restrict__ part) {
+    __shared__ bf16x8 bfr[kSmChunk / 64][2][64];  // B fragments of the chunk's 64-row steps (32 KB)
+    __shared__ float rowv[kSmChunk][8];         // the chunk's x (task 0) or dL/do (task 4) rows
+    __shared__ float bsum[256][kOut];
+    const int task = blockIdx.x % kSmTasks, chunk = blockIdx.x / kSmTasks;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int64_t b0 = (int64_t)chunk * kSmChunk, b1 = std::min<int64_t>(n, b0 + kSmChunk);
+    const int rows = (int)(b1 - b0), nsteps = (rows + 63) / 64;  // n is a multiple of 32
+    // the chunk's rows of x (gathered through idx) or dL/do, all loads issued together
+    if (task == 0) {
+        for (int r = tid; r < rows; r += 256) {
+            const int64_t b = b0 + r;
+            const f32x4 xv = *reinterpret_cast<const f32x4*>(x + (idx ? (int64_t)idx[b] : b) * kIn);
+#pragma unroll
+            for (int c = 0; c < kIn; ++c) rowv[r][c] = xv[c];
+        }
+    } else if (task == 4) {
+        for (int i = tid; i < rows * kOut; i += 256) rowv[i / kOut][i % kOut] = A.dout[b0 * kOut + i];
+    }
+    __syncthreads();
+    // B fragments: a k step is one 64-row tile taken as two products (hh = 0, 1) in the row
+    // order of train_dw: lane (col, kg) of product hh holds B[rows 64 q + 16 kg + 8 hh + e][col];
+    // rows past the chunk's end are zero
+    for (int i = tid; i < nsteps * 128; i += 256) {
+        const int q = i / 128, hh = (i / 64) & 1, l = i % 64, col = l & 15, kg = l >> 4;
+        bf16x8 f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int r = 64 * q + 16 * kg + 8 * hh + e;
+            float v = 0.0f;
+            if (r >= rows) {
+            } else if (task == 0) {
+                if (col < 8) {
+                    const float xv = rowv[r][col & 3];
+                    const float hi = (float)(__bf16)xv;
+                    v = (col < 4) ? hi : xv - hi;
+                } else if (col == 8) {
+                    v = 1.0f;
+                }
+            } else if (task < 4) {
+                v = (col == 0) ? 1.0f : 0.0f;
+            } else if (col < kOut || (col >= 8 && col < 8 + kOut)) {
+                const float dv = rowv[r][col & 7];
+                const float hi = (float)(__bf16)dv;
+                v = (col < 8) ? hi : dv - hi;
+            }
+            f[e] = (__bf16)v;
+        }
+        bfr[q][hh][l] = f;
+    }
+    if (task == 4) {
+        // dL/db5: thread t sums rows t, t + 256, ... of the chunk, then the threads in order
+        float sv[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int r = tid; r < rows; r += 256)
+#pragma unroll
+            for (int o = 0; o < kOut; ++o) sv[o] += rowv[r][o];
+#pragma unroll
+        for (int o = 0; o < kOut; ++o) bsum[tid][o] = sv[o];
+    }
+    __syncthreads();
+    if (task == 4 && tid < kOut) {
+        float b5 = 0.0f;
+        for (int t = 0; t < 256; ++t) b5 += bsum[t][tid];
+        const int64_t nchunk = (n + kSmChunk - 1) / kSmChunk;
+        part[kSmTasks * nchunk * kH * 16 + (int64_t)chunk * 8 + tid] = b5;
+    }
+    const __bf16* src = (task < 4) ? A.dzT[task] : A.hT[3];
+    f32x4 acc[4] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f},
+                    f32x4{0.f, 0.f, 0.f, 0.f}};
+    constexpr int kAhead = 2;
+    bf16x8 af[kAhead][4][2];
+    auto load = [&](int q, bf16x8 (&a)[4][2]) {
+        const int64_t kk = b0 + 64 * q + 16 * lg;
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            const bf16x8* pa = reinterpret_cast<const bf16x8*>(src + tm_index(16 * (4 * wave + mi) + lr, kk));
+            a[mi][0] = pa[0];
+            a[mi][1] = pa[1];
         }
     };
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row0 = tile * kTileRows;
-        __syncthreads();
-        for (int i = tid; i < kTileRows * kIn; i += NT) {
-            const int64_t b = row0 + i / kIn;
-            xs[i] = (b < n) ? x[(idx ? (int64_t)idx[b] : b) * kIn + i % kIn] : 0.0f;
-        }
-        for (int i = tid; i < kTileRows * kOut; i += NT) ds[i] = (row0 + i / kOut < n) ? B.dout[row0 * kOut + i] : 0.0f;
-        __syncthreads();
-        column(4, row0);
-        __syncthreads();
-        for (int l = 4; l >= 2; --l) {
-            // dh_{l-1}[row][i] = sum_o dz_l[row][o] W_l[o][i], A = W_l^T rows (Wb[i][o])
-            const __bf16* W = Wb + (int64_t)(l - 2) * kH * kH + (int64_t)(16 * UJ * wu + lr) * kH;
-            const __bf16* A = act + (16 * RI * wr + lr) * kLdsStride;
-            f32x4 acc[RI][UJ];
+    // every load issued (clamped to the last step) so each step waits only for its own loads;
+    // the rows of a half-filled last tile past n are zeroed in A as they are in B
+    const bool tail_half = (rows % 64) != 0;
 #pragma unroll
-            for (int i = 0; i < RI; ++i)
+    for (int q = 0; q < kAhead; ++q) load(std::min(q, nsteps - 1), af[q]);
+    for (int s0 = 0; s0 < nsteps; s0 += kAhead) {
 #pragma unroll
-                for (int j = 0; j < UJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-            // the weight fragments of step s + 1 load while step s multiplies
-            bf16x8 afn[UJ];
+        for (int q = 0; q < kAhead; ++q) {
+            if (s0 + q < nsteps) {
+                if (tail_half && s0 + q == nsteps - 1 && lg >= 2) {
 #pragma unroll
-            for (int j = 0; j < UJ; ++j) afn[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + 8 * lg);
-#pragma unroll 1
-            for (int s = 0; s < kH / 32; ++s) {
-                const int k = 32 * s + 8 * lg;
-                const int kn = 32 * (s + 1 < kH / 32 ? s + 1 : s) + 8 * lg;
-                bf16x8 af[UJ], bfg[RI];
-#pragma unroll
-                for (int j = 0; j < UJ; ++j) {
-                    af[j] = afn[j];
-                    afn[j] = *reinterpret_cast<const bf16x8*>(W + 16 * j * kH + kn);
+                    for (int mi = 0; mi < 4; ++mi) af[q][mi][0] = af[q][mi][1] = bf16x8{};
                 }
 #pragma unroll
-                for (int i = 0; i < RI; ++i) bfg[i] = *reinterpret_cast<const bf16x8*>(A + 16 * i * kLdsStride + k);
+                for (int hh = 0; hh < 2; ++hh) {
+                    const bf16x8 bb = bfr[s0 + q][hh][lane];
 #pragma unroll
-                for (int i = 0; i < RI; ++i)
-#pragma unroll
-                    for (int j = 0; j < UJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfg[i], acc[i][j], 0, 0, 0);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < UJ; ++j) {
-                const int u = 16 * (UJ * wu + j) + 4 * lg;
-#pragma unroll
-                for (int i = 0; i < RI; ++i) {
-                    const bf16x4 v = {(__bf16)acc[i][j][0], (__bf16)acc[i][j][1], (__bf16)acc[i][j][2],
-                                      (__bf16)acc[i][j][3]};
-                    *reinterpret_cast<bf16x4*>(act + (16 * (RI * wr + i) + lr) * kLdsStride + u) = v;
+                    for (int mi = 0; mi < 4; ++mi)
+                        acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[q][mi][hh], bb, acc[mi], 0, 0, 0);
                 }
             }
-            __syncthreads();
-            column(l - 1, row0);
-            __syncthreads();
+            load(std::min(s0 + q + kAhead, nsteps - 1), af[q]);
         }
     }
-    const int64_t boff[4] = {kB1, kB2, kB3, kB4};
+    // accumulator e of mi: unit 16 (4 wave + mi) + 4 lg + e, column lr
+    float* out = part + ((int64_t)task * ((n + kSmChunk - 1) / kSmChunk) + chunk) * kH * 16;
 #pragma unroll
-    for (int L = 0; L < 4; ++L) atomicAdd(&G[boff[L] + cu], gb[L]);
+    for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int c = 0; c < kIn; ++c) atomicAdd(&G[kW1 + cu * kIn + c], gw1[c]);
-#pragma unroll
-    for (int j = 0; j < kOut; ++j) atomicAdd(&G[kW5 + j * kH + cu], gw5[j]);
-    if (cu == 0) {
-#pragma unroll
-        for (int j = 0; j < kOut; ++j) atomicAdd(&G[kB5 + j], gb5[j]);
+        for (int e = 0; e < 4; ++e) out[(16 * (4 * wave + mi) + 4 * lg + e) * 16 + lr] = acc[mi][e];
+}
+
+// dL/db1..b4, W1, W5, b5 from train_small's chunk partials, added in chunk order
+// (one thread per gradient value).
+__global__ void __launch_bounds__(256) train_small_reduce(const float* __restrict__ part, int nchunk,
+                                                          float* __restrict__ G) {
+    // eight consecutive threads per value: thread k adds chunks k, k + 8, ... in order, then
+    // the eight partial sums are combined by a fixed butterfly
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / 8, k = threadIdx.x % 8;
+    const bool live = i < kSmVals;
+    // (task, column, second column or -1) of the value and its destination
+    int task = 0, col = 0, col2 = -1, u = 0;
+    int64_t dst = -1;
+    const float* p = nullptr;
+    int stride = kH * 16;
+    if (!live) {
+    } else if (i < 4 * kH) {
+        const int L = i / kH;
+        u = i % kH;
+        task = L;
+        col = (L == 0) ? 8 : 0;
+        dst = (L == 0 ? kB1 : (L == 1 ? kB2 : (L == 2 ? kB3 : kB4))) + u;
+    } else if (i < 4 * kH + kH * kIn) {
+        const int j = i - 4 * kH;
+        u = j / kIn;
+        task = 0;
+        col = j % kIn;
+        col2 = 4 + col;
+        dst = kW1 + j;
+    } else if (i < 4 * kH + kH * kIn + kOut * kH) {
+        const int j = i - 4 * kH - kH * kIn, o = j / kH;
+        u = j % kH;
+        task = 4;
+        col = o;
+        col2 = 8 + o;
+        dst = kW5 + j;
+    } else {
+        const int o = i - 4 * kH - kH * kIn - kOut * kH;
+        p = part + (int64_t)kSmTasks * nchunk * kH * 16 + o;  // b5: [chunk][8]
+        stride = 8;
+        dst = kB5 + o;
     }
+    if (live && !p) p = part + (int64_t)task * nchunk * kH * 16 + u * 16 + col;
+    float s = 0.0f;
+    if (live)
+        for (int c = k; c < nchunk; c += 8)
+            s += p[(int64_t)c * stride] + (col2 >= 0 ? p[(int64_t)c * stride + (col2 - col)] : 0.0f);
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    if (live && k == 0) G[dst] = s;
 }
 
 // Partial dW_L over one row chunk: block (column group cg of 64 input units,
@@ -628,7 +753,7 @@ __global__ void __launch_bounds__(256) train_dw(const TrainBufs B, int64_t n, fl
     const int li = pair / kDwChunks, chunk = pair % kDwChunks;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    const int64_t per = (((n + kDwChunks - 1) / kDwChunks) + 31) / 32 * 32;
+    const int64_t per = (((n + kDwChunks - 1) / kDwChunks) + 63) / 64 * 64;  // whole 64-row tiles
     const int64_t b0 = chunk * per, b1 = std::min<int64_t>(n, b0 + per);
     const __bf16* dz = B.dzT[li + 1];  // dL/dz of layer li + 2
     const __bf16* h = B.hT[li];        // h of layer li + 1
@@ -637,37 +762,88 @@ __global__ void __launch_bounds__(256) train_dw(const TrainBufs B, int64_t n, fl
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t b = b0; b < b1; b += 32) {
-        const int64_t kk = b + 8 * lg;
-        bf16x8 af[4], bfr[4];
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) af[mi] = *reinterpret_cast<const bf16x8*>(dz + tm_index(16 * (4 * wave + mi) + lr, kk));
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) bfr[ni] = *reinterpret_cast<const bf16x8*>(h + tm_index(64 * cg + 16 * ni + lr, kk));
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < 4; ++ni)
-                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mi], bfr[ni], acc[mi][ni], 0, 0, 0);
+    // One k step is one 64-row tile, taken as two products of 32: lane (m, kg) loads the 16
+    // consecutive rows 16 kg .. 16 kg + 15 of its unit (32 bytes; the 64 lanes read 16 whole
+    // 128-byte rows of the tile) and gives rows 16 kg + e to the first product and 16 kg + 8 + e
+    // to the second. Both operands use the same order of the rows, which the sum over the rows
+    // does not see. The rows of a half-filled last tile (n is a multiple of 32) past n are
+    // zeroed in both operands. Operands are loaded kDwAhead steps before they are multiplied,
+    // in a ring of registers; every load is issued (past the last step it re-reads that
+    // step), so each step waits only for its own loads.
+    constexpr int kDwAhead = 2;
+    const int64_t nsteps = (b1 - b0 + 63) / 64;
+    if (nsteps <= 0) {
+        float* out = part + (int64_t)(li * kDwChunks + chunk) * kH * kH;
+        for (int i = threadIdx.x; i < 64 * kH; i += 256) out[cg * 64 * kH + i] = 0.0f;  // this group's slots
+        return;
     }
-    // accumulator e of (mi, ni): output unit 16 (4 wave + mi) + 4 lg + e, input unit 64 cg + 16 ni + lr
-    float* out = part + (int64_t)(li * kDwChunks + chunk) * kH * kH;
+    bf16x8 af[kDwAhead][4][2], bfr[kDwAhead][4][2];
+    auto load = [&](int64_t q, bf16x8 (&a)[4][2], bf16x8 (&bb)[4][2]) {
+        const int64_t kk = b0 + 64 * q + 16 * lg;
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            const bf16x8* pa = reinterpret_cast<const bf16x8*>(dz + tm_index(16 * (4 * wave + mi) + lr, kk));
+            a[mi][0] = pa[0];
+            a[mi][1] = pa[1];
+        }
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            const bf16x8* pb = reinterpret_cast<const bf16x8*>(h + tm_index(64 * cg + 16 * ni + lr, kk));
+            bb[ni][0] = pb[0];
+            bb[ni][1] = pb[1];
+        }
+    };
+    const bool tail_half = (b1 - b0) % 64 != 0;  // the last step holds 32 valid rows
+#pragma unroll
+    for (int q = 0; q < kDwAhead; ++q) load(std::min<int64_t>(q, nsteps - 1), af[q], bfr[q]);
+    for (int64_t s0 = 0; s0 < nsteps; s0 += kDwAhead) {
+#pragma unroll
+        for (int q = 0; q < kDwAhead; ++q) {
+            if (s0 + q < nsteps) {
+                if (tail_half && s0 + q == nsteps - 1 && lg >= 2) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            af[q][i][hh] = bf16x8{};
+                            bfr[q][i][hh] = bf16x8{};
+                        }
+                }
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 4; ++ni)
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[q][mi][hh], bfr[q][ni][hh], acc[mi][ni], 0, 0, 0);
+            }
+            load(std::min<int64_t>(s0 + q + kDwAhead, nsteps - 1), af[q], bfr[q]);
+        }
+    }
+    // the accumulators as they are, 16 bytes per lane (dw_slot gives each one's place)
+    f32x4* out = reinterpret_cast<f32x4*>(part + (int64_t)(li * kDwChunks + chunk) * kH * kH) + (cg * 4 + wave) * 16 * 64;
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                out[(int64_t)(16 * (4 * wave + mi) + 4 * lg + e) * kH + 64 * cg + 16 * ni + lr] = acc[mi][ni][e];
+        for (int ni = 0; ni < 4; ++ni) out[(mi * 4 + ni) * 64 + lane] = acc[mi][ni];
+}
+
+// What train_dw leaves in slot j of a chunk's partial sums: j = (((cg 4 + wave) 16 + mi 4 + ni)
+// 64 + lane) 4 + e holds dL/dW[o][k] for output unit o = 16 (4 wave + mi) + 4 (lane / 16) + e
+// and input unit k = 64 cg + 16 ni + lane % 16; returns o kH + k.
+__device__ __forceinline__ int dw_entry(int j) {
+    const int e = j % 4, lane = (j / 4) % 64, t = j / 256, mi = (t % 16) / 4, ni = t % 4, wave = (t / 16) % 4,
+              cg = t / 64;
+    return (16 * (4 * wave + mi) + 4 * (lane / 16) + e) * kH + 64 * cg + 16 * ni + lane % 16;
 }
 
 __global__ void __launch_bounds__(256) train_dw_reduce(const float* __restrict__ part, float* __restrict__ G) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * kH * kH; i += (int64_t)gridDim.x * blockDim.x) {
-        const int li = (int)(i / (kH * kH));
-        const int64_t e = i % (kH * kH);
+        const int li = (int)(i / (kH * kH)), j = (int)(i % (kH * kH));
+        const float* p = part + (int64_t)li * kDwChunks * kH * kH + j;
         float s = 0.0f;
-        for (int c = 0; c < kDwChunks; ++c) s += part[(int64_t)(li * kDwChunks + c) * kH * kH + e];
-        G[(li == 0 ? kW2 : (li == 1 ? kW3 : kW4)) + e] = s;
+        for (int c = 0; c < kDwChunks; ++c) s += p[(int64_t)c * kH * kH];
+        G[(li == 0 ? kW2 : (li == 1 ? kW3 : kW4)) + dw_entry(j)] = s;
     }
 }
 
@@ -687,37 +863,12 @@ __global__ void __launch_bounds__(256) adam(float* __restrict__ P, float* __rest
     }
 }
 
-// For the training kernels, BF16 copies of W2..W4: Wf[l][out][in] (forward) and
-// Wb[l][in][out] (input gradients); after them in Wf, W5 as two BF16 parts
-// hi + lo of 16 x 256 (outputs 5..15 zero) for the output head. For inference,
-// the scaled biases in Pi.
-__global__ void __launch_bounds__(256) pack_weights(const float* __restrict__ P, __bf16* __restrict__ Wf,
-                                                    __bf16* __restrict__ Wb, float* __restrict__ Pi) {
-    const int l = blockIdx.y;  // 0..2 -> W2..W4, 3 -> W5 split, 4 -> scaled biases
-    if (l == 4) {
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kPiSize; i += gridDim.x * blockDim.x) {
-            const int layer = (i - kPiB) / kH, u = (i - kPiB) % kH;
-            const int64_t off = layer == 0 ? kB1 : (layer == 1 ? kB2 : (layer == 2 ? kB3 : kB4));
-            Pi[i] = -kLog2e * P[off + u];
-        }
-        return;
-    }
-    if (l == 3) {
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kW5Rows * kH; i += gridDim.x * blockDim.x) {
-            const int o = i / kH;
-            const float wu = (o < kOut) ? P[kW5 + i] : 0.0f;
-            const __bf16 hu = (__bf16)wu;
-            Wf[kW5SplitU + i] = hu;
-            Wf[kW5SplitU + kW5Rows * kH + i] = (__bf16)(wu - (float)hu);
-        }
-        return;
-    }
-    const float* W = P + (l == 0 ? kW2 : (l == 1 ? kW3 : kW4));
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kH * kH; i += gridDim.x * blockDim.x) {
-        const int o = i / kH, k = i % kH;
-        const __bf16 v = (__bf16)W[i];
-        Wf[(int64_t)l * kH * kH + i] = v;
-        Wb[(int64_t)l * kH * kH + k * kH + o] = v;
+// The inference kernel's scaled biases Pi (see the scaling note above).
+__global__ void __launch_bounds__(256) pack_biases(const float* __restrict__ P, float* __restrict__ Pi) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kPiSize; i += gridDim.x * blockDim.x) {
+        const int layer = (i - kPiB) / kH, u = (i - kPiB) % kH;
+        const int64_t off = layer == 0 ? kB1 : (layer == 1 ? kB2 : (layer == 2 ? kB3 : kB4));
+        Pi[i] = -kLog2e * P[off + u];
     }
 }
 
@@ -1065,14 +1216,16 @@ struct kgrt_mlp {
     int device = 0;
     int64_t max_batch = 0;
     float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr;
-    __bf16 *Wf = nullptr, *Wb = nullptr;
     __bf16* Wr = nullptr;  // MFMA fragments of all layers for the row-parallel inference kernel
+    __bf16* Wt = nullptr;  // fragments of the row-parallel training kernel (input layer, head, W^T)
     float* Pi = nullptr;   // scaled W1 and biases for inference
-    // training arrays, feature-major [256][max_batch] BF16: z[l] holds SiLU'(z_l),
-    // hT[l] and dz the activations h_l (l = 1..3) and h_4, h[l] the gradients dL/dz_l
+    // training arrays, BF16, 256 values per sample: z[l] holds SiLU'(z_l) (l = 2, 3) in the
+    // training kernel's accumulator layout; tile-major, hT[l] and dz the activations h_l
+    // (l = 1..3) and h_4, h[l] the gradients dL/dz_l (l = 1..4)
     __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr;
     float* dout = nullptr;
-    float* part = nullptr;  // weight-gradient partial sums [3][kDwChunks][256][256]
+    float* part = nullptr;   // weight-gradient partial sums [3][kDwChunks][256][256]
+    float* spart = nullptr;  // the other gradients' partial sums: [5][chunks][256][16], then [chunks][8]
     int64_t step = 0;
     // render workspace (grown on demand): features, outputs, fallback list and its integration
     float *r_feat = nullptr, *r_pred = nullptr, *r_tab = nullptr;
@@ -1113,7 +1266,7 @@ int64_t kgrt_mlp_num_params(void) { return kNumParams; }
 int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
-    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wf, m->Wb, m->Wr, m->Pi, m->part, m->dz, m->dout, m->r_feat, m->r_pred,
+    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wr, m->Wt, m->Pi, m->part, m->spart, m->dz, m->dout, m->r_feat, m->r_pred,
                     m->r_tab, m->r_part, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
                     m->h[1], m->h[2], m->h[3], m->h[4], m->z[1], m->z[2], m->z[3], m->z[4],
                     m->hT[1], m->hT[2], m->hT[3]};
@@ -1136,13 +1289,14 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
     const size_t hb = (size_t)((max_batch + 63) / 64 * 64) * kH * sizeof(__bf16);  // whole 64-row tiles
     bool ok = hipMalloc(&m->P, kNumParams * 4) == hipSuccess && hipMalloc(&m->M, kNumParams * 4) == hipSuccess &&
               hipMalloc(&m->V, kNumParams * 4) == hipSuccess && hipMalloc(&m->G, kNumParams * 4) == hipSuccess &&
-              hipMalloc(&m->Wf, kWfSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Wr, kWrSize * sizeof(__bf16)) == hipSuccess &&
+              hipMalloc(&m->Wt, kWtSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Pi, kPiSize * sizeof(float)) == hipSuccess &&
-              hipMalloc(&m->Wb, 3 * kH * kH * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess &&
-              hipMalloc(&m->part, (size_t)3 * kDwChunks * kH * kH * 4) == hipSuccess;
-    for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess && hipMalloc(&m->z[l], hb) == hipSuccess;
+              hipMalloc(&m->part, (size_t)3 * kDwChunks * kH * kH * 4) == hipSuccess &&
+              hipMalloc(&m->spart, (size_t)((max_batch + kSmChunk - 1) / kSmChunk) * (kSmTasks * kH * 16 + 8) * 4) == hipSuccess;
+    for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess;
+    for (int l = 2; ok && l <= 3; ++l) ok = hipMalloc(&m->z[l], hb) == hipSuccess;
     for (int l = 1; ok && l <= 3; ++l) ok = hipMalloc(&m->hT[l], hb) == hipSuccess;
     ok = ok && hipMalloc(&m->dz, hb) == hipSuccess;
     if (!ok) {
@@ -1163,8 +1317,9 @@ int kgrt_mlp_set_params(kgrt_mlp* m, const float* params, int64_t n) {
         return mlp_fail(m, KGRT_E_HIP, "hipMemcpy failed");
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->M, kNumParams, 0.0f);
     hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, 0, m->V, kNumParams, 0.0f);
-    hipLaunchKernelGGL(pack_weights, dim3(64, 5), dim3(256), 0, 0, m->P, m->Wf, m->Wb, m->Pi);
+    hipLaunchKernelGGL(pack_biases, dim3(4), dim3(256), 0, 0, m->P, m->Pi);
     hipLaunchKernelGGL(pack_rows, dim3(208), dim3(256), 0, 0, m->P, m->Wr);
+    hipLaunchKernelGGL(pack_train, dim3(432), dim3(256), 0, 0, m->P, m->Wt);
     m->step = 0;
     if (hipDeviceSynchronize() != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "set_params failed");
     return KGRT_OK;
@@ -1234,31 +1389,43 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     if (!x || !t || !loss) return mlp_fail(m, KGRT_E_INVALID_ARG, "x, t and loss must be device pointers");
     DevGuard g(m->device);
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(fill_f32, dim3(256), dim3(256), 0, st, m->G, kNumParams, 0.0f);
+    // every gradient entry is written (not added) by the two reductions below
     hipLaunchKernelGGL(fill_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1, 0.0f);
+    // per-sample arrays: h1..h4 and dL/dz of layers 1..4 tile-major, SiLU'(z) of layers 2
+    // and 3 in the training kernel's accumulator layout, dL/do row-major
+    TrainRowsArgs ta{};
+    ta.x = x;
+    ta.idx = idx;
+    ta.t = t;
+    ta.n = n;
+    ta.P = m->P;
+    ta.Wr = m->Wr;
+    ta.Wt = m->Wt;
+    for (int l = 0; l < 3; ++l) ta.hT[l] = m->hT[l + 1];
+    ta.hT[3] = m->dz;
+    for (int l = 0; l < 4; ++l) ta.dzT[l] = m->h[l + 1];
+    ta.spF[0] = m->z[2];
+    ta.spF[1] = m->z[3];
+    ta.dout = m->dout;
+    ta.loss = loss;
+    ta.inv_n = 1.0f / (float)n;
     TrainBufs tb{};
     for (int l = 0; l < 4; ++l) {
-        tb.sT[l] = m->z[l + 1];
-        tb.dzT[l] = m->h[l + 1];
+        tb.hT[l] = ta.hT[l];
+        tb.dzT[l] = ta.dzT[l];
     }
-    for (int l = 0; l < 3; ++l) tb.hT[l] = m->hT[l + 1];
-    tb.hT[3] = m->dz;
-    tb.dout = m->dout;
-    tb.loss = loss;
-    tb.inv_n = 1.0f / (float)n;
-    int dev = 0, ncu = 256, pf = 1, pb = 1;
+    int dev = 0, ncu = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    auto kf = train_fwd<kTrainRI, kTrainUJ>;
-    auto kb = train_bwd<kTrainRI, kTrainUJ>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pf, kf, kTrainThreads, 0) != hipSuccess || pf < 1) pf = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pb, kb, kTrainThreads, 0) != hipSuccess || pb < 1) pb = 1;
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-    hipLaunchKernelGGL(kf, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pf)), dim3(kTrainThreads), 0, st, x,
-                       idx, t, n, m->P, m->Wf, tb);
-    hipLaunchKernelGGL(kb, dim3((unsigned)std::min<int64_t>(ntiles, (int64_t)ncu * pb)), dim3(kTrainThreads), 0, st, x,
-                       idx, n, m->P, m->Wb, tb, m->G);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_rows, kTrThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t nblk = (n + kTrRows - 1) / kTrRows;
+    hipLaunchKernelGGL(train_rows, dim3((unsigned)std::min<int64_t>(nblk, (int64_t)ncu * per_cu)), dim3(kTrThreads), 0,
+                       st, ta);
     hipLaunchKernelGGL(train_dw, dim3(kDwBlocks), dim3(256), 0, st, tb, n, m->part);
     hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
+    const int nsm = (int)((n + kSmChunk - 1) / kSmChunk);
+    hipLaunchKernelGGL(train_small, dim3(nsm * kSmTasks), dim3(256), 0, st, x, idx, n, ta, m->spart);
+    hipLaunchKernelGGL(train_small_reduce, dim3((kSmVals * 8 + 255) / 256), dim3(256), 0, st, m->spart, nsm, m->G);
     if (grads && hipMemcpyAsync(grads, m->G, kNumParams * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return mlp_fail(m, KGRT_E_HIP, "gradient copy failed");
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
@@ -1278,8 +1445,9 @@ int kgrt_mlp_train_step(kgrt_mlp* m, const float* x, const float* t, const int32
     const float c1 = 1.0f - powf(opt->beta1, (float)m->step), c2 = 1.0f - powf(opt->beta2, (float)m->step);
     hipLaunchKernelGGL(adam, dim3(256), dim3(256), 0, st, m->P, m->M, m->V, m->G, kNumParams, opt->lr, opt->beta1,
                        opt->beta2, opt->eps, c1, c2);
-    hipLaunchKernelGGL(pack_weights, dim3(64, 5), dim3(256), 0, st, m->P, m->Wf, m->Wb, m->Pi);
+    hipLaunchKernelGGL(pack_biases, dim3(4), dim3(256), 0, st, m->P, m->Pi);
     hipLaunchKernelGGL(pack_rows, dim3(208), dim3(256), 0, st, m->P, m->Wr);
+    hipLaunchKernelGGL(pack_train, dim3(432), dim3(256), 0, st, m->P, m->Wt);
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
 }
 
