@@ -55,22 +55,22 @@ FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "cali
 # WRITE_SIZE (scaled by a 1 GiB copy probe), see
 # profiles/torus_1024_hbm_traffic.md. Valid only for the kernel sources they
 # were taken on (md5 of csrc/kgrt.hip + csrc/kgrt_device.hpp); null otherwise.
-# (The one-frequency kernels' code is unchanged since the torus and thin-disk
-# figures were taken, and the eight-frequency kernel's since the batch figures
-# were: later source changes touched other kernels or launch settings only, and
-# these kernels assemble to the same code.)
-# VALU lane utilisation of the dominant kernel on the 1024^2 torus image (useful
-# FP64 FLOPs / FP64 lane slots issued, rocprofv3 counters), valid for the sources it
-# was taken on; see profiles/trace_kernel_flop_calibration.md.
-LANE_UTILISATION = {"torus": {"value": 0.875, "source_md5": "b40af1c6bde3d6379c0d6568350768b2"},
-                    "batch": {"value": 0.874, "source_md5": "b40af1c6bde3d6379c0d6568350768b2"}}
+# VALU lane utilisation of the dominant kernel (useful FP64 FLOPs / FP64 lane
+# slots issued, rocprofv3 counters), valid for the sources it was taken on; see
+# profiles/trace_kernel_flop_calibration.md.
+HEAD_MD5 = "c21d37cde6fe44fd59c7a302ef379bf2"
+LANE_UTILISATION = {"torus": {"value": 0.876, "source_md5": HEAD_MD5},
+                    "batch": {"value": 0.892, "source_md5": HEAD_MD5},
+                    "thin_disk": {"value": 0.860, "source_md5": HEAD_MD5},
+                    "grid": {"value": 0.874, "source_md5": HEAD_MD5}}
 
-TRAFFIC = {"torus": {"bytes": 490773120, "source_md5": "b40af1c6bde3d6379c0d6568350768b2"},
-           # all chunk launches of one plan launch of the 256-image batch, see
-           # profiles/batch256_trace_kernel_traffic.md
-           "batch": {"bytes": 21378415808, "source_md5": "b40af1c6bde3d6379c0d6568350768b2"},
+TRAFFIC = {"torus": {"bytes": 491315418, "source_md5": HEAD_MD5},
+           # the one launch of the 256-image plan, see profiles/batch256_trace_kernel_traffic.md
+           "batch": {"bytes": 22642143527, "source_md5": HEAD_MD5},
            # the 1024^2 thin-disk image, see profiles/trace_kernel_flop_calibration.md
-           "thin_disk": {"bytes": 1023473280, "source_md5": "b40af1c6bde3d6379c0d6568350768b2"}}
+           "thin_disk": {"bytes": 1022158373, "source_md5": HEAD_MD5},
+           # the 1024^2 image of the gridded snapshot, see profiles/grid_1024_kernel_trace.md
+           "grid": {"bytes": 13355692746, "source_md5": HEAD_MD5}}
 
 
 def kernel_source_md5() -> str:

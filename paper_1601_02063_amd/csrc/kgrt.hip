@@ -881,8 +881,10 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, shmem) != hipSuccess || per_cu <= 0)
             per_cu = 1;
         if (RayCountResidency<NF>::value && Transfer<MODEL>::value) {
-            // the residency of two waves per SIMD when three would leave too few rays per lane
-            const int64_t rays = (env.limit >= 0) ? std::min<int64_t>(env.limit, P.nrays) : P.nrays;
+            // the residency of two waves per SIMD when three would leave too few rays per lane;
+            // decided on the whole plan, also when the autotuner times a prefix of it, so the
+            // residency it times is the one the plan launches
+            const int64_t rays = P.nrays;
             const int two_waves = std::max(1, (2 * 4 * 64) / block);  // blocks per CU at two waves per SIMD
             if (per_cu > two_waves && rays < (int64_t)kMinRaysPerLane * env.num_cus * per_cu * block)
                 per_cu = two_waves;
@@ -1337,7 +1339,9 @@ int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, k
     float best_ms = 1e30f;
     int rc = KGRT_OK;
     for (int block : {64, 128, 256}) {
-        for (int per_cu : {0, 1, 2}) {
+        // blocks per CU: the occupancy rule (0), then two and three waves per SIMD explicitly
+        const int waves2 = std::max(1, 2 * 4 * 64 / block), waves3 = std::max(1, 3 * 4 * 64 / block);
+        for (int per_cu : {0, waves2, waves3}) {
             for (int refill : {1, 16}) {
                 plan->launch = kgrt_launch{block, per_cu, refill, KGRT_LAUNCH_PERSISTENT};
                 rc = plan_enqueue(plan, out, st, sample);  // warm-up
