@@ -8,10 +8,11 @@
 // Inference (mlp_infer_rows) is row-parallel: a wave keeps its rows'
 // activations in registers through all layers, and the weights come as MFMA
 // fragments in a permuted order that lets one layer's accumulators serve as
-// the next layer's operand directly. Training (train_fwd, train_bwd,
-// train_dw) works on 64-sample tiles with the activations in LDS and stores
-// per-sample arrays tile-major for the weight-gradient products, which
-// contract over the batch.
+// the next layer's operand directly. Training runs the forward and backward
+// of every row in the same form (train_rows), stores the per-sample arrays
+// tile-major, and takes the gradient products that contract over the batch
+// in separate kernels (train_dw, train_small) over row ranges added in a
+// fixed order.
 //
 // Parameters: one flat FP32 vector, per layer W[out][in] then b[out] (the FP32
 // master copy); the BF16 copies and fragment arrays derived from it are
@@ -240,9 +241,10 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
 // contiguous bytes, and the whole tile is one 32 KB block.
 __device__ __forceinline__ int64_t tm_index(int u, int64_t b) { return (b >> 6) * (kH * 64) + u * 64 + (b & 63); }
 
-// The weight-gradient products dL/dW_l = sum_b dz_l[b] h_{l-1}[b]^T (l = 2..4) over
-// row chunks (train_dw), added up in chunk order by train_dw_reduce.
-constexpr int kDwChunks = 64;
+// The hidden layers' gradient products dL/dW_l = sum_b dz_l[b] h_{l-1}[b]^T and
+// dL/db_l = sum_b dz_l[b] (l = 2..4) over kDwParts ranges of rows per layer (train_dw),
+// added up in order by train_dw_reduce.
+constexpr int kDwParts = 85;
 struct TrainBufs {
     __bf16* hT[4];   // h of layers 1..4
     __bf16* dzT[4];  // dL/dz of layers 1..4
@@ -563,22 +565,21 @@ train_rows(const TrainRowsArgs A) {
     if (lane == 0) atomicAdd(A.loss, lacc * A.inv_n);
 }
 
-// The gradients that sum over the batch besides dL/dW2..dL/dW4, as MFMA
-// products over chunks of kSmChunk rows, A = a per-sample array (256 units x
-// rows, tile-major), B = 16 columns built from the chunk's rows in LDS:
+// The gradients of the input and output layers (train_dw takes the hidden ones), as MFMA
+// products over chunks of kSmChunk rows, A = a per-sample array (256 units x rows,
+// tile-major), B = 16 columns built from the chunk's rows in LDS:
 //   task 0: A = dz1, B = [x hi (4), x lo (4), 1]: dL/dW1[u][c] = D[u][c] + D[u][4 + c], dL/db1 = D[u][8];
-//   tasks 1..3: A = dz2..dz4, B = [1]: dL/db2..b4 = D[u][0];
-//   task 4: A = h4, B = [dL/do hi (5), 0 (3), dL/do lo (5)]: dL/dW5[o][u] = D[u][o] + D[u][8 + o],
+//   task 1: A = h4, B = [dL/do hi (5), 0 (3), dL/do lo (5)]: dL/dW5[o][u] = D[u][o] + D[u][8 + o],
 //     and dL/db5 = sum dL/do by the block's threads.
 // One block of 4 waves per (task, chunk), a wave 64 units; partial sums
 // [task][chunk][256][16] and [chunk][8], added over the chunks in order by
 // train_small_reduce.
-constexpr int kSmChunk = 1024, kSmTasks = 5;
-constexpr int kSmVals = 4 * kH + kH * kIn + kOut * kH + kOut;  // b1..b4, W1, W5, b5
+constexpr int kSmChunk = 256, kSmTasks = 2;
+constexpr int kSmVals = kH + kH * kIn + kOut * kH + kOut;  // b1, W1, W5, b5
 __global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, const int32_t* __restrict__ idx,
                                                    int64_t n, const TrainRowsArgs A, float* __restrict__ part) {
     __shared__ bf16x8 bfr[kSmChunk / 64][2][64];  // B fragments of the chunk's 64-row steps (32 KB)
-    __shared__ float rowv[kSmChunk][8];         // the chunk's x (task 0) or dL/do (task 4) rows
+    __shared__ float rowv[kSmChunk][8];         // the chunk's x (task 0) or dL/do (task 1) rows
     __shared__ float bsum[256][kOut];
     const int task = blockIdx.x % kSmTasks, chunk = blockIdx.x / kSmTasks;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -593,7 +594,7 @@ __global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, 
 #pragma unroll
             for (int c = 0; c < kIn; ++c) rowv[r][c] = xv[c];
         }
-    } else if (task == 4) {
+    } else {
         for (int i = tid; i < rows * kOut; i += 256) rowv[i / kOut][i % kOut] = A.dout[b0 * kOut + i];
     }
     __syncthreads();
@@ -616,8 +617,6 @@ __global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, 
                 } else if (col == 8) {
                     v = 1.0f;
                 }
-            } else if (task < 4) {
-                v = (col == 0) ? 1.0f : 0.0f;
             } else if (col < kOut || (col >= 8 && col < 8 + kOut)) {
                 const float dv = rowv[r][col & 7];
                 const float hi = (float)(__bf16)dv;
@@ -627,7 +626,7 @@ __global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, 
         }
         bfr[q][hh][l] = f;
     }
-    if (task == 4) {
+    if (task == 1) {
         // dL/db5: thread t sums rows t, t + 256, ... of the chunk, then the threads in order
         float sv[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
         for (int r = tid; r < rows; r += 256)
@@ -637,13 +636,13 @@ __global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, 
         for (int o = 0; o < kOut; ++o) bsum[tid][o] = sv[o];
     }
     __syncthreads();
-    if (task == 4 && tid < kOut) {
+    if (task == 1 && tid < kOut) {
         float b5 = 0.0f;
         for (int t = 0; t < 256; ++t) b5 += bsum[t][tid];
         const int64_t nchunk = (n + kSmChunk - 1) / kSmChunk;
         part[kSmTasks * nchunk * kH * 16 + (int64_t)chunk * 8 + tid] = b5;
     }
-    const __bf16* src = (task < 4) ? A.dzT[task] : A.hT[3];
+    const __bf16* src = (task == 0) ? A.dzT[0] : A.hT[3];
     f32x4 acc[4] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f},
                     f32x4{0.f, 0.f, 0.f, 0.f}};
     constexpr int kAhead = 2;
@@ -689,13 +688,13 @@ __global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, 
         for (int e = 0; e < 4; ++e) out[(16 * (4 * wave + mi) + 4 * lg + e) * 16 + lr] = acc[mi][e];
 }
 
-// dL/db1..b4, W1, W5, b5 from train_small's chunk partials, added in chunk order
+// dL/db1, W1, W5, b5 from train_small's chunk partials, added in chunk order
 // (one thread per gradient value).
 __global__ void __launch_bounds__(256) train_small_reduce(const float* __restrict__ part, int nchunk,
                                                           float* __restrict__ G) {
-    // eight consecutive threads per value: thread k adds chunks k, k + 8, ... in order, then
-    // the eight partial sums are combined by a fixed butterfly
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / 8, k = threadIdx.x % 8;
+    // 32 consecutive threads per value: thread k adds chunks k, k + 32, ... in order, then the
+    // 32 partial sums are combined by a fixed butterfly
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / 32, k = threadIdx.x % 32;
     const bool live = i < kSmVals;
     // (task, column, second column or -1) of the value and its destination
     int task = 0, col = 0, col2 = -1, u = 0;
@@ -703,28 +702,25 @@ __global__ void __launch_bounds__(256) train_small_reduce(const float* __restric
     const float* p = nullptr;
     int stride = kH * 16;
     if (!live) {
-    } else if (i < 4 * kH) {
-        const int L = i / kH;
-        u = i % kH;
-        task = L;
-        col = (L == 0) ? 8 : 0;
-        dst = (L == 0 ? kB1 : (L == 1 ? kB2 : (L == 2 ? kB3 : kB4))) + u;
-    } else if (i < 4 * kH + kH * kIn) {
-        const int j = i - 4 * kH;
+    } else if (i < kH) {
+        u = i;
+        col = 8;
+        dst = kB1 + u;
+    } else if (i < kH + kH * kIn) {
+        const int j = i - kH;
         u = j / kIn;
-        task = 0;
         col = j % kIn;
         col2 = 4 + col;
         dst = kW1 + j;
-    } else if (i < 4 * kH + kH * kIn + kOut * kH) {
-        const int j = i - 4 * kH - kH * kIn, o = j / kH;
+    } else if (i < kH + kH * kIn + kOut * kH) {
+        const int j = i - kH - kH * kIn, o = j / kH;
         u = j % kH;
-        task = 4;
+        task = 1;
         col = o;
         col2 = 8 + o;
         dst = kW5 + j;
     } else {
-        const int o = i - 4 * kH - kH * kIn - kOut * kH;
+        const int o = i - kH - kH * kIn - kOut * kH;
         p = part + (int64_t)kSmTasks * nchunk * kH * 16 + o;  // b5: [chunk][8]
         stride = 8;
         dst = kB5 + o;
@@ -732,117 +728,129 @@ __global__ void __launch_bounds__(256) train_small_reduce(const float* __restric
     if (live && !p) p = part + (int64_t)task * nchunk * kH * 16 + u * 16 + col;
     float s = 0.0f;
     if (live)
-        for (int c = k; c < nchunk; c += 8)
+        for (int c = k; c < nchunk; c += 32)
             s += p[(int64_t)c * stride] + (col2 >= 0 ? p[(int64_t)c * stride + (col2 - col)] : 0.0f);
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) s += __shfl_xor(s, d);
     if (live && k == 0) G[dst] = s;
 }
 
-// Partial dW_L over one row chunk: block (column group cg of 64 input units,
-// chunk, layer L - 2), 4 waves of 64 output units x 64 input units each.
-// Blocks go to the eight XCDs in turn (block b to XCD b mod 8); the four
-// column groups of one (layer, chunk) read the same dz rows, so they take four
-// consecutive block slots of one XCD and share its L2.
-constexpr int kDwBlocks = 3 * kDwChunks * (kH / 64);
-static_assert(kH / 64 == 4 && kDwBlocks % 32 == 0, "train_dw block mapping");
-__global__ void __launch_bounds__(256) train_dw(const TrainBufs B, int64_t n, float* __restrict__ part) {
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int cg = slot & 3, pair = (slot >> 2) * 8 + xcd;
-    const int li = pair / kDwChunks, chunk = pair % kDwChunks;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Partial dW_L and db_L over a range of 64-row tiles: block (layer L - 2, part j) takes tiles
+// [ntiles j / kDwParts, ntiles (j + 1) / kDwParts) and the whole 256 x 256 output; wave w
+// holds output units 128 (w / 4) .. + 127 against input units 64 (w % 4) .. + 63 (8 x 4
+// MFMA blocks). A k step is one tile, taken as two products of 32 rows (hh = 0, 1): lane
+// (m, kg) of a fragment holds rows 16 kg + 8 hh .. + 7 of its unit, the same order in both
+// operands, which the sum over the rows does not see. Each step's 64 fragments (dz and h of
+// all 256 units, 64 KB) reach LDS by direct global-to-LDS loads, double-buffered: the next
+// tile loads while the waves multiply the current one. The rows of a half-filled last tile
+// (n is a multiple of 32) past n are zeroed in both operands.
+constexpr int kDwWaves = 8;
+__global__ void __launch_bounds__(64 * kDwWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+train_dw(const TrainBufs B, int64_t n, float* __restrict__ part) {
+    __shared__ bf16x8 stg[2][64][64];  // [stage][fragment: 2 unit block + hh, dz then h][lane] (2 x 64 KB)
+    const int li = blockIdx.x / kDwParts, j = blockIdx.x % kDwParts;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lr = lane & 15, lg = lane >> 4;
-    const int64_t per = (((n + kDwChunks - 1) / kDwChunks) + 63) / 64 * 64;  // whole 64-row tiles
-    const int64_t b0 = chunk * per, b1 = std::min<int64_t>(n, b0 + per);
+    const int wo = wave >> 2, wk = wave & 3;  // wave-uniform (scalar registers)
+    const int64_t ntiles = (n + 63) / 64;
+    const int64_t t0 = ntiles * j / kDwParts, t1 = ntiles * (j + 1) / kDwParts;
+    const int nsteps = (int)(t1 - t0);
+    const bool tail_half = (n % 64) != 0 && t1 == ntiles;  // the last tile holds 32 valid rows
     const __bf16* dz = B.dzT[li + 1];  // dL/dz of layer li + 2
     const __bf16* h = B.hT[li];        // h of layer li + 1
-    f32x4 acc[4][4];
+    f32x4 acc[8][4];
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < 8; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // One k step is one 64-row tile, taken as two products of 32: lane (m, kg) loads the 16
-    // consecutive rows 16 kg .. 16 kg + 15 of its unit (32 bytes; the 64 lanes read 16 whole
-    // 128-byte rows of the tile) and gives rows 16 kg + e to the first product and 16 kg + 8 + e
-    // to the second. Both operands use the same order of the rows, which the sum over the rows
-    // does not see. The rows of a half-filled last tile (n is a multiple of 32) past n are
-    // zeroed in both operands. Operands are loaded kDwAhead steps before they are multiplied,
-    // in a ring of registers; every load is issued (past the last step it re-reads that
-    // step), so each step waits only for its own loads.
-    constexpr int kDwAhead = 2;
-    const int64_t nsteps = (b1 - b0 + 63) / 64;
-    if (nsteps <= 0) {
-        float* out = part + (int64_t)(li * kDwChunks + chunk) * kH * kH;
-        for (int i = threadIdx.x; i < 64 * kH; i += 256) out[cg * 64 * kH + i] = 0.0f;  // this group's slots
-        return;
-    }
-    bf16x8 af[kDwAhead][4][2], bfr[kDwAhead][4][2];
-    auto load = [&](int64_t q, bf16x8 (&a)[4][2], bf16x8 (&bb)[4][2]) {
-        const int64_t kk = b0 + 64 * q + 16 * lg;
+    // dL/db_L = sum_b dz_L[b] as the product with a column of ones: wave (wo, wk) takes unit
+    // blocks 2 wk and 2 wk + 1 of its 128 output units
+    f32x4 bacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    bf16x8 ones;
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-            const bf16x8* pa = reinterpret_cast<const bf16x8*>(dz + tm_index(16 * (4 * wave + mi) + lr, kk));
-            a[mi][0] = pa[0];
-            a[mi][1] = pa[1];
-        }
+    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)(lr == 0 ? 1.0f : 0.0f);
+    // fragments wave, wave + 8, ... of tile t0 + q into stage buf (each wave moves 8 of the 64)
+    auto issue = [&](int q, int buf) {
+        const int64_t tile = t0 + q;
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-            const bf16x8* pb = reinterpret_cast<const bf16x8*>(h + tm_index(64 * cg + 16 * ni + lr, kk));
-            bb[ni][0] = pb[0];
-            bb[ni][1] = pb[1];
+        for (int i = 0; i < 64 / kDwWaves; ++i) {
+            const int f = wave + kDwWaves * i, hh = f & 1, ub = (f >> 1) & 15;
+            const __bf16* src = ((f < 32) ? dz : h) + tile * (kH * 64) + (16 * ub + lr) * 64 + 16 * lg + 8 * hh;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                             (__attribute__((address_space(3))) void*)&stg[buf][f][0], 16, 0, 0);
         }
     };
-    const bool tail_half = (b1 - b0) % 64 != 0;  // the last step holds 32 valid rows
+    if (nsteps > 0) issue(0, 0);
+    for (int q = 0; q < nsteps; ++q) {
+        // this wave's loads of tile q are in; after the barrier every wave's are, and every wave
+        // is done with the other stage
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (q + 1 < nsteps) issue(q + 1, (q + 1) & 1);
+        const int buf = q & 1;
+        const bool zero_hi = tail_half && q == nsteps - 1 && lg >= 2;
 #pragma unroll
-    for (int q = 0; q < kDwAhead; ++q) load(std::min<int64_t>(q, nsteps - 1), af[q], bfr[q]);
-    for (int64_t s0 = 0; s0 < nsteps; s0 += kDwAhead) {
+        for (int hh = 0; hh < 2; ++hh) {
+            bf16x8 a[8], b[4];
 #pragma unroll
-        for (int q = 0; q < kDwAhead; ++q) {
-            if (s0 + q < nsteps) {
-                if (tail_half && s0 + q == nsteps - 1 && lg >= 2) {
+            for (int mi = 0; mi < 8; ++mi) a[mi] = stg[buf][(8 * wo + mi) * 2 + hh][lane];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+            for (int ni = 0; ni < 4; ++ni) b[ni] = stg[buf][32 + (4 * wk + ni) * 2 + hh][lane];
+            if (zero_hi) {
 #pragma unroll
-                        for (int hh = 0; hh < 2; ++hh) {
-                            af[q][i][hh] = bf16x8{};
-                            bfr[q][i][hh] = bf16x8{};
-                        }
-                }
+                for (int mi = 0; mi < 8; ++mi) a[mi] = bf16x8{};
 #pragma unroll
-                for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-                    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                        for (int ni = 0; ni < 4; ++ni)
-                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[q][mi][hh], bfr[q][ni][hh], acc[mi][ni], 0, 0, 0);
+                for (int ni = 0; ni < 4; ++ni) b[ni] = bf16x8{};
             }
-            load(std::min<int64_t>(s0 + q + kDwAhead, nsteps - 1), af[q], bfr[q]);
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 8; ++mi)  // (a uniform branch: no register indexed at run time)
+                if ((mi >> 1) == wk) bacc[mi & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mi], ones, bacc[mi & 1], 0, 0, 0);
         }
     }
-    // the accumulators as they are, 16 bytes per lane (dw_slot gives each one's place)
-    f32x4* out = reinterpret_cast<f32x4*>(part + (int64_t)(li * kDwChunks + chunk) * kH * kH) + (cg * 4 + wave) * 16 * 64;
+    // the accumulators as they are, 16 bytes per lane (dw_entry gives each one's place)
+    f32x4* out = reinterpret_cast<f32x4*>(part + (int64_t)(li * kDwParts + j) * kH * kH) + wave * 32 * 64;
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < 8; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) out[(mi * 4 + ni) * 64 + lane] = acc[mi][ni];
+    // bias parts after the weight parts: [layer][part][256]; column 0 of the products
+    if (lr == 0) {
+        float* bo = part + (int64_t)3 * kDwParts * kH * kH + (int64_t)(li * kDwParts + j) * kH;
+#pragma unroll
+        for (int q2 = 0; q2 < 2; ++q2)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bo[128 * wo + 16 * (2 * wk + q2) + 4 * lg + e] = bacc[q2][e];
+    }
 }
 
-// What train_dw leaves in slot j of a chunk's partial sums: j = (((cg 4 + wave) 16 + mi 4 + ni)
-// 64 + lane) 4 + e holds dL/dW[o][k] for output unit o = 16 (4 wave + mi) + 4 (lane / 16) + e
-// and input unit k = 64 cg + 16 ni + lane % 16; returns o kH + k.
+// What train_dw leaves in slot j of a part: j = (((wave 8 + mi) 4 + ni) 64 + lane) 4 + e holds
+// dL/dW[o][k] for output unit o = 128 (wave / 4) + 16 mi + 4 (lane / 16) + e and input unit
+// k = 64 (wave % 4) + 16 ni + lane % 16; returns o kH + k.
 __device__ __forceinline__ int dw_entry(int j) {
-    const int e = j % 4, lane = (j / 4) % 64, t = j / 256, mi = (t % 16) / 4, ni = t % 4, wave = (t / 16) % 4,
-              cg = t / 64;
-    return (16 * (4 * wave + mi) + 4 * (lane / 16) + e) * kH + 64 * cg + 16 * ni + lane % 16;
+    const int e = j % 4, lane = (j / 4) % 64, t = j / 256, ni = t % 4, mi = (t / 4) % 8, wave = t / 32;
+    return (128 * (wave / 4) + 16 * mi + 4 * (lane / 16) + e) * kH + 64 * (wave % 4) + 16 * ni + lane % 16;
 }
 
 __global__ void __launch_bounds__(256) train_dw_reduce(const float* __restrict__ part, float* __restrict__ G) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * kH * kH; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * kH * kH + 3 * kH;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i >= 3 * kH * kH) {  // dL/db2..b4
+            const int li = (int)((i - 3 * kH * kH) / kH), o = (int)((i - 3 * kH * kH) % kH);
+            const float* p = part + (int64_t)3 * kDwParts * kH * kH + (int64_t)li * kDwParts * kH + o;
+            float s = 0.0f;
+            for (int c = 0; c < kDwParts; ++c) s += p[(int64_t)c * kH];
+            G[(li == 0 ? kB2 : (li == 1 ? kB3 : kB4)) + o] = s;
+            continue;
+        }
         const int li = (int)(i / (kH * kH)), j = (int)(i % (kH * kH));
-        const float* p = part + (int64_t)li * kDwChunks * kH * kH + j;
+        const float* p = part + (int64_t)li * kDwParts * kH * kH + j;
         float s = 0.0f;
-        for (int c = 0; c < kDwChunks; ++c) s += p[(int64_t)c * kH * kH];
+        for (int c = 0; c < kDwParts; ++c) s += p[(int64_t)c * kH * kH];
         G[(li == 0 ? kW2 : (li == 1 ? kW3 : kW4)) + dw_entry(j)] = s;
     }
 }
@@ -1224,7 +1232,7 @@ struct kgrt_mlp {
     // (l = 1..3) and h_4, h[l] the gradients dL/dz_l (l = 1..4)
     __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr;
     float* dout = nullptr;
-    float* part = nullptr;   // weight-gradient partial sums [3][kDwChunks][256][256]
+    float* part = nullptr;   // weight- and bias-gradient partial sums [3][kDwParts][256 x 256], [3][kDwParts][256]
     float* spart = nullptr;  // the other gradients' partial sums: [5][chunks][256][16], then [chunks][8]
     int64_t step = 0;
     // render workspace (grown on demand): features, outputs, fallback list and its integration
@@ -1293,7 +1301,7 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
               hipMalloc(&m->Wt, kWtSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Pi, kPiSize * sizeof(float)) == hipSuccess &&
               hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess &&
-              hipMalloc(&m->part, (size_t)3 * kDwChunks * kH * kH * 4) == hipSuccess &&
+              hipMalloc(&m->part, (size_t)3 * kDwParts * (kH * kH + kH) * 4) == hipSuccess &&
               hipMalloc(&m->spart, (size_t)((max_batch + kSmChunk - 1) / kSmChunk) * (kSmTasks * kH * 16 + 8) * 4) == hipSuccess;
     for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess;
     for (int l = 2; ok && l <= 3; ++l) ok = hipMalloc(&m->z[l], hb) == hipSuccess;
@@ -1421,11 +1429,11 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     const int64_t nblk = (n + kTrRows - 1) / kTrRows;
     hipLaunchKernelGGL(train_rows, dim3((unsigned)std::min<int64_t>(nblk, (int64_t)ncu * per_cu)), dim3(kTrThreads), 0,
                        st, ta);
-    hipLaunchKernelGGL(train_dw, dim3(kDwBlocks), dim3(256), 0, st, tb, n, m->part);
+    hipLaunchKernelGGL(train_dw, dim3(3 * kDwParts), dim3(64 * kDwWaves), 0, st, tb, n, m->part);
     hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
     const int nsm = (int)((n + kSmChunk - 1) / kSmChunk);
     hipLaunchKernelGGL(train_small, dim3(nsm * kSmTasks), dim3(256), 0, st, x, idx, n, ta, m->spart);
-    hipLaunchKernelGGL(train_small_reduce, dim3((kSmVals * 8 + 255) / 256), dim3(256), 0, st, m->spart, nsm, m->G);
+    hipLaunchKernelGGL(train_small_reduce, dim3((kSmVals * 32 + 255) / 256), dim3(256), 0, st, m->spart, nsm, m->G);
     if (grads && hipMemcpyAsync(grads, m->G, kNumParams * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return mlp_fail(m, KGRT_E_HIP, "gradient copy failed");
     return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
