@@ -269,8 +269,8 @@ struct TrainBufs {
 //   backward: dh4 = dL/do W5 (both as hi + lo), dz_l = dh_l SiLU'(z_l),
 //     dh_{l-1} = dz_l W_l on MFMA with W_l^T fragments (l = 4..2), SiLU'(z1)
 //     recomputed from x.
-// h1..h4 and dz1..dz4 go to global memory tile-major (transposed through a
-// per-wave LDS scratch, 4 rows of one unit per lane), dL/do row-major: every
+// h1..h4 and dz1..dz4 go to global memory tile-major (transposed by a product
+// with the identity on MFMA, 4 rows of one unit per lane), dL/do row-major: every
 // sum over the batch (the weight and bias gradients) is taken by train_dw and
 // train_small over row chunks, with the chunks added in a fixed order, so a
 // step's gradient does not depend on the order blocks run in.
@@ -342,7 +342,6 @@ train_rows(const TrainRowsArgs A) {
     __shared__ bf16x8 wb[2][8 * 8 * 64];                // two half layers of fragments (2 x 64 KB)
     __shared__ bf16x8 w1l[16 * 64];                     // the input layer's fragments (16 KB)
     __shared__ __align__(16) float bl[4][kH];           // b1..b4
-    __shared__ __align__(16) __bf16 trs[kTrWaves][16 * 16];  // per-wave transposition scratch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     auto cat = [](const bf16x4& a, const bf16x4& b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); };
@@ -384,12 +383,18 @@ train_rows(const TrainRowsArgs A) {
     };
     static_assert(kTrWaves == 8, "each wave moves 8 of a half layer's 64 fragments");
     // lane (r, g) holds X[row r][unit 4g + e] of a 16-unit block; returns, for lane
-    // (u = r, q = g), X[rows 4q .. 4q + 3][unit u] (LDS operations of one wave run in order)
-    __bf16* const tr = trs[wave];
-    auto transpose = [&](const bf16x4& v) {
+    // (u = r, q = g), X[rows 4q .. 4q + 3][unit u]: the product X I on a 16x16x16 MFMA, with X
+    // as the A operand (lane (m, kg) holds A[m][4 kg + e]) and the identity as B, whose result
+    // lane (n, q) holds D[4q + e][n] = X[4q + e][n] (exact: one product by 1 per entry)
+    bf16x4 ident;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) tr[(4 * g + e) * 16 + r] = v[e];
-        return *reinterpret_cast<const bf16x4*>(tr + r * 16 + 4 * g);
+    for (int e = 0; e < 4; ++e) ident[e] = (__bf16)((g == (r >> 2) && e == (r & 3)) ? 1.0f : 0.0f);
+    auto transpose = [&](const bf16x4& v) {
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(v, ident, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        bf16x4 t;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (__bf16)d[e];
+        return t;
     };
     float lacc = 0.0f;
     const int64_t nblk = (A.n + kTrRows - 1) / kTrRows;
