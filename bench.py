@@ -58,19 +58,19 @@ FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "cali
 # VALU lane utilisation of the dominant kernel (useful FP64 FLOPs / FP64 lane
 # slots issued, rocprofv3 counters), valid for the sources it was taken on; see
 # profiles/trace_kernel_flop_calibration.md.
-HEAD_MD5 = "c21d37cde6fe44fd59c7a302ef379bf2"
+HEAD_MD5 = "acdbbeb3d6d2a8aaac5b19bae98ba4a8"
 LANE_UTILISATION = {"torus": {"value": 0.876, "source_md5": HEAD_MD5},
                     "batch": {"value": 0.892, "source_md5": HEAD_MD5},
                     "thin_disk": {"value": 0.860, "source_md5": HEAD_MD5},
                     "grid": {"value": 0.874, "source_md5": HEAD_MD5}}
 
-TRAFFIC = {"torus": {"bytes": 491315418, "source_md5": HEAD_MD5},
+TRAFFIC = {"torus": {"bytes": 490904853, "source_md5": HEAD_MD5},
            # the one launch of the 256-image plan, see profiles/batch256_trace_kernel_traffic.md
-           "batch": {"bytes": 22642143527, "source_md5": HEAD_MD5},
+           "batch": {"bytes": 22646623373, "source_md5": HEAD_MD5},
            # the 1024^2 thin-disk image, see profiles/trace_kernel_flop_calibration.md
-           "thin_disk": {"bytes": 1022158373, "source_md5": HEAD_MD5},
+           "thin_disk": {"bytes": 1019623193, "source_md5": HEAD_MD5},
            # the 1024^2 image of the gridded snapshot, see profiles/grid_1024_kernel_trace.md
-           "grid": {"bytes": 13355692746, "source_md5": HEAD_MD5}}
+           "grid": {"bytes": 13397072956, "source_md5": HEAD_MD5}}
 
 
 def kernel_source_md5() -> str:

@@ -261,11 +261,13 @@ int64_t kgrt_plan_num_rays(const kgrt_plan* plan);
  * and replayed; a new capture happens when the output pointers or the launch
  * shape change. Two launches of one plan must not overlap in time. */
 int kgrt_plan_launch(kgrt_plan* plan, const kgrt_outputs* out, uint32_t flags, void* stream);
-/* Times candidate launch shapes (block 64/128/256; residency: the occupancy
- * rule, two or three waves per SIMD; refill granularity 1 or 16) on the plan's
- * first <= 524288 rays (at the residency the whole plan would get) and keeps the fastest for
- * later launches; writes it to *best if best != NULL. Synchronous: it waits
- * for `stream`. Outputs of the sampled rays are overwritten. */
+/* Times candidate launch shapes on the plan's first <= 524288 rays: the
+ * persistent kernel (many rays per lane) at block 64/128/256, residency (the
+ * occupancy rule, decided on the whole plan, or two or three waves per SIMD)
+ * and refill granularity 1 or 16, and one ray per thread at block 64/128/256.
+ * The fastest is kept for later launches and written to *best if best !=
+ * NULL. Synchronous: it waits for `stream`. Outputs of the sampled rays are
+ * overwritten. */
 int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, kgrt_launch* best);
 /* Sets the plan's launch shape explicitly (NULL = context default). */
 int kgrt_plan_set_launch(kgrt_plan* plan, const kgrt_launch* launch);

@@ -1338,31 +1338,34 @@ int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, k
     kgrt_launch winner = base;
     float best_ms = 1e30f;
     int rc = KGRT_OK;
+    // candidates: the persistent kernel (many rays per lane, refilled from the queue) at every
+    // block size, residency and refill granularity, and one ray per thread (a lane traces a
+    // single ray) at every block size
+    std::vector<kgrt_launch> cand;
     for (int block : {64, 128, 256}) {
         // blocks per CU: the occupancy rule (0), then two and three waves per SIMD explicitly
         const int waves2 = std::max(1, 2 * 4 * 64 / block), waves3 = std::max(1, 3 * 4 * 64 / block);
-        for (int per_cu : {0, waves2, waves3}) {
-            for (int refill : {1, 16}) {
-                plan->launch = kgrt_launch{block, per_cu, refill, KGRT_LAUNCH_PERSISTENT};
-                rc = plan_enqueue(plan, out, st, sample);  // warm-up
-                if (rc != KGRT_OK) break;
-                (void)hipEventRecord(e0, st);
-                rc = plan_enqueue(plan, out, st, sample);
-                (void)hipEventRecord(e1, st);
-                if (rc != KGRT_OK || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = (rc != KGRT_OK) ? rc : fail(ctx, KGRT_E_HIP, "autotune timing failed");
-                    break;
-                }
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    winner = plan->launch;
-                }
-            }
-            if (rc != KGRT_OK) break;
-        }
+        for (int per_cu : {0, waves2, waves3})
+            for (int refill : {1, 16}) cand.push_back(kgrt_launch{block, per_cu, refill, KGRT_LAUNCH_PERSISTENT});
+        cand.push_back(kgrt_launch{block, 0, 1, KGRT_LAUNCH_ONE_RAY_PER_THREAD});
+    }
+    for (const kgrt_launch& c : cand) {
+        plan->launch = c;
+        rc = plan_enqueue(plan, out, st, sample);  // warm-up
         if (rc != KGRT_OK) break;
+        (void)hipEventRecord(e0, st);
+        rc = plan_enqueue(plan, out, st, sample);
+        (void)hipEventRecord(e1, st);
+        if (rc != KGRT_OK || hipEventSynchronize(e1) != hipSuccess) {
+            rc = (rc != KGRT_OK) ? rc : fail(ctx, KGRT_E_HIP, "autotune timing failed");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            winner = plan->launch;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
