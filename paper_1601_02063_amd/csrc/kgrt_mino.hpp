@@ -27,7 +27,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kgrt_device.hpp"
+
 namespace kgrt_mino {
+
+// 1/sqrt(x), x > 0, to about an ulp: the hardware seed and two Newton steps (kgrt::fm::rsqrt)
+__device__ __forceinline__ double rsq(double x) { return kgrt::fm::rsqrt(x); }
 
 // 32-point Gauss-Legendre rule on [0, 1]: the 16 nodes below 1/2 (the others
 // are 1 - t) and their weights, from csrc/gen_gauss_legendre.py (mpmath).
@@ -98,7 +103,7 @@ __device__ inline double j_tp(const Quartic& q, double utp, double ux) {
         const double ua = fma(-d * ta, ta, utp), ub = fma(-d * tb, tb, utp);
         const double qa = fma(fma(fma(b3, ua, b2), ua, b1), ua, b0);
         const double qb = fma(fma(fma(b3, ub, b2), ub, b1), ub, b0);
-        acc = fma(kGlW[k], 1.0 / sqrt(-qa) + 1.0 / sqrt(-qb), acc);
+        acc = fma(kGlW[k], rsq(-qa) + rsq(-qb), acc);
     }
     return 2.0 * sqrt(d) * acc;
 }
@@ -106,7 +111,7 @@ __device__ inline double j_tp(const Quartic& q, double utp, double ux) {
 // dJ/ds at s = sqrt(utp - u): 2 / sqrt(-q3(u))
 __device__ inline double dj_ds(const Quartic& q, double utp, double u) {
     const double b3 = q.k4, b2 = fma(utp, b3, q.k3), b1 = fma(utp, b2, q.k2), b0 = utp * b1;
-    return 2.0 / sqrt(-fma(fma(fma(b3, u, b2), u, b1), u, b0));
+    return 2.0 * rsq(-fma(fma(fma(b3, u, b2), u, b1), u, b0));
 }
 
 // int_{u0}^{u1} du / sqrt(P(u)) where P > 0 (no turning point).
@@ -115,7 +120,7 @@ __device__ inline double k_direct(const Quartic& q, double u0, double u1) {
     double acc = 0.0;
 #pragma unroll 4
     for (int k = 0; k < 16; ++k) {
-        acc = fma(kGlW[k], 1.0 / sqrt(q.P(fma(d, kGlT[k], u0))) + 1.0 / sqrt(q.P(fma(d, 1.0 - kGlT[k], u0))), acc);
+        acc = fma(kGlW[k], rsq(q.P(fma(d, kGlT[k], u0))) + rsq(q.P(fma(d, 1.0 - kGlT[k], u0))), acc);
     }
     return d * acc;
 }
