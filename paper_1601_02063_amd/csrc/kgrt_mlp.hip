@@ -9,7 +9,7 @@
 // activations in registers through all layers, and the weights come as MFMA
 // fragments in a permuted order that lets one layer's accumulators serve as
 // the next layer's operand directly. Training runs the forward and backward
-// of every row in the same form (train_rows), stores the per-sample arrays
+// of every row in one kernel (train_cols), stores the per-sample arrays
 // tile-major, and takes the gradient products that contract over the batch
 // in separate kernels (train_dw, train_small) over row ranges added in a
 // fixed order.
@@ -250,30 +250,21 @@ struct TrainBufs {
     __bf16* dzT[4];  // dL/dz of layers 1..4
 };
 
-// ------------------------------------------ row-parallel fused training
-// Forward and backward of one 16-row tile per wave in one kernel, in the form
-// of the inference kernel: a layer's activations stay in the wave's
-// registers (the MFMA result of a 16-unit block, lane (r, g) holding units
-// 4g..4g+3 of row r, is a quarter of the next product's B operand once the
-// weights are stored in permuted fragment order). A hidden layer's weight
-// fragments reach LDS in two halves of 64 KB by direct global-to-LDS loads,
-// double-buffered: the next half loads while the waves multiply with the
-// other, and a barrier per half layer is the only one between the waves. Per tile:
+// ------------------------------------------ fused training pass
+// Forward and backward of every row in one kernel (train_cols below):
 //   forward: z1 = W1 x + b1 (FP32 operands as BF16 hi + lo parts), then
-//     z_l = W_l h_{l-1} + b_l (l = 2..4, BF16 x BF16, FP32 accumulation);
-//     h_l = SiLU(z_l) stays in registers, SiLU'(z_l) (BF16) too for layer 4
-//     and, for layers 2 and 3, goes to global memory in the accumulator
-//     layout (8 bytes per lane and unit block, read back by the same lane;
-//     the registers would not hold it); the head o = W5 h4 + b5 (W5 as
-//     hi + lo), the loss and dL/do;
+//     z_l = W_l h_{l-1} + b_l (l = 2..4, BF16 x BF16, FP32 accumulation),
+//     h_l = SiLU(z_l); SiLU'(z_l) (BF16) kept for the backward: layers 2 and 3
+//     in global memory in the accumulator layout, layer 4 in registers; the
+//     head o = W5 h4 + b5 (W5 as hi + lo), the loss and dL/do;
 //   backward: dh4 = dL/do W5 (both as hi + lo), dz_l = dh_l SiLU'(z_l),
 //     dh_{l-1} = dz_l W_l on MFMA with W_l^T fragments (l = 4..2), SiLU'(z1)
 //     recomputed from x.
 // h1..h4 and dz1..dz4 go to global memory tile-major (transposed by a product
 // with the identity on MFMA, 4 rows of one unit per lane), dL/do row-major: every
 // sum over the batch (the weight and bias gradients) is taken by train_dw and
-// train_small over row chunks, with the chunks added in a fixed order, so a
-// step's gradient does not depend on the order blocks run in.
+// train_small over row ranges, added in a fixed order, so a step's gradient
+// does not depend on the order blocks run in.
 //
 // Training fragment array Wt (BF16, 1 KB fragments, unscaled weights):
 //   W1 hi + lo [jb 16][lane][8] (as the inference kernel's input layer);
@@ -284,7 +275,6 @@ struct TrainBufs {
 // The forward hidden fragments are the inference kernel's (Wr, unscaled).
 constexpr int64_t kWtW1 = 0, kWtW5 = kWtW1 + 16 * kWrFrag, kWtW5T = kWtW5 + 16 * kWrFrag;
 constexpr int64_t kWtBwd = kWtW5T + 32 * kWrFrag, kWtSize = kWtBwd + 3 * 16 * 8 * kWrFrag;
-constexpr int kTrWaves = 8, kTrThreads = 64 * kTrWaves, kTrRows = 16 * kTrWaves;
 
 __global__ void __launch_bounds__(256) pack_train(const float* __restrict__ P, __bf16* __restrict__ Wt) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kWtSize; i += (int64_t)gridDim.x * blockDim.x) {
@@ -337,55 +327,33 @@ struct TrainRowsArgs {
     float inv_n;
 };
 
-__global__ void __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-train_rows(const TrainRowsArgs A) {
-    __shared__ bf16x8 wb[2][8 * 8 * 64];                // two half layers of fragments (2 x 64 KB)
-    __shared__ bf16x8 w1l[16 * 64];                     // the input layer's fragments (16 KB)
-    __shared__ __align__(16) float bl[4][kH];           // b1..b4
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// ------------------------------------------ column-parallel fused training
+// Forward and backward of a block of 128 rows (8 tiles of 16) by 8 waves, wave w
+// owning unit blocks 2w and 2w + 1 (32 units) of every layer: its 16 weight
+// fragments of a layer sit in its registers and the layer's input activations,
+// all 256 units of the block's rows, in LDS, where every wave reads them as MFMA
+// B operands (one 1 KB read serves both unit blocks). Each layer's output goes
+// back to LDS in the position order that makes a contiguous 16-byte read the
+// permuted k-step operand of the fragments above (unit block 2s + b, lane group
+// g at positions 32 s + 8 g + 4 b .. + 3), so the same fragment arrays serve the
+// row-parallel inference kernel. h and dz leave for HBM tile-major (transposed
+// by a product with the identity), SiLU'(z2), SiLU'(z3) in the accumulator
+// layout; SiLU'(z4) stays in registers.
+constexpr int kTcWaves = 8, kTcThreads = 64 * kTcWaves, kTcRows = 128, kTcPitch = 256;
+__global__ void __launch_bounds__(kTcThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+train_cols(const TrainRowsArgs A) {
+    __shared__ __align__(16) __bf16 act[2][kTcRows * kTcPitch];  // two activation buffers (2 x 66 KB)
+    __shared__ __align__(16) f32x4 bl[4][kH / 4];                // b1..b4
+    __shared__ __align__(16) f32x4 xs[kTcRows];                  // the block's x rows
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = lane & 15, g = lane >> 4;
-    auto cat = [](const bf16x4& a, const bf16x4& b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); };
     auto mfma = [](bf16x8 a, bf16x8 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); };
-    const float* Pp = A.P;
-    for (int i = tid; i < 4 * kH; i += kTrThreads) {
-        const int L = i / kH;
-        bl[L][i % kH] = Pp[(L == 0 ? kB1 : (L == 1 ? kB2 : (L == 2 ? kB3 : kB4))) + i % kH];
+    for (int i = tid; i < kH; i += kTcThreads) {
+        const int L = i / (kH / 4), q = i % (kH / 4);
+        const int64_t off = (L == 0 ? kB1 : (L == 1 ? kB2 : (L == 2 ? kB3 : kB4))) + 4 * q;
+        bl[L][q] = f32x4{A.P[off], A.P[off + 1], A.P[off + 2], A.P[off + 3]};
     }
-    for (int i = tid; i < 16 * 64; i += kTrThreads) w1l[i] = reinterpret_cast<const bf16x8*>(A.Wt)[kWtW1 / 8 + i];
-    // bias of layer L + 1 for the units lane group g holds in unit block jb
-    auto bias = [&](int L, int jb) { return *reinterpret_cast<const f32x4*>(&bl[L][16 * jb + 4 * g]); };
-    // the eight weight fragments of unit block jb, all read before the products that use them
-    // (jb 0..7 from the first half buffer, 8..15 from the second)
-    auto frags = [&](int jb, bf16x8 (&w)[8]) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) w[s] = wb[jb >> 3][((jb & 7) * 8 + s) * 64 + lane];
-    };
-    // The six hidden-layer fragment sets a block of rows uses, in order: forward W2..W4
-    // (lam = 0..2), backward W4^T..W2^T (lam = 3..5). Each set goes to LDS in two halves
-    // (unit blocks 0..7 and 8..15, 64 KB each) by direct global-to-LDS loads: one half
-    // loads while the other is in use. issue() starts half h of set lam (each wave moves 8
-    // fragments of 1 KB); half_barrier() waits for the wave's own loads, then for every wave,
-    // so the half just loaded is complete and the other buffer is free.
-    typedef const __attribute__((address_space(1))) bf16x8 GW;
-    auto issue = [&](int lam, int h) {
-        GW* set = (lam < 3) ? (GW*)A.Wr + kWrHid / 8 + lam * (16 * 8 * 64)
-                            : (GW*)A.Wt + kWtBwd / 8 + (5 - lam) * (16 * 8 * 64);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int f = wave + kTrWaves * i;  // fragment of the half
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(set + (h * 64 + f) * 64 + lane),
-                                             (__attribute__((address_space(3))) void*)&wb[h][f * 64], 16, 0, 0);
-        }
-    };
-    auto half_barrier = [&]() {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-    };
-    static_assert(kTrWaves == 8, "each wave moves 8 of a half layer's 64 fragments");
-    // lane (r, g) holds X[row r][unit 4g + e] of a 16-unit block; returns, for lane
-    // (u = r, q = g), X[rows 4q .. 4q + 3][unit u]: the product X I on a 16x16x16 MFMA, with X
-    // as the A operand (lane (m, kg) holds A[m][4 kg + e]) and the identity as B, whose result
-    // lane (n, q) holds D[4q + e][n] = X[4q + e][n] (exact: one product by 1 per entry)
+    // the identity as a 16x16x16 B operand: X I with X as A lands as X^T in the accumulator layout
     bf16x4 ident;
 #pragma unroll
     for (int e = 0; e < 4; ++e) ident[e] = (__bf16)((g == (r >> 2) && e == (r & 3)) ? 1.0f : 0.0f);
@@ -396,173 +364,257 @@ train_rows(const TrainRowsArgs A) {
         for (int e = 0; e < 4; ++e) t[e] = (__bf16)d[e];
         return t;
     };
+    typedef const __attribute__((address_space(1))) bf16x8 GW;
     float lacc = 0.0f;
-    const int64_t nblk = (A.n + kTrRows - 1) / kTrRows;
-    if (blockIdx.x < nblk) issue(0, 0);
-    __syncthreads();  // b1..b4 and the input layer's fragments staged
+    const int64_t nblk = (A.n + kTcRows - 1) / kTcRows;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const bool more = blk + gridDim.x < nblk;  // another block of rows follows
-        // fragment and parameter pointers opaque per block of rows, so their loads are not hoisted
         GW* Wr = (GW*)A.Wr;
         GW* Wt = (GW*)A.Wt;
+        const float* Pp = A.P;
         asm volatile("" : "+s"(Wr), "+s"(Wt), "+s"(Pp));
-        // this wave's 16 rows: n is a multiple of 32, so a tile is all valid or all beyond n
-        const int64_t row0 = __builtin_amdgcn_readfirstlane((int)(blk * kTrRows + 16 * wave));
-        const bool tile_ok = row0 < A.n;
-        const int64_t row = row0 + r;
-        const int64_t src = tile_ok ? (A.idx ? (int64_t)A.idx[row] : row) : 0;
-        f32x4 xv = {0.f, 0.f, 0.f, 0.f};
-        if (tile_ok && g <= 1) xv = *reinterpret_cast<const f32x4*>(A.x + src * kIn);
-        bf16x8 xf;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const __bf16 hi = (__bf16)xv[c];
-            xf[c] = hi;
-            xf[4 + c] = (g == 0) ? (__bf16)(xv[c] - (float)hi) : (__bf16)0.0f;
+        const int64_t row0 = blk * kTcRows;
+        const int ntile = (int)std::min<int64_t>(8, (A.n - row0) / 16);  // n is a multiple of 32
+        __syncthreads();  // the previous block of rows is done with LDS
+        if (tid < kTcRows) {
+            f32x4 xv = {0.f, 0.f, 0.f, 0.f};
+            if (row0 + tid < A.n) {
+                const int64_t src = A.idx ? (int64_t)A.idx[row0 + tid] : row0 + tid;
+                xv = *reinterpret_cast<const f32x4*>(A.x + src * kIn);
+            }
+            xs[tid] = xv;
         }
-        // the tile's h_l or dz_l, transposed, to a tile-major array (4 rows per lane)
-        const int64_t tmo = tm_index(r, row0 + 4 * g);
-        auto store_t = [&](const bf16x4& v, __bf16* dst, int jb) {
-            const bf16x4 vt = transpose(v);
-            if (tile_ok) *reinterpret_cast<bf16x4*>(dst + tmo + 16 * 64 * jb) = vt;
+        __syncthreads();
+        // B operand of the input layer for tile t (hi + lo parts of x, see pack_train)
+        auto xfrag = [&](int t) {
+            const f32x4 xv = xs[16 * t + r];
+            bf16x8 f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const __bf16 hi = (__bf16)xv[c];
+                f[c] = (g <= 1) ? hi : (__bf16)0.0f;
+                f[4 + c] = (g == 0) ? (__bf16)(xv[c] - (float)hi) : (__bf16)0.0f;
+            }
+            return f;
         };
-        // SiLU'(z) of this wave's tile, layers 2 and 3, in the accumulator layout
-        const int64_t spo = ((row0 >> 4) * 16 * 64 + lane) * 4;
-        // ---------------- forward
-        bf16x4 act[16], nxt[16], sp4[16];
+        // LDS: the 16-byte k-step operand (tile t, step s) and the 8-byte result of unit block jb.
+        // A row's 32 chunks of 16 bytes are stored with the chunk index XORed with the row's
+        // index in its tile, so the 16 rows of a tile that one read instruction touches at the
+        // same chunk land in different banks.
+        auto ldsB = [&](const __bf16* buf, int t, int s) {
+            return *reinterpret_cast<const bf16x8*>(buf + (16 * t + r) * kTcPitch + 8 * ((4 * s + g) ^ r));
+        };
+        auto ldsW = [&](__bf16* buf, int t, int jb, const bf16x4& v) {
+            *reinterpret_cast<bf16x4*>(buf + (16 * t + r) * kTcPitch + 8 * ((4 * (jb >> 1) + g) ^ r) + 4 * (jb & 1)) = v;
+        };
+        // HBM: tile t's values of unit block jb, transposed, to a tile-major array
+        auto store_t = [&](const bf16x4& v, __bf16* dst, int t, int jb) {
+            const bf16x4 vt = transpose(v);
+            *reinterpret_cast<bf16x4*>(dst + tm_index(16 * jb + r, row0 + 16 * t + 4 * g)) = vt;
+        };
+        auto sp_ptr = [&](__bf16* arr, int t, int jb) {
+            return reinterpret_cast<bf16x4*>(arr + ((row0 + 16 * t) >> 4) * (16 * 64 * 4) + (jb * 64 + lane) * 4);
+        };
+        const int jb0 = 2 * wave;  // this wave's unit blocks jb0, jb0 + 1
+        // ---------------- input layer: h1 = SiLU(W1 x + b1)
+        {
+            const bf16x8 w1[2] = {Wt[kWtW1 / 8 + jb0 * 64 + lane], Wt[kWtW1 / 8 + (jb0 + 1) * 64 + lane]};
+            const f32x4 b1[2] = {bl[0][4 * jb0 + g], bl[0][4 * (jb0 + 1) + g]};
+            for (int t = 0; t < ntile; ++t) {
+                const bf16x8 xf = xfrag(t);
 #pragma unroll
-        for (int jb = 0; jb < 16; ++jb) {
-            const f32x4 z = mfma(w1l[jb * 64 + lane], xf, bias(0, jb));
+                for (int u = 0; u < 2; ++u) {
+                    const f32x4 z = mfma(w1[u], xf, b1[u]);
+                    bf16x4 h;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) act[jb][e] = (__bf16)(z[e] * sigmoidf_(z[e]));
-            store_t(act[jb], A.hT[0], jb);
+                    for (int e = 0; e < 4; ++e) h[e] = (__bf16)(z[e] * sigmoidf_(z[e]));
+                    ldsW(act[0], t, jb0 + u, h);
+                    store_t(h, A.hT[0], t, jb0 + u);
+                }
+            }
         }
+        __syncthreads();
+        // ---------------- hidden layers W2..W4: act[l % 2] -> act[(l + 1) % 2]
+        bf16x4 sp4[8][2];
 #pragma unroll 1
         for (int l = 0; l < 3; ++l) {
-            asm volatile("" : "+s"(Wr), "+s"(Pp));  // no loads hoisted out of this loop
-            half_barrier();  // first half of set l in; second buffer free
-            issue(l, 1);
-            __bf16* spdst = A.spF[l < 2 ? l : 0] + spo;
+            asm volatile("" : "+s"(Wr));
+            bf16x8 w[2][8];
 #pragma unroll
-            for (int jb = 0; jb < 16; ++jb) {
-                if (jb == 8) {
-                    half_barrier();  // second half in; first buffer free
-                    issue(l + 1, 0);
-                }
-                bf16x8 w[8];
-                frags(jb, w);
-                f32x4 z = bias(l + 1, jb);
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int s = 0; s < 8; ++s) z = mfma(w[s], cat(act[2 * s], act[2 * s + 1]), z);
-                bf16x4 spv;
+                for (int s = 0; s < 8; ++s) w[u][s] = Wr[kWrHid / 8 + l * (16 * 8 * 64) + ((jb0 + u) * 8 + s) * 64 + lane];
+            const f32x4 bb[2] = {bl[l + 1][4 * jb0 + g], bl[l + 1][4 * (jb0 + 1) + g]};
+            const __bf16* in = act[l & 1];
+            __bf16* out = act[(l + 1) & 1];
+            // two tiles at a time: four independent accumulator chains (ntile is even)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float sg = sigmoidf_(z[e]);
-                    nxt[jb][e] = (__bf16)(z[e] * sg);
-                    spv[e] = (__bf16)(sg * (1.0f + z[e] * (1.0f - sg)));
-                }
-                if (l == 2) sp4[jb] = spv;
-                else if (tile_ok) *reinterpret_cast<bf16x4*>(spdst + jb * 64 * 4) = spv;
-                store_t(nxt[jb], A.hT[l + 1], jb);
-            }
+            for (int t0 = 0; t0 < 8; t0 += 2) {
+                if (t0 >= ntile) break;
+                f32x4 z[2][2] = {{bb[0], bb[1]}, {bb[0], bb[1]}};
 #pragma unroll
-            for (int jb = 0; jb < 16; ++jb) act[jb] = nxt[jb];
-        }
-        asm volatile("" : "+s"(Wt), "+s"(Pp));
-        // ---------------- head, loss, dL/do (lane (r, 0): outputs 0..3, lane (r, 1): output 4)
-        f32x4 o = {0.f, 0.f, 0.f, 0.f};
+                for (int s = 0; s < 8; ++s) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const bf16x8 hv = cat(act[2 * s], act[2 * s + 1]);
-            o = mfma(Wt[kWtW5 / 8 + (2 * s) * 64 + lane], hv, o);
-            o = mfma(Wt[kWtW5 / 8 + (2 * s + 1) * 64 + lane], hv, o);
-        }
-        f32x4 d = {0.f, 0.f, 0.f, 0.f};
-        if (tile_ok && g <= 1) {
-            const float* tt = A.t + src * 6;
-            const float m = tt[5];
-            if (g == 0) {
-                const float o0 = o[0] + Pp[kB5], o1 = o[1] + Pp[kB5 + 1], o2 = o[2] + Pp[kB5 + 2], o3 = o[3] + Pp[kB5 + 3];
-                const float cap = tt[0];
-                const float sp = (o0 > 0.0f) ? o0 + log1pf(__expf(-o0)) : log1pf(__expf(o0));
-                const float e1 = o1 - tt[1], e2 = o2 - tt[2], e3 = o3 - tt[3];
-                lacc += kWCap * (sp - cap * o0) + kWLogR * e1 * e1 + kWG * e2 * e2 + kWPhi * m * e3 * e3;
-                d[0] = kWCap * (sigmoidf_(o0) - cap) * A.inv_n;
-                d[1] = 2.0f * kWLogR * e1 * A.inv_n;
-                d[2] = 2.0f * kWG * e2 * A.inv_n;
-                d[3] = 2.0f * kWPhi * m * e3 * A.inv_n;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) A.dout[row * kOut + e] = d[e];
-            } else {
-                const float e4 = o[0] + Pp[kB5 + 4] - tt[4];
-                lacc += kWPhi * m * e4 * e4;
-                d[0] = 2.0f * kWPhi * m * e4 * A.inv_n;
-                A.dout[row * kOut + 4] = d[0];
-            }
-        }
-        // B operands of dh4 = dL/do W5: lane (r, 0) holds dL/do of row r (hi and lo parts);
-        // output 4 comes from lane (r, 1)
-        const float d4 = __shfl(d[0], r + 16);
-        bf16x8 dhi, dlo;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = (g == 0 && e < kOut) ? (e < 4 ? d[e] : d4) : 0.0f;
-            const __bf16 hi = (__bf16)v;
-            dhi[e] = hi;
-            dlo[e] = (__bf16)(v - (float)hi);
-        }
-        // ---------------- backward
-        asm volatile("" : "+s"(Wt), "+s"(Pp));
-        bf16x4 dz[16], ndz[16];
-        // dz4 = (dL/do W5) SiLU'(z4)
-#pragma unroll
-        for (int jb = 0; jb < 16; ++jb) {
-            const bf16x8 wh = Wt[kWtW5T / 8 + (2 * jb) * 64 + lane], wo = Wt[kWtW5T / 8 + (2 * jb + 1) * 64 + lane];
-            f32x4 h = mfma(wh, dhi, f32x4{0.f, 0.f, 0.f, 0.f});
-            h = mfma(wo, dhi, h);
-            h = mfma(wh, dlo, h);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) dz[jb][e] = (__bf16)(h[e] * (float)sp4[jb][e]);
-            store_t(dz[jb], A.dzT[3], jb);
-        }
-        // dh_{L-1} = dz_L W_L for L = 4, 3, 2 (fragment set li = L - 2), dz_{L-1} = dh_{L-1} SiLU'(z_{L-1})
-#pragma unroll 1
-        for (int li = 2; li >= 0; --li) {
-            asm volatile("" : "+s"(Wt), "+s"(Pp));  // no loads hoisted out of this loop
-            const int lam = 5 - li;
-            half_barrier();
-            issue(lam, 1);
-            const __bf16* spsrc = A.spF[li > 0 ? li - 1 : 0] + spo;
-#pragma unroll
-            for (int jb = 0; jb < 16; ++jb) {
-                if (jb == 8) {
-                    half_barrier();
-                    if (lam < 5) issue(lam + 1, 0);
-                    else if (more) issue(0, 0);  // the next block of rows' first set
-                }
-                bf16x8 w[8];
-                frags(jb, w);
-                f32x4 h = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 8; ++s) h = mfma(w[s], cat(dz[2 * s], dz[2 * s + 1]), h);
-                bf16x4 spv;
-                if (li > 0) {
-                    spv = *reinterpret_cast<const bf16x4*>(spsrc + jb * 64 * 4);
-                } else {
-                    // layer 1: SiLU'(z1) recomputed from x
-                    const f32x4 z = mfma(w1l[jb * 64 + lane], xf, bias(0, jb));
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float sg = sigmoidf_(z[e]);
-                        spv[e] = (__bf16)(sg * (1.0f + z[e] * (1.0f - sg)));
+                    for (int q = 0; q < 2; ++q) {
+                        const bf16x8 b = ldsB(in, t0 + q, s);
+                        z[q][0] = mfma(w[0][s], b, z[q][0]);
+                        z[q][1] = mfma(w[1][s], b, z[q][1]);
                     }
                 }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ndz[jb][e] = (__bf16)(h[e] * (float)spv[e]);
-                store_t(ndz[jb], A.dzT[li], jb);
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int t = t0 + q;
+                        bf16x4 h, spv;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float sg = sigmoidf_(z[q][u][e]);
+                            h[e] = (__bf16)(z[q][u][e] * sg);
+                            spv[e] = (__bf16)(sg * (1.0f + z[q][u][e] * (1.0f - sg)));
+                        }
+                        if (l == 2) sp4[t][u] = spv;
+                        else *sp_ptr(A.spF[l], t, jb0 + u) = spv;
+                        ldsW(out, t, jb0 + u, h);
+                        store_t(h, A.hT[l + 1], t, jb0 + u);
+                    }
+            }
+            __syncthreads();
+        }
+        // ---------------- head (wave w: tile w), loss, dL/do; h4 is in act[1]
+        __bf16* const dfr = act[0];  // dL/do operands of the 8 tiles (hi, lo), 16 KB
+        if (wave < ntile) {
+            const int t = wave;
+            f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const bf16x8 hv = ldsB(act[1], t, s);
+                o = mfma(Wt[kWtW5 / 8 + (2 * s) * 64 + lane], hv, o);
+                o = mfma(Wt[kWtW5 / 8 + (2 * s + 1) * 64 + lane], hv, o);
+            }
+            const int64_t row = row0 + 16 * t + r;
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+            if (g <= 1) {
+                const int64_t src = A.idx ? (int64_t)A.idx[row] : row;
+                const float* tt = A.t + src * 6;
+                const float m = tt[5];
+                if (g == 0) {
+                    const float o0 = o[0] + Pp[kB5], o1 = o[1] + Pp[kB5 + 1], o2 = o[2] + Pp[kB5 + 2], o3 = o[3] + Pp[kB5 + 3];
+                    const float cap = tt[0];
+                    const float sp = (o0 > 0.0f) ? o0 + log1pf(__expf(-o0)) : log1pf(__expf(o0));
+                    const float e1 = o1 - tt[1], e2 = o2 - tt[2], e3 = o3 - tt[3];
+                    lacc += kWCap * (sp - cap * o0) + kWLogR * e1 * e1 + kWG * e2 * e2 + kWPhi * m * e3 * e3;
+                    d[0] = kWCap * (sigmoidf_(o0) - cap) * A.inv_n;
+                    d[1] = 2.0f * kWLogR * e1 * A.inv_n;
+                    d[2] = 2.0f * kWG * e2 * A.inv_n;
+                    d[3] = 2.0f * kWPhi * m * e3 * A.inv_n;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) A.dout[row * kOut + e] = d[e];
+                } else {
+                    const float e4 = o[0] + Pp[kB5 + 4] - tt[4];
+                    lacc += kWPhi * m * e4 * e4;
+                    d[0] = 2.0f * kWPhi * m * e4 * A.inv_n;
+                    A.dout[row * kOut + 4] = d[0];
+                }
+            }
+            // B operands of dh4 = dL/do W5: lane (r, 0) holds dL/do of row r (hi and lo parts)
+            const float d4 = __shfl(d[0], r + 16);
+            bf16x8 dhi, dlo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = (g == 0 && e < kOut) ? (e < 4 ? d[e] : d4) : 0.0f;
+                const __bf16 hi = (__bf16)v;
+                dhi[e] = hi;
+                dlo[e] = (__bf16)(v - (float)hi);
+            }
+            reinterpret_cast<bf16x8*>(dfr)[(2 * t) * 64 + lane] = dhi;
+            reinterpret_cast<bf16x8*>(dfr)[(2 * t + 1) * 64 + lane] = dlo;
+        }
+        __syncthreads();
+        // ---------------- dz4 = (dL/do W5) SiLU'(z4) -> act[1]
+        {
+            const bf16x8 wh[2] = {Wt[kWtW5T / 8 + (2 * jb0) * 64 + lane], Wt[kWtW5T / 8 + (2 * (jb0 + 1)) * 64 + lane]};
+            const bf16x8 wo[2] = {Wt[kWtW5T / 8 + (2 * jb0 + 1) * 64 + lane], Wt[kWtW5T / 8 + (2 * (jb0 + 1) + 1) * 64 + lane]};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t >= ntile) break;
+                const bf16x8 dhi = reinterpret_cast<const bf16x8*>(dfr)[(2 * t) * 64 + lane];
+                const bf16x8 dlo = reinterpret_cast<const bf16x8*>(dfr)[(2 * t + 1) * 64 + lane];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    f32x4 h = mfma(wh[u], dhi, f32x4{0.f, 0.f, 0.f, 0.f});
+                    h = mfma(wo[u], dhi, h);
+                    h = mfma(wh[u], dlo, h);
+                    bf16x4 dz;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dz[e] = (__bf16)(h[e] * (float)sp4[t][u][e]);
+                    ldsW(act[1], t, jb0 + u, dz);
+                    store_t(dz, A.dzT[3], t, jb0 + u);
+                }
+            }
+        }
+        __syncthreads();
+        // ---------------- backward hidden: dh_{L-1} = dz_L W_L (L = 4, 3, 2), dz_{L-1} = dh SiLU'(z_{L-1})
+#pragma unroll 1
+        for (int li = 2; li >= 0; --li) {
+            asm volatile("" : "+s"(Wt));
+            bf16x8 w[2][8];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) w[u][s] = Wt[kWtBwd / 8 + li * (16 * 8 * 64) + ((jb0 + u) * 8 + s) * 64 + lane];
+            const __bf16* in = act[(li + 1) & 1];  // dz4 in act[1], dz3 in act[0], dz2 in act[1]
+            __bf16* out = act[li & 1];
+            bf16x8 w1[2];
+            f32x4 b1[2];
+            if (li == 0) {
+                w1[0] = Wt[kWtW1 / 8 + jb0 * 64 + lane];
+                w1[1] = Wt[kWtW1 / 8 + (jb0 + 1) * 64 + lane];
+                b1[0] = bl[0][4 * jb0 + g];
+                b1[1] = bl[0][4 * (jb0 + 1) + g];
             }
 #pragma unroll
-            for (int jb = 0; jb < 16; ++jb) dz[jb] = ndz[jb];
+            for (int t0 = 0; t0 < 8; t0 += 2) {
+                if (t0 >= ntile) break;
+                f32x4 hh[2][2] = {{f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}},
+                                  {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}}};
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const bf16x8 b = ldsB(in, t0 + q, s);
+                        hh[q][0] = mfma(w[0][s], b, hh[q][0]);
+                        hh[q][1] = mfma(w[1][s], b, hh[q][1]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                const int t = t0 + q;
+                const f32x4 (&h)[2] = hh[q];
+                bf16x8 xf;
+                if (li == 0) xf = xfrag(t);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    bf16x4 spv;
+                    if (li > 0) {
+                        spv = *sp_ptr(A.spF[li - 1], t, jb0 + u);
+                    } else {
+                        // layer 1: SiLU'(z1) recomputed from x
+                        const f32x4 z = mfma(w1[u], xf, b1[u]);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float sg = sigmoidf_(z[e]);
+                            spv[e] = (__bf16)(sg * (1.0f + z[e] * (1.0f - sg)));
+                        }
+                    }
+                    bf16x4 dz;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dz[e] = (__bf16)(h[u][e] * (float)spv[e]);
+                    if (li > 0) ldsW(out, t, jb0 + u, dz);
+                    store_t(dz, A.dzT[li], t, jb0 + u);
+                }
+                }
+            }
+            __syncthreads();
         }
     }
 #pragma unroll
@@ -1427,13 +1479,10 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
         tb.hT[l] = ta.hT[l];
         tb.dzT[l] = ta.dzT[l];
     }
-    int dev = 0, ncu = 256, per_cu = 1;
+    int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, train_rows, kTrThreads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const int64_t nblk = (n + kTrRows - 1) / kTrRows;
-    hipLaunchKernelGGL(train_rows, dim3((unsigned)std::min<int64_t>(nblk, (int64_t)ncu * per_cu)), dim3(kTrThreads), 0,
-                       st, ta);
+    const int64_t nblk = (n + kTcRows - 1) / kTcRows;
+    hipLaunchKernelGGL(train_cols, dim3((unsigned)std::min<int64_t>(nblk, (int64_t)ncu)), dim3(kTcThreads), 0, st, ta);
     hipLaunchKernelGGL(train_dw, dim3(3 * kDwParts), dim3(64 * kDwWaves), 0, st, tb, n, m->part);
     hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
     const int nsm = (int)((n + kSmChunk - 1) / kSmChunk);
