@@ -390,10 +390,14 @@ int kgrt_mlp_forward(kgrt_mlp* mlp, const float* x_dev, float* y_dev, int64_t n,
  * 32 <= n <= max_batch, n a multiple of 32. Loss per sample:
  * BCE-with-logits(o0, t0) + 10 (o1-t1)^2 + 10 (o2-t2)^2 + t5 ((o3-t3)^2 + (o4-t4)^2),
  * averaged; written to loss_dev (one float). If grads_dev is not NULL the
- * gradient (num_params floats) is copied there. */
+ * gradient (num_params floats) is copied there. Every sum over the batch is
+ * taken in a fixed order, so the same inputs give bit-identical loss and
+ * gradient. */
 int kgrt_mlp_loss_grads(kgrt_mlp* mlp, const float* x_dev, const float* t_dev, const int32_t* idx_dev, int64_t n,
                         float* loss_dev, float* grads_dev, void* stream);
-/* One Adam step on the batch (as kgrt_mlp_loss_grads), then refreshes the BF16 weights. */
+/* One Adam step on the batch (as kgrt_mlp_loss_grads): each parameter's new
+ * value is written to P and to the BF16 fragments that hold it in the same
+ * launch that sums its gradient. */
 int kgrt_mlp_train_step(kgrt_mlp* mlp, const float* x_dev, const float* t_dev, const int32_t* idx_dev, int64_t n,
                         const kgrt_adam* opt, float* loss_dev, void* stream);
 /* Ray features (a, cos(incl), x/15, y/15) from rays_dev [n][4] = (a, incl_deg, x, y). */

@@ -246,8 +246,8 @@ __device__ __forceinline__ int64_t tm_index(int u, int64_t b) { return (b >> 6) 
 // added up in order by train_dw_reduce.
 constexpr int kDwParts = 85;
 struct TrainBufs {
-    __bf16* hT[4];   // h of layers 1..4
-    __bf16* dzT[4];  // dL/dz of layers 1..4
+    __bf16* hT[3];   // h of layers 1..3
+    __bf16* dzT[3];  // dL/dz of layers 2..4
 };
 
 // ------------------------------------------ fused training pass
@@ -319,13 +319,20 @@ struct TrainRowsArgs {
     const float* P;
     const __bf16* Wr;
     const __bf16* Wt;
-    __bf16* hT[4];   // h1..h4, tile-major [B/64][256][64]
-    __bf16* dzT[4];  // dL/dz of layers 1..4, tile-major
+    __bf16* hT[3];   // h1..h3, tile-major [B/64][256][64]
+    __bf16* dzT[3];  // dL/dz of layers 2..4, tile-major
     __bf16* spF[2];  // SiLU'(z) of layers 2 and 3 in the accumulator layout [B/16][jb 16][lane 64][4]
-    float* dout;     // dL/do [B][5]
-    float* loss;
+    float* gpart;    // the input and output layers' gradient partials per 128-row block (see below)
+    float* lpart;    // the loss of each wave's rows over n [grid][8], added up by finish_step
     float inv_n;
 };
+
+// The input and output layers' gradients leave the training pass as partial sums over each
+// 128-row block, one value per position, in the order of their products' accumulators: dL/dW1
+// and dL/db1 as [block][jb 16][g 4][c 5][e 4] (c < 4: W1[u][c], c = 4: b1[u]), dL/dW5 as
+// [block][jb 16][g 4][o 5][e 4] (W5[o][u]), unit u = 16 jb + 4 g + e; then dL/db5 as
+// [block][8].
+constexpr int64_t kGpIn = 16 * 4 * 5 * 4, kGpOut = 16 * 4 * 5 * 4, kGpB5 = 8;
 
 // ------------------------------------------ column-parallel fused training
 // Forward and backward of a block of 128 rows (8 tiles of 16) by 8 waves, wave w
@@ -339,7 +346,7 @@ struct TrainRowsArgs {
 // row-parallel inference kernel. h and dz leave for HBM tile-major (transposed
 // by a product with the identity), SiLU'(z2), SiLU'(z3) in the accumulator
 // layout; SiLU'(z4) stays in registers.
-constexpr int kTcWaves = 8, kTcThreads = 64 * kTcWaves, kTcRows = 128, kTcPitch = 256;
+constexpr int kTcWaves = 8, kTcThreads = 64 * kTcWaves, kTcRows = 128, kTcPitch = 256, kTcMaxGrid = 1024;
 __global__ void __launch_bounds__(kTcThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 train_cols(const TrainRowsArgs A) {
     __shared__ __align__(16) __bf16 act[2][kTcRows * kTcPitch];  // two activation buffers (2 x 66 KB)
@@ -403,6 +410,9 @@ train_cols(const TrainRowsArgs A) {
         auto ldsB = [&](const __bf16* buf, int t, int s) {
             return *reinterpret_cast<const bf16x8*>(buf + (16 * t + r) * kTcPitch + 8 * ((4 * s + g) ^ r));
         };
+        auto ldsR = [&](const __bf16* buf, int t, int jb) {
+            return *reinterpret_cast<const bf16x4*>(buf + (16 * t + r) * kTcPitch + 8 * ((4 * (jb >> 1) + g) ^ r) + 4 * (jb & 1));
+        };
         auto ldsW = [&](__bf16* buf, int t, int jb, const bf16x4& v) {
             *reinterpret_cast<bf16x4*>(buf + (16 * t + r) * kTcPitch + 8 * ((4 * (jb >> 1) + g) ^ r) + 4 * (jb & 1)) = v;
         };
@@ -411,6 +421,33 @@ train_cols(const TrainRowsArgs A) {
             const bf16x4 vt = transpose(v);
             *reinterpret_cast<bf16x4*>(dst + tm_index(16 * jb + r, row0 + 16 * t + 4 * g)) = vt;
         };
+        // K = 16 B operands over the 16 rows of tile t (lane (n, g): rows 16 t + 4 g + e, column n)
+        // for the input and output layers' gradient products: x as hi (columns 0..3) and lo
+        // (4..7) parts and a column of ones (8); dL/do (LDS, see the head) as hi (0..4) and lo
+        // (8..12) parts
+        auto xcols = [&](int t) {
+            bf16x4 f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const f32x4 xv = xs[16 * t + 4 * g + e];
+                const float v = xv[r & 3];
+                const __bf16 hi = (__bf16)v;
+                f[e] = r < 4 ? hi : (r < 8 ? (__bf16)(v - (float)hi) : (__bf16)(r == 8 ? 1.0f : 0.0f));
+            }
+            return f;
+        };
+        auto dcols = [&](const float* dsh, int t) {
+            bf16x4 f;
+            const int c = r & 7;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = (c < kOut && r < 13) ? dsh[(16 * t + 4 * g + e) * 8 + c] : 0.0f;
+                const __bf16 hi = (__bf16)v;
+                f[e] = r < 8 ? hi : (__bf16)(v - (float)hi);
+            }
+            return f;
+        };
+        auto mfma16 = [](bf16x4 a, bf16x4 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); };
         auto sp_ptr = [&](__bf16* arr, int t, int jb) {
             return reinterpret_cast<bf16x4*>(arr + ((row0 + 16 * t) >> 4) * (16 * 64 * 4) + (jb * 64 + lane) * 4);
         };
@@ -475,13 +512,15 @@ train_cols(const TrainRowsArgs A) {
                         if (l == 2) sp4[t][u] = spv;
                         else *sp_ptr(A.spF[l], t, jb0 + u) = spv;
                         ldsW(out, t, jb0 + u, h);
-                        store_t(h, A.hT[l + 1], t, jb0 + u);
+                        if (l < 2) store_t(h, A.hT[l + 1], t, jb0 + u);
                     }
             }
             __syncthreads();
         }
         // ---------------- head (wave w: tile w), loss, dL/do; h4 is in act[1]
         __bf16* const dfr = act[0];  // dL/do operands of the 8 tiles (hi, lo), 16 KB
+        float* const dsh = reinterpret_cast<float*>(act[0] + 8 * 1024);  // dL/do [tile 8][row 16][8], 4 KB
+        float* const bsh = dsh + 8 * 16 * 8;  // dL/db5 of each tile [tile 8][8]
         if (wave < ntile) {
             const int t = wave;
             f32x4 o = {0.f, 0.f, 0.f, 0.f};
@@ -508,12 +547,26 @@ train_cols(const TrainRowsArgs A) {
                     d[2] = 2.0f * kWG * e2 * A.inv_n;
                     d[3] = 2.0f * kWPhi * m * e3 * A.inv_n;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) A.dout[row * kOut + e] = d[e];
+                    for (int e = 0; e < 4; ++e) dsh[(16 * t + r) * 8 + e] = d[e];
                 } else {
                     const float e4 = o[0] + Pp[kB5 + 4] - tt[4];
                     lacc += kWPhi * m * e4 * e4;
                     d[0] = 2.0f * kWPhi * m * e4 * A.inv_n;
-                    A.dout[row * kOut + 4] = d[0];
+                    dsh[(16 * t + r) * 8 + 4] = d[0];
+                }
+            }
+            // dL/db5 over the tile's rows: lanes 0 and 16 hold the sums of columns 0..3 and 4
+            {
+                f32x4 ds = d;
+#pragma unroll
+                for (int dd = 1; dd < 16; dd <<= 1)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ds[e] += __shfl_xor(ds[e], dd);
+                if (lane == 0) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bsh[t * 8 + e] = ds[e];
+                } else if (lane == 16) {
+                    bsh[t * 8 + 4] = ds[0];
                 }
             }
             // B operands of dh4 = dL/do W5: lane (r, 0) holds dL/do of row r (hi and lo parts)
@@ -530,10 +583,40 @@ train_cols(const TrainRowsArgs A) {
             reinterpret_cast<bf16x8*>(dfr)[(2 * t + 1) * 64 + lane] = dlo;
         }
         __syncthreads();
+        if (wave == 0 && lane < kOut) {  // dL/db5 of the block: its tiles in order
+            float sb = 0.0f;
+            for (int t = 0; t < ntile; ++t) sb += bsh[t * 8 + lane];
+            A.gpart[nblk * (kGpIn + kGpOut) + blk * kGpB5 + lane] = sb;
+        }
         // ---------------- dz4 = (dL/do W5) SiLU'(z4) -> act[1]
         {
             const bf16x8 wh[2] = {Wt[kWtW5T / 8 + (2 * jb0) * 64 + lane], Wt[kWtW5T / 8 + (2 * (jb0 + 1)) * 64 + lane]};
             const bf16x8 wo[2] = {Wt[kWtW5T / 8 + (2 * jb0 + 1) * 64 + lane], Wt[kWtW5T / 8 + (2 * (jb0 + 1) + 1) * 64 + lane]};
+            // dL/dW5 over the block's rows: h4 (in act[1] until this wave writes its units of dz4
+            // there) transposed against the dL/do columns
+            {
+                f32x4 gw5[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (t >= ntile) break;
+                    const bf16x4 dc = dcols(dsh, t);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) gw5[u] = mfma16(transpose(ldsR(act[1], t, jb0 + u)), dc, gw5[u]);
+                }
+                // lane (n, g) holds column n of units 16 jb + 4 g + e: dL/do hi (n < 5) and lo
+                // (n = 8..12) parts, added here
+                float* gp = A.gpart + nblk * kGpIn + blk * kGpOut;
+                asm volatile("" : "+s"(gp));  // the lane addresses are formed here, not kept from the loop head
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    f32x4 v = gw5[u];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += __shfl_down(gw5[u][e], 8);
+                    if (r < kOut) *reinterpret_cast<f32x4*>(gp + (((jb0 + u) * 4 + g) * 5 + r) * 4) = v;
+                }
+            }
+            __bf16* dz4 = A.dzT[2];
+            asm volatile("" : "+s"(dz4));  // its lane addresses are formed here, not kept from the kernel's start
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 if (t >= ntile) break;
@@ -548,7 +631,7 @@ train_cols(const TrainRowsArgs A) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) dz[e] = (__bf16)(h[e] * (float)sp4[t][u][e]);
                     ldsW(act[1], t, jb0 + u, dz);
-                    store_t(dz, A.dzT[3], t, jb0 + u);
+                    store_t(dz, dz4, t, jb0 + u);
                 }
             }
         }
@@ -566,6 +649,7 @@ train_cols(const TrainRowsArgs A) {
             __bf16* out = act[li & 1];
             bf16x8 w1[2];
             f32x4 b1[2];
+            f32x4 gw1[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};  // dL/dW1, dL/db1
             if (li == 0) {
                 w1[0] = Wt[kWtW1 / 8 + jb0 * 64 + lane];
                 w1[1] = Wt[kWtW1 / 8 + (jb0 + 1) * 64 + lane];
@@ -591,7 +675,11 @@ train_cols(const TrainRowsArgs A) {
                 const int t = t0 + q;
                 const f32x4 (&h)[2] = hh[q];
                 bf16x8 xf;
-                if (li == 0) xf = xfrag(t);
+                bf16x4 xc;
+                if (li == 0) {
+                    xf = xfrag(t);
+                    xc = xcols(t);
+                }
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     bf16x4 spv;
@@ -609,9 +697,24 @@ train_cols(const TrainRowsArgs A) {
                     bf16x4 dz;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) dz[e] = (__bf16)(h[u][e] * (float)spv[e]);
-                    if (li > 0) ldsW(out, t, jb0 + u, dz);
-                    store_t(dz, A.dzT[li], t, jb0 + u);
+                    if (li > 0) {
+                        ldsW(out, t, jb0 + u, dz);
+                        store_t(dz, A.dzT[li - 1], t, jb0 + u);
+                    } else {
+                        gw1[u] = mfma16(transpose(dz), xc, gw1[u]);
+                    }
                 }
+                }
+            }
+            if (li == 0) {  // lane (n, g): column n of units 16 jb + 4 g + e, x hi (0..3), lo (4..7), ones (8)
+                float* gp = A.gpart + blk * kGpIn;
+                asm volatile("" : "+s"(gp));
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    f32x4 v = gw1[u];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += __shfl_down(gw1[u][e], 4);
+                    if (r < 4 || r == 8) *reinterpret_cast<f32x4*>(gp + (((jb0 + u) * 4 + g) * 5 + (r < 4 ? r : 4)) * 4) = v;
                 }
             }
             __syncthreads();
@@ -619,177 +722,7 @@ train_cols(const TrainRowsArgs A) {
     }
 #pragma unroll
     for (int dd = 32; dd > 0; dd >>= 1) lacc += __shfl_xor(lacc, dd);
-    if (lane == 0) atomicAdd(A.loss, lacc * A.inv_n);
-}
-
-// The gradients of the input and output layers (train_dw takes the hidden ones), as MFMA
-// products over chunks of kSmChunk rows, A = a per-sample array (256 units x rows,
-// tile-major), B = 16 columns built from the chunk's rows in LDS:
-//   task 0: A = dz1, B = [x hi (4), x lo (4), 1]: dL/dW1[u][c] = D[u][c] + D[u][4 + c], dL/db1 = D[u][8];
-//   task 1: A = h4, B = [dL/do hi (5), 0 (3), dL/do lo (5)]: dL/dW5[o][u] = D[u][o] + D[u][8 + o],
-//     and dL/db5 = sum dL/do by the block's threads.
-// One block of 4 waves per (task, chunk), a wave 64 units; partial sums
-// [task][chunk][256][16] and [chunk][8], added over the chunks in order by
-// train_small_reduce.
-constexpr int kSmChunk = 256, kSmTasks = 2;
-constexpr int kSmVals = kH + kH * kIn + kOut * kH + kOut;  // b1, W1, W5, b5
-__global__ void __launch_bounds__(256) train_small(const float* __restrict__ x, const int32_t* __restrict__ idx,
-                                                   int64_t n, const TrainRowsArgs A, float* __restrict__ part) {
-    __shared__ bf16x8 bfr[kSmChunk / 64][2][64];  // B fragments of the chunk's 64-row steps (32 KB)
-    __shared__ float rowv[kSmChunk][8];         // the chunk's x (task 0) or dL/do (task 1) rows
-    __shared__ float bsum[256][kOut];
-    const int task = blockIdx.x % kSmTasks, chunk = blockIdx.x / kSmTasks;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lg = lane >> 4;
-    const int64_t b0 = (int64_t)chunk * kSmChunk, b1 = std::min<int64_t>(n, b0 + kSmChunk);
-    const int rows = (int)(b1 - b0), nsteps = (rows + 63) / 64;  // n is a multiple of 32
-    // the chunk's rows of x (gathered through idx) or dL/do, all loads issued together
-    if (task == 0) {
-        for (int r = tid; r < rows; r += 256) {
-            const int64_t b = b0 + r;
-            const f32x4 xv = *reinterpret_cast<const f32x4*>(x + (idx ? (int64_t)idx[b] : b) * kIn);
-#pragma unroll
-            for (int c = 0; c < kIn; ++c) rowv[r][c] = xv[c];
-        }
-    } else {
-        for (int i = tid; i < rows * kOut; i += 256) rowv[i / kOut][i % kOut] = A.dout[b0 * kOut + i];
-    }
-    __syncthreads();
-    // B fragments: a k step is one 64-row tile taken as two products (hh = 0, 1) in the row
-    // order of train_dw: lane (col, kg) of product hh holds B[rows 64 q + 16 kg + 8 hh + e][col];
-    // rows past the chunk's end are zero
-    for (int i = tid; i < nsteps * 128; i += 256) {
-        const int q = i / 128, hh = (i / 64) & 1, l = i % 64, col = l & 15, kg = l >> 4;
-        bf16x8 f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int r = 64 * q + 16 * kg + 8 * hh + e;
-            float v = 0.0f;
-            if (r >= rows) {
-            } else if (task == 0) {
-                if (col < 8) {
-                    const float xv = rowv[r][col & 3];
-                    const float hi = (float)(__bf16)xv;
-                    v = (col < 4) ? hi : xv - hi;
-                } else if (col == 8) {
-                    v = 1.0f;
-                }
-            } else if (col < kOut || (col >= 8 && col < 8 + kOut)) {
-                const float dv = rowv[r][col & 7];
-                const float hi = (float)(__bf16)dv;
-                v = (col < 8) ? hi : dv - hi;
-            }
-            f[e] = (__bf16)v;
-        }
-        bfr[q][hh][l] = f;
-    }
-    if (task == 1) {
-        // dL/db5: thread t sums rows t, t + 256, ... of the chunk, then the threads in order
-        float sv[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        for (int r = tid; r < rows; r += 256)
-#pragma unroll
-            for (int o = 0; o < kOut; ++o) sv[o] += rowv[r][o];
-#pragma unroll
-        for (int o = 0; o < kOut; ++o) bsum[tid][o] = sv[o];
-    }
-    __syncthreads();
-    if (task == 1 && tid < kOut) {
-        float b5 = 0.0f;
-        for (int t = 0; t < 256; ++t) b5 += bsum[t][tid];
-        const int64_t nchunk = (n + kSmChunk - 1) / kSmChunk;
-        part[kSmTasks * nchunk * kH * 16 + (int64_t)chunk * 8 + tid] = b5;
-    }
-    const __bf16* src = (task == 0) ? A.dzT[0] : A.hT[3];
-    f32x4 acc[4] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f},
-                    f32x4{0.f, 0.f, 0.f, 0.f}};
-    constexpr int kAhead = 2;
-    bf16x8 af[kAhead][4][2];
-    auto load = [&](int q, bf16x8 (&a)[4][2]) {
-        const int64_t kk = b0 + 64 * q + 16 * lg;
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-            const bf16x8* pa = reinterpret_cast<const bf16x8*>(src + tm_index(16 * (4 * wave + mi) + lr, kk));
-            a[mi][0] = pa[0];
-            a[mi][1] = pa[1];
-        }
-    };
-    // every load issued (clamped to the last step) so each step waits only for its own loads;
-    // the rows of a half-filled last tile past n are zeroed in A as they are in B
-    const bool tail_half = (rows % 64) != 0;
-#pragma unroll
-    for (int q = 0; q < kAhead; ++q) load(std::min(q, nsteps - 1), af[q]);
-    for (int s0 = 0; s0 < nsteps; s0 += kAhead) {
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q) {
-            if (s0 + q < nsteps) {
-                if (tail_half && s0 + q == nsteps - 1 && lg >= 2) {
-#pragma unroll
-                    for (int mi = 0; mi < 4; ++mi) af[q][mi][0] = af[q][mi][1] = bf16x8{};
-                }
-#pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {
-                    const bf16x8 bb = bfr[s0 + q][hh][lane];
-#pragma unroll
-                    for (int mi = 0; mi < 4; ++mi)
-                        acc[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[q][mi][hh], bb, acc[mi], 0, 0, 0);
-                }
-            }
-            load(std::min(s0 + q + kAhead, nsteps - 1), af[q]);
-        }
-    }
-    // accumulator e of mi: unit 16 (4 wave + mi) + 4 lg + e, column lr
-    float* out = part + ((int64_t)task * ((n + kSmChunk - 1) / kSmChunk) + chunk) * kH * 16;
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[(16 * (4 * wave + mi) + 4 * lg + e) * 16 + lr] = acc[mi][e];
-}
-
-// dL/db1, W1, W5, b5 from train_small's chunk partials, added in chunk order
-// (one thread per gradient value).
-__global__ void __launch_bounds__(256) train_small_reduce(const float* __restrict__ part, int nchunk,
-                                                          float* __restrict__ G) {
-    // 32 consecutive threads per value: thread k adds chunks k, k + 32, ... in order, then the
-    // 32 partial sums are combined by a fixed butterfly
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / 32, k = threadIdx.x % 32;
-    const bool live = i < kSmVals;
-    // (task, column, second column or -1) of the value and its destination
-    int task = 0, col = 0, col2 = -1, u = 0;
-    int64_t dst = -1;
-    const float* p = nullptr;
-    int stride = kH * 16;
-    if (!live) {
-    } else if (i < kH) {
-        u = i;
-        col = 8;
-        dst = kB1 + u;
-    } else if (i < kH + kH * kIn) {
-        const int j = i - kH;
-        u = j / kIn;
-        col = j % kIn;
-        col2 = 4 + col;
-        dst = kW1 + j;
-    } else if (i < kH + kH * kIn + kOut * kH) {
-        const int j = i - kH - kH * kIn, o = j / kH;
-        u = j % kH;
-        task = 1;
-        col = o;
-        col2 = 8 + o;
-        dst = kW5 + j;
-    } else {
-        const int o = i - kH - kH * kIn - kOut * kH;
-        p = part + (int64_t)kSmTasks * nchunk * kH * 16 + o;  // b5: [chunk][8]
-        stride = 8;
-        dst = kB5 + o;
-    }
-    if (live && !p) p = part + (int64_t)task * nchunk * kH * 16 + u * 16 + col;
-    float s = 0.0f;
-    if (live)
-        for (int c = k; c < nchunk; c += 32)
-            s += p[(int64_t)c * stride] + (col2 >= 0 ? p[(int64_t)c * stride + (col2 - col)] : 0.0f);
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) s += __shfl_xor(s, d);
-    if (live && k == 0) G[dst] = s;
+    if (lane == 0) A.lpart[blockIdx.x * kTcWaves + wave] = lacc * A.inv_n;
 }
 
 // Partial dW_L and db_L over a range of 64-row tiles: block (layer L - 2, part j) takes tiles
@@ -813,7 +746,7 @@ train_dw(const TrainBufs B, int64_t n, float* __restrict__ part) {
     const int64_t t0 = ntiles * j / kDwParts, t1 = ntiles * (j + 1) / kDwParts;
     const int nsteps = (int)(t1 - t0);
     const bool tail_half = (n % 64) != 0 && t1 == ntiles;  // the last tile holds 32 valid rows
-    const __bf16* dz = B.dzT[li + 1];  // dL/dz of layer li + 2
+    const __bf16* dz = B.dzT[li];      // dL/dz of layer li + 2
     const __bf16* h = B.hT[li];        // h of layer li + 1
     f32x4 acc[8][4];
 #pragma unroll
@@ -893,39 +826,178 @@ __device__ __forceinline__ int dw_entry(int j) {
     return (128 * (wave / 4) + 16 * mi + 4 * (lane / 16) + e) * kH + 64 * (wave % 4) + 16 * ni + lane % 16;
 }
 
-__global__ void __launch_bounds__(256) train_dw_reduce(const float* __restrict__ part, float* __restrict__ G) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * kH * kH + 3 * kH;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (i >= 3 * kH * kH) {  // dL/db2..b4
-            const int li = (int)((i - 3 * kH * kH) / kH), o = (int)((i - 3 * kH * kH) % kH);
-            const float* p = part + (int64_t)3 * kDwParts * kH * kH + (int64_t)li * kDwParts * kH + o;
-            float s = 0.0f;
-            for (int c = 0; c < kDwParts; ++c) s += p[(int64_t)c * kH];
-            G[(li == 0 ? kB2 : (li == 1 ? kB3 : kB4)) + o] = s;
-            continue;
+// ------------------------------------------------- finishing a step
+// One launch takes every gradient value from its partial sums in a fixed order: the hidden
+// layers' weights and biases over train_dw's kDwParts parts (one thread per value), the input
+// and output layers' over the training pass's 128-row blocks (32 consecutive threads per value:
+// thread k adds blocks k, k + 32, ... in order, then a fixed butterfly combines the 32 sums),
+// and the loss
+// over the training pass's per-wave partials (the last block). For a training step the thread
+// holding a gradient then applies Adam to its parameter (Kingma & Ba 2015:
+// m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+// p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)) and writes the new value into
+// every fragment slot that holds it: the slots pack_rows, pack_train and pack_biases fill,
+// whose all-zero slots never change, so no repacking pass follows.
+struct FinishArgs {
+    const float* part;   // train_dw's partial sums
+    const float* gpart;  // the training pass's input- and output-layer partial sums
+    int64_t nrb;         // its 128-row blocks
+    const float* lpart;  // the training pass's per-wave loss partials
+    int nlp;
+    float* loss;
+    float* G;
+    int adam;  // 0: gradients and loss only
+    float *P, *M, *V, *Pi;
+    __bf16 *Wr, *Wt;
+    float lr, b1, b2, eps, c1, c2;
+};
+constexpr int kFinHidVals = 3 * kH * kH + 3 * kH;
+constexpr int kFinHidBlocks = kFinHidVals / 256;
+static_assert(kFinHidVals % 256 == 0, "one thread per hidden-layer gradient value");
+constexpr int kFinSmBlocks = (kGpIn + kGpOut) / 16 + 1;
+constexpr int kFinBlocks = kFinHidBlocks + kFinSmBlocks + 1;
+
+// input unit k of a layer -> (k step s, lane group g, element e) with kperm(s, g, e) = k
+__device__ __forceinline__ void kperm_inv(int k, int& s, int& g, int& e) {
+    s = k >> 5;
+    const int w = k & 31;
+    g = (w & 15) >> 2;
+    e = (w & 3) + ((w >> 4) << 2);
+}
+
+__device__ __forceinline__ void split_hi_lo(float w, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)w;
+    lo = (__bf16)(w - (float)hi);
+}
+
+// The new value p of parameter i into its fragment slots (the layouts above pack_rows and
+// pack_train, read backwards); b5 has none, the head reads it from P.
+__device__ void scatter_param(const FinishArgs& F, int64_t i, float p) {
+    __bf16 hi, lo;
+    if (i < kB1) {  // W1[u][c]: lane group 0 holds hi at elements c and c + 4, lane group 1 lo at c
+        const int u = (int)(i / kIn), c = (int)(i % kIn), r = u % 16;
+        __bf16* wr = F.Wr + kWrW1 + (int64_t)(u / 16) * kWrFrag;
+        __bf16* wt = F.Wt + kWtW1 + (int64_t)(u / 16) * kWrFrag;
+        split_hi_lo(-kLog2e * p, hi, lo);
+        wr[r * 8 + c] = hi;
+        wr[r * 8 + c + 4] = hi;
+        wr[(16 + r) * 8 + c] = lo;
+        split_hi_lo(p, hi, lo);
+        wt[r * 8 + c] = hi;
+        wt[r * 8 + c + 4] = hi;
+        wt[(16 + r) * 8 + c] = lo;
+    } else if (i < kW2) {
+        F.Pi[kPiB + (i - kB1)] = -kLog2e * p;
+    } else if (i < kW5) {
+        const int64_t off = i - kW2;
+        const int l = (int)(off / (kH * kH + kH)), j = (int)(off % (kH * kH + kH));
+        if (j >= kH * kH) {
+            F.Pi[kPiB + (l + 1) * kH + (j - kH * kH)] = -kLog2e * p;
+            return;
         }
-        const int li = (int)(i / (kH * kH)), j = (int)(i % (kH * kH));
-        const float* p = part + (int64_t)li * kDwParts * kH * kH + j;
-        float s = 0.0f;
-        for (int c = 0; c < kDwParts; ++c) s += p[(int64_t)c * kH * kH];
-        G[(li == 0 ? kW2 : (li == 1 ? kW3 : kW4)) + dw_entry(j)] = s;
+        const int o = j / kH, k = j % kH;
+        int s, g, e;
+        kperm_inv(k, s, g, e);  // forward fragment: row o, input k
+        F.Wr[kWrHid + ((int64_t)(l * 16 + o / 16) * 8 + s) * kWrFrag + (16 * g + o % 16) * 8 + e] = (__bf16)p;
+        kperm_inv(o, s, g, e);  // transposed fragment: row k, input o
+        F.Wt[kWtBwd + ((int64_t)(l * 16 + k / 16) * 8 + s) * kWrFrag + (16 * g + k % 16) * 8 + e] = (__bf16)p;
+    } else if (i < kB5) {
+        const int o = (int)((i - kW5) / kH), k = (int)((i - kW5) % kH);
+        int s, g, e;
+        kperm_inv(k, s, g, e);
+        const int lane = 16 * g + o;
+        split_hi_lo(-p / kLog2e, hi, lo);
+        F.Wr[kWrW5 + (2 * s) * kWrFrag + lane * 8 + e] = hi;
+        F.Wr[kWrW5 + (2 * s + 1) * kWrFrag + lane * 8 + e] = lo;
+        split_hi_lo(p, hi, lo);
+        F.Wt[kWtW5 + (2 * s) * kWrFrag + lane * 8 + e] = hi;
+        F.Wt[kWtW5 + (2 * s + 1) * kWrFrag + lane * 8 + e] = lo;
+        F.Wt[kWtW5T + (2 * (k / 16)) * kWrFrag + (k % 16) * 8 + o] = hi;
+        F.Wt[kWtW5T + (2 * (k / 16) + 1) * kWrFrag + (k % 16) * 8 + o] = lo;
     }
 }
 
-// ------------------------------------------------------------------ Adam
-// Kingma & Ba (2015): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
-// p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
-__global__ void __launch_bounds__(256) adam(float* __restrict__ P, float* __restrict__ M, float* __restrict__ V,
-                                            const float* __restrict__ G, int64_t np, float lr, float b1, float b2,
-                                            float eps, float c1, float c2) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
-        const float g = G[i];
-        const float m = b1 * M[i] + (1.0f - b1) * g;
-        const float v = b2 * V[i] + (1.0f - b2) * g * g;
-        M[i] = m;
-        V[i] = v;
-        P[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+__device__ __forceinline__ void finish_param(const FinishArgs& F, int64_t i, float g) {
+    F.G[i] = g;
+    if (!F.adam) return;
+    const float m = F.b1 * F.M[i] + (1.0f - F.b1) * g;
+    const float v = F.b2 * F.V[i] + (1.0f - F.b2) * g * g;
+    F.M[i] = m;
+    F.V[i] = v;
+    const float p = F.P[i] - F.lr * (m / F.c1) / (sqrtf(v / F.c2) + F.eps);
+    F.P[i] = p;
+    scatter_param(F, i, p);
+}
+
+__global__ void __launch_bounds__(256) finish_step(const FinishArgs F) {
+    const int tid = threadIdx.x;
+    if (blockIdx.x < kFinHidBlocks) {
+        const int i = blockIdx.x * 256 + tid;
+        float s = 0.0f;
+        if (i >= 3 * kH * kH) {  // dL/db2..b4
+            const int li = (i - 3 * kH * kH) / kH, o = (i - 3 * kH * kH) % kH;
+            const float* p = F.part + (int64_t)3 * kDwParts * kH * kH + (int64_t)li * kDwParts * kH + o;
+#pragma unroll 17
+            for (int c = 0; c < kDwParts; ++c) s += p[(int64_t)c * kH];
+            finish_param(F, (li == 0 ? kB2 : (li == 1 ? kB3 : kB4)) + o, s);
+        } else {
+            const int li = i / (kH * kH), j = i % (kH * kH);
+            const float* p = F.part + (int64_t)li * kDwParts * kH * kH + j;
+#pragma unroll 17
+            for (int c = 0; c < kDwParts; ++c) s += p[(int64_t)c * kH * kH];
+            finish_param(F, (li == 0 ? kW2 : (li == 1 ? kW3 : kW4)) + dw_entry(j), s);
+        }
+        return;
     }
+    if (blockIdx.x < kFinHidBlocks + kFinSmBlocks) {  // dL/db1, W1, W5, b5
+        // 16 consecutive positions of one region, 16 threads each: thread k adds the blocks
+        // k, k + 16, ... in order, then the 16 sums are added in order through LDS
+        __shared__ float red[16][16];
+        const int sb = blockIdx.x - kFinHidBlocks, q = tid & 15, k = tid >> 4;
+        const int region = sb < kGpIn / 16 ? 0 : (sb < (kGpIn + kGpOut) / 16 ? 1 : 2);
+        const int pos = (sb - (region == 0 ? 0 : (region == 1 ? kGpIn / 16 : (kGpIn + kGpOut) / 16))) * 16 + q;
+        const int64_t stride = region == 0 ? kGpIn : (region == 1 ? kGpOut : kGpB5);
+        const float* p = F.gpart + (region == 0 ? 0 : (region == 1 ? F.nrb * kGpIn : F.nrb * (kGpIn + kGpOut))) + pos;
+        const bool live = pos < stride;
+        float s = 0.0f;
+        if (live) {
+            int64_t b = k;
+            for (; b + 48 < F.nrb; b += 64) {
+                const float v0 = p[b * stride], v1 = p[(b + 16) * stride], v2 = p[(b + 32) * stride], v3 = p[(b + 48) * stride];
+                s += v0;
+                s += v1;
+                s += v2;
+                s += v3;
+            }
+            for (; b < F.nrb; b += 16) s += p[b * stride];
+        }
+        red[k][q] = s;
+        __syncthreads();
+        if (k == 0 && live) {
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v += red[j][q];
+            int64_t dst;
+            if (region == 2) {
+                if (pos >= kOut) return;
+                dst = kB5 + pos;
+            } else {
+                const int e = pos & 3, c = (pos >> 2) % 5, jg = pos / 20, u = 4 * jg + e;  // jg = 4 jb + g
+                dst = region == 0 ? (c < 4 ? kW1 + u * kIn + c : kB1 + u) : kW5 + c * kH + u;
+            }
+            finish_param(F, dst, v);
+        }
+        return;
+    }
+    // the loss: thread t adds partials t, t + 256, ... in order, then a fixed tree
+    __shared__ float red[4];
+    float s = 0.0f;
+    for (int c = tid; c < F.nlp; c += 256) s += F.lpart[c];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) s += __shfl_xor(s, d);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) *F.loss = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // The inference kernel's scaled biases Pi (see the scaling note above).
@@ -1284,13 +1356,13 @@ struct kgrt_mlp {
     __bf16* Wr = nullptr;  // MFMA fragments of all layers for the row-parallel inference kernel
     __bf16* Wt = nullptr;  // fragments of the row-parallel training kernel (input layer, head, W^T)
     float* Pi = nullptr;   // scaled W1 and biases for inference
-    // training arrays, BF16, 256 values per sample: z[l] holds SiLU'(z_l) (l = 2, 3) in the
-    // training kernel's accumulator layout; tile-major, hT[l] and dz the activations h_l
-    // (l = 1..3) and h_4, h[l] the gradients dL/dz_l (l = 1..4)
-    __bf16 *h[5] = {}, *z[5] = {}, *hT[4] = {}, *dz = nullptr;
-    float* dout = nullptr;
+    // training arrays, BF16, 256 values per sample: tile-major, hT[l] the activations h_{l+1}
+    // and dzT[l] the gradients dL/dz_{l+2} (l = 0..2); spF[l] SiLU'(z_{l+2}) (l = 0, 1) in the
+    // training pass's accumulator layout
+    __bf16 *hT[3] = {}, *dzT[3] = {}, *spF[2] = {};
     float* part = nullptr;   // weight- and bias-gradient partial sums [3][kDwParts][256 x 256], [3][kDwParts][256]
-    float* spart = nullptr;  // the other gradients' partial sums: [5][chunks][256][16], then [chunks][8]
+    float* gpart = nullptr;  // the input and output layers' partial sums per 128-row block
+    float* lpart = nullptr;  // the training pass's per-wave loss partials [kTcMaxGrid][8]
     int64_t step = 0;
     // render workspace (grown on demand): features, outputs, fallback list and its integration
     float *r_feat = nullptr, *r_pred = nullptr, *r_tab = nullptr;
@@ -1331,10 +1403,9 @@ int64_t kgrt_mlp_num_params(void) { return kNumParams; }
 int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
-    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wr, m->Wt, m->Pi, m->part, m->spart, m->dz, m->dout, m->r_feat, m->r_pred,
+    void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wr, m->Wt, m->Pi, m->part, m->gpart, m->lpart, m->r_feat, m->r_pred,
                     m->r_tab, m->r_part, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
-                    m->h[1], m->h[2], m->h[3], m->h[4], m->z[1], m->z[2], m->z[3], m->z[4],
-                    m->hT[1], m->hT[2], m->hT[3]};
+                    m->hT[0], m->hT[1], m->hT[2], m->dzT[0], m->dzT[1], m->dzT[2], m->spF[0], m->spF[1]};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete m;
@@ -1357,13 +1428,11 @@ int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out) {
               hipMalloc(&m->Wr, kWrSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Wt, kWtSize * sizeof(__bf16)) == hipSuccess &&
               hipMalloc(&m->Pi, kPiSize * sizeof(float)) == hipSuccess &&
-              hipMalloc(&m->dout, (size_t)max_batch * kOut * 4) == hipSuccess &&
               hipMalloc(&m->part, (size_t)3 * kDwParts * (kH * kH + kH) * 4) == hipSuccess &&
-              hipMalloc(&m->spart, (size_t)((max_batch + kSmChunk - 1) / kSmChunk) * (kSmTasks * kH * 16 + 8) * 4) == hipSuccess;
-    for (int l = 1; ok && l <= 4; ++l) ok = hipMalloc(&m->h[l], hb) == hipSuccess;
-    for (int l = 2; ok && l <= 3; ++l) ok = hipMalloc(&m->z[l], hb) == hipSuccess;
-    for (int l = 1; ok && l <= 3; ++l) ok = hipMalloc(&m->hT[l], hb) == hipSuccess;
-    ok = ok && hipMalloc(&m->dz, hb) == hipSuccess;
+              hipMalloc(&m->gpart, (size_t)((max_batch + kTcRows - 1) / kTcRows) * (kGpIn + kGpOut + kGpB5) * 4) == hipSuccess &&
+              hipMalloc(&m->lpart, (size_t)kTcMaxGrid * kTcWaves * 4) == hipSuccess;
+    for (int l = 0; ok && l < 3; ++l) ok = hipMalloc(&m->hT[l], hb) == hipSuccess && hipMalloc(&m->dzT[l], hb) == hipSuccess;
+    for (int l = 0; ok && l < 2; ++l) ok = hipMalloc(&m->spF[l], hb) == hipSuccess;
     if (!ok) {
         kgrt_mlp_destroy(m);
         return KGRT_E_NOMEM;
@@ -1446,18 +1515,20 @@ int kgrt_mlp_forward(kgrt_mlp* m, const float* x, float* y, int64_t n, void* str
 // Loss and gradients of one batch (n <= max_batch samples, gathered through
 // idx if not NULL). Gradients land in the internal buffer and, if grads is
 // not NULL, are copied to grads (device, num_params floats).
-int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32_t* idx, int64_t n, float* loss,
-                        float* grads, void* stream) {
-    if (!m) return KGRT_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// The loss and gradient of a batch (kgrt_mlp_loss_grads) and, with opt, the Adam step that
+// follows (kgrt_mlp_train_step): the training pass, the hidden layers' gradient products and
+// finish_step, three launches on one stream.
+int loss_grads_step(kgrt_mlp* m, const float* x, const float* t, const int32_t* idx, int64_t n, float* loss,
+                    const kgrt_adam* opt, hipStream_t st) {
     if (n < 32 || n > m->max_batch || (n % 32) != 0)
         return mlp_fail(m, KGRT_E_INVALID_ARG, "need 32 <= n <= max_batch with n a multiple of 32");
     if (!x || !t || !loss) return mlp_fail(m, KGRT_E_INVALID_ARG, "x, t and loss must be device pointers");
-    DevGuard g(m->device);
-    hipStream_t st = (hipStream_t)stream;
-    // every gradient entry is written (not added) by the two reductions below
-    hipLaunchKernelGGL(fill_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1, 0.0f);
-    // per-sample arrays: h1..h4 and dL/dz of layers 1..4 tile-major, SiLU'(z) of layers 2
-    // and 3 in the training kernel's accumulator layout, dL/do row-major
+    // per-sample arrays: h1..h3 and dL/dz of layers 2..4 tile-major, SiLU'(z) of layers 2
+    // and 3 in the training pass's accumulator layout
     TrainRowsArgs ta{};
     ta.x = x;
     ta.idx = idx;
@@ -1466,31 +1537,68 @@ int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32
     ta.P = m->P;
     ta.Wr = m->Wr;
     ta.Wt = m->Wt;
-    for (int l = 0; l < 3; ++l) ta.hT[l] = m->hT[l + 1];
-    ta.hT[3] = m->dz;
-    for (int l = 0; l < 4; ++l) ta.dzT[l] = m->h[l + 1];
-    ta.spF[0] = m->z[2];
-    ta.spF[1] = m->z[3];
-    ta.dout = m->dout;
-    ta.loss = loss;
+    for (int l = 0; l < 3; ++l) {
+        ta.hT[l] = m->hT[l];
+        ta.dzT[l] = m->dzT[l];
+    }
+    ta.spF[0] = m->spF[0];
+    ta.spF[1] = m->spF[1];
+    ta.gpart = m->gpart;
+    ta.lpart = m->lpart;
     ta.inv_n = 1.0f / (float)n;
     TrainBufs tb{};
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < 3; ++l) {
         tb.hT[l] = ta.hT[l];
         tb.dzT[l] = ta.dzT[l];
     }
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t nblk = (n + kTcRows - 1) / kTcRows;
-    hipLaunchKernelGGL(train_cols, dim3((unsigned)std::min<int64_t>(nblk, (int64_t)ncu)), dim3(kTcThreads), 0, st, ta);
+    const int grid = (int)std::min<int64_t>(std::min<int64_t>((n + kTcRows - 1) / kTcRows, ncu), kTcMaxGrid);
+    hipLaunchKernelGGL(train_cols, dim3((unsigned)grid), dim3(kTcThreads), 0, st, ta);
     hipLaunchKernelGGL(train_dw, dim3(3 * kDwParts), dim3(64 * kDwWaves), 0, st, tb, n, m->part);
-    hipLaunchKernelGGL(train_dw_reduce, dim3(768), dim3(256), 0, st, m->part, m->G);
-    const int nsm = (int)((n + kSmChunk - 1) / kSmChunk);
-    hipLaunchKernelGGL(train_small, dim3(nsm * kSmTasks), dim3(256), 0, st, x, idx, n, ta, m->spart);
-    hipLaunchKernelGGL(train_small_reduce, dim3((kSmVals * 32 + 255) / 256), dim3(256), 0, st, m->spart, nsm, m->G);
+    // every gradient entry and the loss are written (not added) by finish_step
+    FinishArgs fa{};
+    fa.part = m->part;
+    fa.gpart = m->gpart;
+    fa.nrb = (n + kTcRows - 1) / kTcRows;
+    fa.lpart = m->lpart;
+    fa.nlp = grid * kTcWaves;
+    fa.loss = loss;
+    fa.G = m->G;
+    fa.P = m->P;
+    fa.M = m->M;
+    fa.V = m->V;
+    fa.Pi = m->Pi;
+    fa.Wr = m->Wr;
+    fa.Wt = m->Wt;
+    if (opt) {
+        m->step += 1;
+        fa.adam = 1;
+        fa.lr = opt->lr;
+        fa.b1 = opt->beta1;
+        fa.b2 = opt->beta2;
+        fa.eps = opt->eps;
+        fa.c1 = 1.0f - powf(opt->beta1, (float)m->step);
+        fa.c2 = 1.0f - powf(opt->beta2, (float)m->step);
+    }
+    hipLaunchKernelGGL(finish_step, dim3(kFinBlocks), dim3(256), 0, st, fa);
+    return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
+}
+
+}  // namespace
+
+extern "C" {
+
+int kgrt_mlp_loss_grads(kgrt_mlp* m, const float* x, const float* t, const int32_t* idx, int64_t n, float* loss,
+                        float* grads, void* stream) {
+    if (!m) return KGRT_E_INVALID_ARG;
+    DevGuard g(m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int rc = loss_grads_step(m, x, t, idx, n, loss, nullptr, st);
+    if (rc != KGRT_OK) return rc;
     if (grads && hipMemcpyAsync(grads, m->G, kNumParams * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return mlp_fail(m, KGRT_E_HIP, "gradient copy failed");
-    return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
+    return KGRT_OK;
 }
 
 int kgrt_mlp_train_step(kgrt_mlp* m, const float* x, const float* t, const int32_t* idx, int64_t n,
@@ -1499,18 +1607,8 @@ int kgrt_mlp_train_step(kgrt_mlp* m, const float* x, const float* t, const int32
     if (!(opt->lr > 0.0f && opt->beta1 >= 0.0f && opt->beta1 < 1.0f && opt->beta2 >= 0.0f && opt->beta2 < 1.0f &&
           opt->eps > 0.0f))
         return mlp_fail(m, KGRT_E_INVALID_ARG, "invalid Adam settings");
-    int rc = kgrt_mlp_loss_grads(m, x, t, idx, n, loss, nullptr, stream);
-    if (rc != KGRT_OK) return rc;
     DevGuard g(m->device);
-    hipStream_t st = (hipStream_t)stream;
-    m->step += 1;
-    const float c1 = 1.0f - powf(opt->beta1, (float)m->step), c2 = 1.0f - powf(opt->beta2, (float)m->step);
-    hipLaunchKernelGGL(adam, dim3(256), dim3(256), 0, st, m->P, m->M, m->V, m->G, kNumParams, opt->lr, opt->beta1,
-                       opt->beta2, opt->eps, c1, c2);
-    hipLaunchKernelGGL(pack_biases, dim3(4), dim3(256), 0, st, m->P, m->Pi);
-    hipLaunchKernelGGL(pack_rows, dim3(208), dim3(256), 0, st, m->P, m->Wr);
-    hipLaunchKernelGGL(pack_train, dim3(432), dim3(256), 0, st, m->P, m->Wt);
-    return hipGetLastError() == hipSuccess ? KGRT_OK : mlp_fail(m, KGRT_E_HIP, "kernel launch failed");
+    return loss_grads_step(m, x, t, idx, n, loss, opt, (hipStream_t)stream);
 }
 
 int kgrt_surrogate_features(const double* rays4, int64_t n, float* features, void* stream) {

@@ -276,8 +276,8 @@ def test_adam_steps_match_reference(ctx):
         P = mlp.get_params().astype(np.float64)
         gm, gv, gstep = mlp.get_adam()
         assert gstep == step
-        # the step's own gradient is recomputed (its atomic bias sums may differ in the last
-        # bits), which moves a parameter by at most lr * 1e-3 here; FP32 rounding of P beside it
+        # the step's gradient recomputed by loss_grads (every sum is taken in a fixed order, so
+        # it is the same gradient); FP32 rounding of the update against the FP64 reference
         np.testing.assert_allclose(P, P_ref, rtol=3e-7, atol=1e-3 * lr)
         np.testing.assert_allclose(gm, m, rtol=1e-4, atol=1e-7 * np.abs(g).max())
         np.testing.assert_allclose(gv, v, rtol=1e-4, atol=1e-9 * (g ** 2).max())
@@ -287,4 +287,44 @@ def test_adam_steps_match_reference(ctx):
     mlp.set_adam(gm, gv, 2)
     gm2, gv2, s2 = mlp.get_adam()
     assert s2 == 2 and np.array_equal(gm2, gm) and np.array_equal(gv2, gv)
+    mlp.close()
+
+
+def test_train_step_fragments_match_repack(ctx):
+    """After Adam steps the fragments written parameter by parameter at the end of each step are
+    the ones a full repack of the same parameters writes: the inference outputs, the loss and the
+    gradient are bit-identical before and after set_params(get_params()); two gradient calls on
+    the same batch are bit-identical too (no order-dependent sums)."""
+    import torch
+    from paper_1601_02063_amd import kgrt as K
+    p = reference_params(29)
+    rng = np.random.Generator(np.random.PCG64(30))
+    n = 4096
+    x = torch.from_numpy(rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)).to(ctx.device)
+    tt = np.zeros((n, 6), dtype=np.float32)
+    tt[:, 0] = rng.integers(0, 2, n)
+    tt[:, 1:5] = rng.normal(size=(n, 4))
+    tt[:, 5] = rng.integers(0, 2, n)
+    t = torch.from_numpy(tt).to(ctx.device)
+    xq = torch.from_numpy(rng.uniform(-1, 1, size=(1000, 4)).astype(np.float32)).to(ctx.device)
+    mlp = K.Mlp(ctx, max_batch=n)
+    mlp.set_params(p)
+    loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+    for _ in range(3):
+        mlp.train_step(x, t, None, n, 3e-3, loss)
+    y1 = mlp.forward(xq).cpu().numpy()
+    l1, g1 = mlp.loss_grads(x, t)
+    l1, g1 = float(l1), g1.cpu().numpy()
+    l1b, g1b = mlp.loss_grads(x, t)
+    assert float(l1b) == l1 and np.array_equal(g1b.cpu().numpy(), g1)
+    P = mlp.get_params()
+    gm, gv, gstep = mlp.get_adam()
+    assert not np.array_equal(P, p)
+    mlp.set_params(P)
+    mlp.set_adam(gm, gv, gstep)
+    y2 = mlp.forward(xq).cpu().numpy()
+    l2, g2 = mlp.loss_grads(x, t)
+    assert np.array_equal(y1, y2)
+    assert float(l2) == l1
+    assert np.array_equal(g2.cpu().numpy(), g1)
     mlp.close()
