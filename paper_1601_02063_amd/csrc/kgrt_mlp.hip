@@ -9,10 +9,11 @@
 // activations in registers through all layers, and the weights come as MFMA
 // fragments in a permuted order that lets one layer's accumulators serve as
 // the next layer's operand directly. Training runs the forward and backward
-// of every row in one kernel (train_cols), stores the per-sample arrays
-// tile-major, and takes the gradient products that contract over the batch
-// in separate kernels (train_dw, train_small) over row ranges added in a
-// fixed order.
+// of every row in one kernel (train_cols), which also takes the input and
+// output layers' gradient products over its rows, stores the per-sample arrays
+// of the hidden layers tile-major for the hidden layers' gradient products
+// (train_dw), and one more kernel (finish_step) adds every partial sum in a
+// fixed order and applies Adam.
 //
 // Parameters: one flat FP32 vector, per layer W[out][in] then b[out] (the FP32
 // master copy); the BF16 copies and fragment arrays derived from it are
@@ -237,13 +238,14 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
 }
 
 // Per-sample arrays of the training step are stored tile-major,
-// [B/64][256 units][64 rows] BF16: a tile's values for one unit are 128
-// contiguous bytes, and the whole tile is one 32 KB block.
-__device__ __forceinline__ int64_t tm_index(int u, int64_t b) { return (b >> 6) * (kH * 64) + u * 64 + (b & 63); }
+// [B/16][256 units][16 rows] BF16: a 16-row tile's values for one unit are 32
+// contiguous bytes, so the training pass writes a unit block of a tile (16 units)
+// as 512 contiguous bytes, and the whole tile is one 8 KB block.
+__device__ __forceinline__ int64_t tm_index(int u, int64_t b) { return (b >> 4) * (kH * 16) + u * 16 + (b & 15); }
 
 // The hidden layers' gradient products dL/dW_l = sum_b dz_l[b] h_{l-1}[b]^T and
 // dL/db_l = sum_b dz_l[b] (l = 2..4) over kDwParts ranges of rows per layer (train_dw),
-// added up in order by train_dw_reduce.
+// added up in order by finish_step.
 constexpr int kDwParts = 85;
 struct TrainBufs {
     __bf16* hT[3];   // h of layers 1..3
@@ -260,11 +262,11 @@ struct TrainBufs {
 //   backward: dh4 = dL/do W5 (both as hi + lo), dz_l = dh_l SiLU'(z_l),
 //     dh_{l-1} = dz_l W_l on MFMA with W_l^T fragments (l = 4..2), SiLU'(z1)
 //     recomputed from x.
-// h1..h4 and dz1..dz4 go to global memory tile-major (transposed by a product
-// with the identity on MFMA, 4 rows of one unit per lane), dL/do row-major: every
-// sum over the batch (the weight and bias gradients) is taken by train_dw and
-// train_small over row ranges, added in a fixed order, so a step's gradient
-// does not depend on the order blocks run in.
+// h1..h3 and dz2..dz4 go to global memory tile-major (transposed by a product
+// with the identity on MFMA, 4 rows of one unit per lane) for train_dw; the
+// products of dz1 with x and of h4 with dL/do are taken here over each block of
+// rows. Every sum over the batch is added in a fixed order (finish_step), so a
+// step's gradient does not depend on the order blocks run in.
 //
 // Training fragment array Wt (BF16, 1 KB fragments, unscaled weights):
 //   W1 hi + lo [jb 16][lane][8] (as the inference kernel's input layer);
@@ -319,7 +321,7 @@ struct TrainRowsArgs {
     const float* P;
     const __bf16* Wr;
     const __bf16* Wt;
-    __bf16* hT[3];   // h1..h3, tile-major [B/64][256][64]
+    __bf16* hT[3];   // h1..h3, tile-major [B/16][256][16]
     __bf16* dzT[3];  // dL/dz of layers 2..4, tile-major
     __bf16* spF[2];  // SiLU'(z) of layers 2 and 3 in the accumulator layout [B/16][jb 16][lane 64][4]
     float* gpart;    // the input and output layers' gradient partials per 128-row block (see below)
@@ -765,7 +767,8 @@ train_dw(const TrainBufs B, int64_t n, float* __restrict__ part) {
 #pragma unroll
         for (int i = 0; i < 64 / kDwWaves; ++i) {
             const int f = wave + kDwWaves * i, hh = f & 1, ub = (f >> 1) & 15;
-            const __bf16* src = ((f < 32) ? dz : h) + tile * (kH * 64) + (16 * ub + lr) * 64 + 16 * lg + 8 * hh;
+            // rows 16 lg + 8 hh .. + 7 of the 64-row step: 16-row tile 4 tile + lg
+            const __bf16* src = ((f < 32) ? dz : h) + (4 * tile + lg) * (kH * 16) + (16 * ub + lr) * 16 + 8 * hh;
             __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                              (__attribute__((address_space(3))) void*)&stg[buf][f][0], 16, 0, 0);
         }
