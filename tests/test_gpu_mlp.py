@@ -68,19 +68,21 @@ def test_forward_matches_reference(ctx):
     mlp.close()
 
 
-def test_gradients_match_reference(ctx):
+@pytest.mark.parametrize("n", [512, 12832])
+def test_gradients_match_reference(ctx, n):
+    """A gathered batch against the FP64 reference; n = 12832 is 101 blocks of 128 rows, the last
+    one of 32 rows (two tiles), and a half-filled last 64-row step of the weight-gradient products."""
     import torch
     from paper_1601_02063_amd import kgrt as K
     p = reference_params(5)
     rng = np.random.Generator(np.random.PCG64(8))
-    n = 512
     x = rng.uniform(-1, 1, size=(n + 100, 4)).astype(np.float32)
     t = np.zeros((n + 100, 6), dtype=np.float32)
     t[:, 0] = rng.integers(0, 2, n + 100)
     t[:, 1:5] = rng.normal(size=(n + 100, 4))
     t[:, 5] = rng.integers(0, 2, n + 100)
     idx = rng.permutation(n + 100)[:n].astype(np.int32)  # gathered batch
-    mlp = K.Mlp(ctx, max_batch=1024)
+    mlp = K.Mlp(ctx, max_batch=max(1024, n))
     mlp.set_params(p)
     loss, g = mlp.loss_grads(torch.from_numpy(x).to(ctx.device), torch.from_numpy(t).to(ctx.device),
                              torch.from_numpy(idx).to(ctx.device))
