@@ -79,7 +79,10 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 constexpr int64_t kWrFrag = 64 * 8;
 constexpr int64_t kWrHid = 0, kWrW1 = 3 * 16 * 8 * kWrFrag, kWrW5 = kWrW1 + 16 * kWrFrag;
 constexpr int64_t kWrSize = kWrW5 + 8 * 2 * kWrFrag;
-constexpr int kRowsRB = 2, kRowsWaves = 8, kRowsThreads = 64 * kRowsWaves, kRowsTile = 16 * kRowsRB * kRowsWaves;
+// three 16-row tiles per wave: each 1 KB fragment read from LDS feeds three products (the 8 waves
+// of a block read every fragment of a layer, so LDS traffic per product falls as RB grows), at
+// two waves per SIMD
+constexpr int kRowsRB = 3, kRowsWaves = 8, kRowsThreads = 64 * kRowsWaves, kRowsTile = 16 * kRowsRB * kRowsWaves;
 
 __host__ __device__ constexpr int kperm(int s, int g, int e) { return 32 * s + 4 * g + (e < 4 ? e : 12 + e); }
 
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(256) pack_rows(const float* __restrict__ P, __
     }
 }
 
-__global__ void __launch_bounds__(kRowsThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(kRowsThreads) __attribute__((amdgpu_waves_per_eu(kRowsWaves / 4, kRowsWaves / 4)))
 mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__ P, const __bf16* __restrict__ Wr,
                const float* __restrict__ Pi, float* __restrict__ y) {
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
@@ -196,9 +199,9 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
                     __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, RB, 0);
                         if (i < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x002, 3 * RB, 0);
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
