@@ -834,10 +834,10 @@ __device__ __forceinline__ int dw_entry(int j) {
 
 // ------------------------------------------------- finishing a step
 // One launch takes every gradient value from its partial sums in a fixed order: the hidden
-// layers' weights and biases over train_dw's kDwParts parts (one thread per value), the input
-// and output layers' over the training pass's 128-row blocks (32 consecutive threads per value:
-// thread k adds blocks k, k + 32, ... in order, then a fixed butterfly combines the 32 sums),
-// and the loss
+// layers' weights and biases over train_dw's kDwParts parts (one thread per value, adding the
+// parts in order), the input and output layers' over the training pass's 128-row blocks (16
+// threads per value, each adding every 16th block in order, then the 16 sums in order), and the
+// loss
 // over the training pass's per-wave partials (the last block). For a training step the thread
 // holding a gradient then applies Adam to its parameter (Kingma & Ba 2015:
 // m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
