@@ -368,7 +368,11 @@ typedef struct kgrt_adam {
 int64_t kgrt_mlp_num_params(void);
 /* Creates a network on the current device of ctx with workspace for batches
  * of up to max_batch samples (16 <= max_batch <= 2^24, a multiple of 16).
- * Parameters are undefined until kgrt_mlp_set_params. */
+ * Parameters are undefined until kgrt_mlp_set_params. The network object owns
+ * its parameters, Adam state, gradient and the training workspace (per-sample
+ * activations and partial sums): its training and gradient calls share that
+ * workspace, so calls on one object must be ordered (one stream, or streams
+ * the caller synchronises). */
 int kgrt_mlp_create(kgrt_ctx* ctx, int64_t max_batch, kgrt_mlp** out);
 int kgrt_mlp_destroy(kgrt_mlp* mlp);
 const char* kgrt_mlp_last_error(const kgrt_mlp* mlp);
