@@ -201,7 +201,7 @@ mlp_infer_rows(const float* __restrict__ x, int64_t n, const float* __restrict__
                     for (int i = 0; i < 8; ++i) {
                         __builtin_amdgcn_sched_group_barrier(0x008, RB, 0);
                         if (i < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x002, 3 * RB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x002, 2 * RB, 0);
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
