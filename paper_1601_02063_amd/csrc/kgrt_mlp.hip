@@ -1373,10 +1373,14 @@ struct kgrt_mlp {
     // render workspace (grown on demand): features, outputs, fallback list and its integration
     float *r_feat = nullptr, *r_pred = nullptr, *r_tab = nullptr;
     double* r_part = nullptr;  // per-image flux partial sums [nimg][kFluxBlocks]
-    int64_t* r_idx = nullptr;
-    int32_t* r_st = nullptr;
-    double *r_rays = nullptr, *r_I = nullptr;
-    unsigned long long* r_cnt = nullptr;
+    // two fallback lists: one is integrated on the side stream while the next group of pixels
+    // fills the other; an event per list marks its integration and composite done
+    int64_t* r_idx[2] = {};
+    int32_t* r_st[2] = {};
+    double *r_rays[2] = {}, *r_I[2] = {};
+    unsigned long long* r_cnt[2] = {};
+    hipStream_t r_side = nullptr;
+    hipEvent_t r_ev_fill = nullptr, r_ev_done[2] = {};
     int64_t r_cap = 0, r_list_cap = 0, r_tab_cap = 0;
     std::string err;
 };
@@ -1409,11 +1413,17 @@ int64_t kgrt_mlp_num_params(void) { return kNumParams; }
 int kgrt_mlp_destroy(kgrt_mlp* m) {
     if (!m) return KGRT_OK;
     DevGuard g(m->device);
+    if (m->r_side) (void)hipStreamSynchronize(m->r_side);
     void* ptrs[] = {m->P, m->M, m->V, m->G, m->Wr, m->Wt, m->Pi, m->part, m->gpart, m->lpart, m->r_feat, m->r_pred,
-                    m->r_tab, m->r_part, m->r_idx, m->r_st, m->r_rays, m->r_I, m->r_cnt,
+                    m->r_tab, m->r_part, m->r_idx[0], m->r_st[0], m->r_rays[0], m->r_I[0], m->r_cnt[0],
+                    m->r_idx[1], m->r_st[1], m->r_rays[1], m->r_I[1], m->r_cnt[1],
                     m->hT[0], m->hT[1], m->hT[2], m->dzT[0], m->dzT[1], m->dzT[2], m->spF[0], m->spF[1]};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (m->r_ev_fill) (void)hipEventDestroy(m->r_ev_fill);
+    for (hipEvent_t e : m->r_ev_done)
+        if (e) (void)hipEventDestroy(e);
+    if (m->r_side) (void)hipStreamDestroy(m->r_side);
     delete m;
     return KGRT_OK;
 }
@@ -1715,21 +1725,32 @@ int ensure_render_ws(kgrt_mlp* m, int64_t seg, int64_t list, int32_t nimg) {
     }
     if (list > m->r_list_cap) {
         if (hipDeviceSynchronize() != hipSuccess) return KGRT_E_HIP;
-        void* old[] = {m->r_idx, m->r_st, m->r_rays, m->r_I};
-        for (void* p : old)
-            if (p) (void)hipFree(p);
-        m->r_idx = nullptr;
-        m->r_st = nullptr;
-        m->r_rays = m->r_I = nullptr;
+        for (int b = 0; b < 2; ++b) {
+            void* old[] = {m->r_idx[b], m->r_st[b], m->r_rays[b], m->r_I[b]};
+            for (void* p : old)
+                if (p) (void)hipFree(p);
+            m->r_idx[b] = nullptr;
+            m->r_st[b] = nullptr;
+            m->r_rays[b] = m->r_I[b] = nullptr;
+        }
         m->r_list_cap = 0;
-        bool ok = hipMalloc(&m->r_idx, (size_t)list * sizeof(int64_t)) == hipSuccess &&
-                  hipMalloc(&m->r_st, (size_t)list * sizeof(int32_t)) == hipSuccess &&
-                  hipMalloc(&m->r_rays, (size_t)list * 4 * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&m->r_I, (size_t)list * sizeof(double)) == hipSuccess;
-        if (!ok) return KGRT_E_NOMEM;
+        for (int b = 0; b < 2; ++b) {
+            bool ok = hipMalloc(&m->r_idx[b], (size_t)list * sizeof(int64_t)) == hipSuccess &&
+                      hipMalloc(&m->r_st[b], (size_t)list * sizeof(int32_t)) == hipSuccess &&
+                      hipMalloc(&m->r_rays[b], (size_t)list * 4 * sizeof(double)) == hipSuccess &&
+                      hipMalloc(&m->r_I[b], (size_t)list * sizeof(double)) == hipSuccess;
+            if (!ok) return KGRT_E_NOMEM;
+        }
         m->r_list_cap = list;
     }
-    if (!m->r_cnt && hipMalloc(&m->r_cnt, sizeof(unsigned long long)) != hipSuccess) return KGRT_E_NOMEM;
+    for (int b = 0; b < 2; ++b)
+        if (!m->r_cnt[b] && hipMalloc(&m->r_cnt[b], sizeof(unsigned long long)) != hipSuccess) return KGRT_E_NOMEM;
+    // default priority, not synchronised with the null stream: the events below order it
+    if (!m->r_side && hipStreamCreateWithFlags(&m->r_side, hipStreamNonBlocking) != hipSuccess) return KGRT_E_HIP;
+    if (!m->r_ev_fill && hipEventCreateWithFlags(&m->r_ev_fill, hipEventDisableTiming) != hipSuccess) return KGRT_E_HIP;
+    for (int b = 0; b < 2; ++b)
+        if (!m->r_ev_done[b] && hipEventCreateWithFlags(&m->r_ev_done[b], hipEventDisableTiming) != hipSuccess)
+            return KGRT_E_HIP;
     if (nimg > m->r_tab_cap) {
         if (m->r_tab) {
             if (hipDeviceSynchronize() != hipSuccess) return KGRT_E_HIP;
@@ -1784,7 +1805,9 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
     hipStream_t st = (hipStream_t)stream;
     // Pixels of all images, concatenated, are handled in groups of at most
     // kListMax pixels; a group runs the network in segments of at most kSegMax
-    // pixels and sends all its fallback rays to the integrator in one launch.
+    // pixels and sends all its fallback rays to the integrator in one launch,
+    // on a side stream, while the caller's stream goes on with the next group
+    // (into the other of two fallback lists).
     constexpr int64_t kSegMax = int64_t(1) << 22, kListMax = int64_t(1) << 26;
     int64_t total = 0;
     for (int32_t k = 0; k < nimg; ++k) total += (int64_t)cams[k].nx * cams[k].ny;
@@ -1805,21 +1828,32 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
     if (fallback_counts) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(256), 0, st, fallback_counts, (int64_t)nimg);
     const RenderCfg cfg{fb->p_lo, fb->p_hi, fb->crit_band, fb->edge_band, fb->g_tol, fb->grad_max};
     // one ray list covers images of one observer distance and azimuth
+    int cur = 0;  // the list being filled
     auto flush = [&](int64_t listed, double r_obs, double phi_obs) -> int {
+        if (hipEventRecord(m->r_ev_fill, st) != hipSuccess || hipStreamWaitEvent(m->r_side, m->r_ev_fill, 0) != hipSuccess)
+            return mlp_fail(m, KGRT_E_HIP, "stream ordering failed");
         kgrt_outputs o{};
-        o.status = m->r_st;
-        o.intensity = m->r_I;
-        int r = kgrt_trace_rays_dev(ctx, m->r_rays, (const int64_t*)m->r_cnt, listed, r_obs, phi_obs, disk, nullptr, 0,
-                                    integ, &o, stream);
+        o.status = m->r_st[cur];
+        o.intensity = m->r_I[cur];
+        int r = kgrt_trace_rays_dev(ctx, m->r_rays[cur], (const int64_t*)m->r_cnt[cur], listed, r_obs, phi_obs, disk,
+                                    nullptr, 0, integ, &o, m->r_side);
         if (r != KGRT_OK) return mlp_fail(m, r, "fallback integration failed");
         const unsigned grid = (unsigned)std::min<int64_t>(4096, (listed + 255) / 256);
-        hipLaunchKernelGGL(composite_kernel, dim3(grid), dim3(256), 0, st, m->r_cnt, listed, m->r_idx, m->r_I, m->r_st,
-                           intensity, status, total);
+        hipLaunchKernelGGL(composite_kernel, dim3(grid), dim3(256), 0, m->r_side, m->r_cnt[cur], listed, m->r_idx[cur],
+                           m->r_I[cur], m->r_st[cur], intensity, status, total);
+        if (hipEventRecord(m->r_ev_done[cur], m->r_side) != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "event failed");
+        // the other list is reused once its previous integration and composite are done
+        cur ^= 1;
+        if (hipStreamWaitEvent(st, m->r_ev_done[cur], 0) != hipSuccess)
+            return mlp_fail(m, KGRT_E_HIP, "stream ordering failed");
+        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, m->r_cnt[cur], (int64_t)1);
         return KGRT_OK;
     };
     int64_t off = 0, listed = 0;
     double g_robs = cams[0].r_obs, g_phi = cams[0].phi_obs_deg;
-    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, m->r_cnt, (int64_t)1);
+    for (int b = 0; b < 2; ++b)
+        if (hipEventRecord(m->r_ev_done[b], st) != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "event failed");
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, m->r_cnt[cur], (int64_t)1);
     for (int32_t k = 0; k < nimg; ++k) {
         const kgrt_camera& c = cams[k];
         const int64_t n = (int64_t)c.nx * c.ny;
@@ -1846,7 +1880,6 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
         for (int64_t p0 = 0; p0 < n;) {
             if (listed > 0 && (listed == list_cap || c.r_obs != g_robs || c.phi_obs_deg != g_phi)) {
                 if ((rc = flush(listed, g_robs, g_phi)) != KGRT_OK) return rc;
-                hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, m->r_cnt, (int64_t)1);
                 listed = 0;
             }
             g_robs = c.r_obs;
@@ -1858,13 +1891,17 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
             if (rc != KGRT_OK) return rc;
             hipLaunchKernelGGL(decode_kernel, dim3(grid), dim3(256), 0, st, im, p0, cnt, m->r_pred,
                                m->r_tab + (size_t)k * kCritBins, cfg, intensity + off, status ? status + off : nullptr,
-                               off, m->r_cnt, m->r_idx, m->r_rays, fallback_counts ? fallback_counts + k : nullptr);
+                               off, m->r_cnt[cur], m->r_idx[cur], m->r_rays[cur],
+                               fallback_counts ? fallback_counts + k : nullptr);
             listed += cnt;
             p0 += cnt;
         }
         off += n;
     }
     if (listed > 0 && (rc = flush(listed, g_robs, g_phi)) != KGRT_OK) return rc;
+    // the caller's stream continues after every integration and composite
+    for (int b = 0; b < 2; ++b)
+        if (hipStreamWaitEvent(st, m->r_ev_done[b], 0) != hipSuccess) return mlp_fail(m, KGRT_E_HIP, "stream ordering failed");
     if (flux) {
         off = 0;
         for (int32_t k = 0; k < nimg; ++k) {
