@@ -441,20 +441,24 @@ typedef struct kgrt_fallback {
 int kgrt_critical_curve(double a, double incl_deg, float* radius_host, int32_t nbins);
 
 /* Thin-disk images (section 4.3, j = r^-3, I = g^3 j) from the surrogate, with
- * fallback rays (kgrt_fallback) re-integrated by the FP64 integrator on the
- * same stream: features -> network -> decode (crossing-radius polish, Keplerian
- * g at it, fallback test) -> device-built ray list -> integrator -> composite
- * -> per-image flux (each summed in a fixed order). The fallback rays of
+ * fallback rays (kgrt_fallback) re-integrated by the FP64 integrator:
+ * features -> network -> decode (crossing-radius polish, Keplerian g at it,
+ * fallback test) -> device-built ray list -> integrator -> composite ->
+ * per-image flux (each summed in a fixed order). The fallback rays of
  * consecutive images with the same r_obs and phi_obs, up to 2^26 pixels, go to
- * the integrator as one list (one launch). Outputs (device): intensity [total]
+ * the integrator as one list (one launch), on a stream of the network object
+ * ordered by events, while `stream` goes on with the next images (into a
+ * second list); `stream` waits for every list before the flux sums, so the
+ * call is ordered on `stream` like the others. The integration uses ctx's
+ * work queue: ctx must not trace on another stream meanwhile. Outputs (device): intensity [total]
  * (images concatenated, pixel j*nx+i), status [total] or NULL (KGRT_FALLBACK
  * set on re-integrated rays; others carry the predicted capture/escape bit),
  * flux [nimg] or NULL (sum of intensity per image), fallback_counts [nimg] or
  * NULL. Everything, the critical-curve tables included (built on the device,
  * the same as kgrt_critical_curve's), is asynchronous on `stream`; the host
  * waits only when the workspace grows. Workspace grows on demand
- * and is kept by the network object (about 60 bytes per pixel, at most 2^26
- * pixels' worth, plus 36 bytes per pixel of at most 2^22). */
+ * and is kept by the network object (about 104 bytes per pixel, two lists of
+ * at most 2^26 pixels' worth, plus 36 bytes per pixel of at most 2^22). */
 int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* mlp, const kgrt_camera* cams, int32_t nimg,
                           const kgrt_model* disk, const kgrt_integrator* integ, const kgrt_fallback* fb,
                           double* intensity_dev, int32_t* status_dev, double* flux_dev,
