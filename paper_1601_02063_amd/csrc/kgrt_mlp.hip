@@ -1218,7 +1218,7 @@ __global__ void __launch_bounds__(256) flux_partial(const double* __restrict__ I
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
