@@ -1381,6 +1381,7 @@ struct kgrt_mlp {
     unsigned long long* r_cnt[2] = {};
     hipStream_t r_side = nullptr;
     hipEvent_t r_ev_fill = nullptr, r_ev_done[2] = {};
+    kgrt_ctx* r_ctx = nullptr;  // the context of the fallback integrations (its own work queue)
     int64_t r_cap = 0, r_list_cap = 0, r_tab_cap = 0;
     std::string err;
 };
@@ -1424,6 +1425,7 @@ int kgrt_mlp_destroy(kgrt_mlp* m) {
     for (hipEvent_t e : m->r_ev_done)
         if (e) (void)hipEventDestroy(e);
     if (m->r_side) (void)hipStreamDestroy(m->r_side);
+    if (m->r_ctx) (void)kgrt_ctx_destroy(m->r_ctx);
     delete m;
     return KGRT_OK;
 }
@@ -1751,6 +1753,14 @@ int ensure_render_ws(kgrt_mlp* m, int64_t seg, int64_t list, int32_t nimg) {
     for (int b = 0; b < 2; ++b)
         if (!m->r_ev_done[b] && hipEventCreateWithFlags(&m->r_ev_done[b], hipEventDisableTiming) != hipSuccess)
             return KGRT_E_HIP;
+    // A fallback list holds the image's hardest rays (most of them near the critical curve):
+    // lanes are refilled once 16 of a wave's are idle, which measured fastest for such lists
+    // (one lane at a time, the default for whole images, spends more on refills than it saves)
+    if (!m->r_ctx) {
+        if (kgrt_ctx_create(m->device, &m->r_ctx) != KGRT_OK) return KGRT_E_HIP;
+        const kgrt_launch L{256, 0, 16, KGRT_LAUNCH_PERSISTENT};
+        if (kgrt_ctx_set_launch(m->r_ctx, &L) != KGRT_OK) return KGRT_E_HIP;
+    }
     if (nimg > m->r_tab_cap) {
         if (m->r_tab) {
             if (hipDeviceSynchronize() != hipSuccess) return KGRT_E_HIP;
@@ -1835,9 +1845,9 @@ int kgrt_surrogate_render(kgrt_ctx* ctx, kgrt_mlp* m, const kgrt_camera* cams, i
         kgrt_outputs o{};
         o.status = m->r_st[cur];
         o.intensity = m->r_I[cur];
-        int r = kgrt_trace_rays_dev(ctx, m->r_rays[cur], (const int64_t*)m->r_cnt[cur], listed, r_obs, phi_obs, disk,
-                                    nullptr, 0, integ, &o, m->r_side);
-        if (r != KGRT_OK) return mlp_fail(m, r, "fallback integration failed");
+        int r = kgrt_trace_rays_dev(m->r_ctx, m->r_rays[cur], (const int64_t*)m->r_cnt[cur], listed, r_obs, phi_obs,
+                                    disk, nullptr, 0, integ, &o, m->r_side);
+        if (r != KGRT_OK) return mlp_fail(m, r, std::string("fallback integration failed: ") + kgrt_last_error(m->r_ctx));
         const unsigned grid = (unsigned)std::min<int64_t>(4096, (listed + 255) / 256);
         hipLaunchKernelGGL(composite_kernel, dim3(grid), dim3(256), 0, m->r_side, m->r_cnt[cur], listed, m->r_idx[cur],
                            m->r_I[cur], m->r_st[cur], intensity, status, total);
