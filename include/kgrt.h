@@ -166,7 +166,9 @@ typedef struct kgrt_outputs {
 typedef struct kgrt_launch {
     int32_t block;          /* threads per block: 64, 128 or 256 (default 256) */
     int32_t blocks_per_cu;  /* resident blocks per compute unit (default: occupancy limit) */
-    int32_t refill_min;     /* refill a wave only when at least this many lanes are idle (1..64, default 1) */
+    int32_t refill_min;     /* refill a wave only when at least this many lanes are idle (1..64; default
+                               64 for the one-frequency torus, gridded-plasma and thin-disk kernels,
+                               1 for the others) */
     int32_t mode;           /* KGRT_LAUNCH_* (default persistent) */
 } kgrt_launch;
 
@@ -264,7 +266,7 @@ int kgrt_plan_launch(kgrt_plan* plan, const kgrt_outputs* out, uint32_t flags, v
 /* Times candidate launch shapes on the plan's first <= 524288 rays: the
  * persistent kernel (many rays per lane) at block 64/128/256, residency (the
  * occupancy rule, decided on the whole plan, or two or three waves per SIMD)
- * and refill granularity 1 or 16, and one ray per thread at block 64/128/256.
+ * and refill granularity 1, 16 or 64, and one ray per thread at block 64/128/256.
  * The fastest is kept for later launches and written to *best if best !=
  * NULL. Synchronous: it waits for `stream`. Outputs of the sampled rays are
  * overwritten. */

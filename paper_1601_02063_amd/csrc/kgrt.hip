@@ -233,6 +233,15 @@ template <int MODEL, int NF> struct WavesPerEU {
             : (NF == 1 ? KGRT_WAVES_TORUS
                        : ((AccInLds<NF>::value || RayCountResidency<NF>::value) ? 3 : KGRT_WAVES_TORUS_MULTI));
 };
+// Refill granularity when the caller sets none: the one-frequency torus, gridded-plasma and
+// thin-disk kernels refill a wave only when all 64 lanes are idle (a wave takes 64 consecutive
+// rays of the queue, neighbouring pixels that stay in step: less divergence and refill work,
+// 4-12% faster than refilling lane by lane, measured); the others refill lane by lane (the
+// eight-frequency kernel was 2% slower at 64).
+template <int MODEL, int NF> struct DefaultRefill {
+    static constexpr int value =
+        (NF == 1 && (MODEL == KGRT_MODEL_TORUS || MODEL == KGRT_MODEL_GRID || MODEL == KGRT_MODEL_THIN_DISK)) ? 64 : 1;
+};
 // dynamic LDS bytes of one block of `block` threads
 template <int NF> constexpr size_t acc_lds_bytes(int block) {
     return AccInLds<NF>::value ? (size_t)3 * NF * block * sizeof(double) : 0;
@@ -892,7 +901,8 @@ int launch_one(kgrt_ctx* ctx, const LaunchEnv& env, KParams P, hipStream_t st) {
     }
     P.counter = env.counter;
     P.naive = (env.launch.mode == KGRT_LAUNCH_ONE_RAY_PER_THREAD) ? 1 : 0;
-    P.refill_min = (env.launch.refill_min >= 1 && env.launch.refill_min <= 64) ? env.launch.refill_min : 1;
+    P.refill_min = (env.launch.refill_min >= 1 && env.launch.refill_min <= 64) ? env.launch.refill_min
+                                                                                : DefaultRefill<MODEL, NF>::value;
     const int64_t total = (env.limit >= 0) ? std::min<int64_t>(env.limit, P.nrays) : P.nrays;
     const int64_t cap = env.rec_cap;
     for (int64_t base = 0; base < total; base += cap) {
@@ -1346,7 +1356,7 @@ int kgrt_plan_autotune(kgrt_plan* plan, const kgrt_outputs* out, void* stream, k
         // blocks per CU: the occupancy rule (0), then two and three waves per SIMD explicitly
         const int waves2 = std::max(1, 2 * 4 * 64 / block), waves3 = std::max(1, 3 * 4 * 64 / block);
         for (int per_cu : {0, waves2, waves3})
-            for (int refill : {1, 16}) cand.push_back(kgrt_launch{block, per_cu, refill, KGRT_LAUNCH_PERSISTENT});
+            for (int refill : {1, 16, 64}) cand.push_back(kgrt_launch{block, per_cu, refill, KGRT_LAUNCH_PERSISTENT});
         cand.push_back(kgrt_launch{block, 0, 1, KGRT_LAUNCH_ONE_RAY_PER_THREAD});
     }
     for (const kgrt_launch& c : cand) {
