@@ -58,19 +58,19 @@ FLOPS_PER_ATTEMPT = {"torus": (1287.0, "calibrated"), "thin_disk": (852.0, "cali
 # VALU lane utilisation of the dominant kernel (useful FP64 FLOPs / FP64 lane
 # slots issued, rocprofv3 counters), valid for the sources it was taken on; see
 # profiles/trace_kernel_flop_calibration.md.
-HEAD_MD5 = "831eabb44ef1cc1e9ba1b13b20df89e4"
+HEAD_MD5 = "30905ad1bf94774f8d905f9cc6655a3a"
 LANE_UTILISATION = {"torus": {"value": 0.940, "source_md5": HEAD_MD5},
                     "batch": {"value": 0.892, "source_md5": HEAD_MD5},
                     "thin_disk": {"value": 0.910, "source_md5": HEAD_MD5},
                     "grid": {"value": 0.939, "source_md5": HEAD_MD5}}
 
-TRAFFIC = {"torus": {"bytes": 132676548, "source_md5": HEAD_MD5},
+TRAFFIC = {"torus": {"bytes": 132671652, "source_md5": HEAD_MD5},
            # the one launch of the 256-image plan, see profiles/batch256_trace_kernel_traffic.md
-           "batch": {"bytes": 22648429565, "source_md5": HEAD_MD5},
+           "batch": {"bytes": 22641750604, "source_md5": HEAD_MD5},
            # the 1024^2 thin-disk image, see profiles/trace_kernel_flop_calibration.md
-           "thin_disk": {"bytes": 317102561, "source_md5": HEAD_MD5},
+           "thin_disk": {"bytes": 316799880, "source_md5": HEAD_MD5},
            # the 1024^2 image of the gridded snapshot, see profiles/grid_1024_kernel_trace.md
-           "grid": {"bytes": 3639434533, "source_md5": HEAD_MD5}}
+           "grid": {"bytes": 3613276482, "source_md5": HEAD_MD5}}
 
 
 def kernel_source_md5() -> str:
@@ -291,10 +291,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "rays": n, "nfreq": len(freqs), "launch": {
             "block": args.block or 256, "blocks_per_cu": args.blocks_per_cu or "occupancy",
-            "refill_min": args.refill_min or (64 if (len(freqs) <= 1 and mod.kind in (K.MODEL_TORUS, K.MODEL_GRID,
-                                                                                        K.MODEL_THIN_DISK,
-                                                                                        K.MODEL_GEODESIC))
-                                              else 1)}},
+            "refill_min": args.refill_min or (64 if len(freqs) < 8 else 1)}},
         "kernel_ms": round(ms_mean, 4),
         "kernel_ms_min": round(min(kern_ms), 4),
         "rays_per_s": round(n / (ms_mean * 1e-3), 1),

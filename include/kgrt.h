@@ -167,8 +167,7 @@ typedef struct kgrt_launch {
     int32_t block;          /* threads per block: 64, 128 or 256 (default 256) */
     int32_t blocks_per_cu;  /* resident blocks per compute unit (default: occupancy limit) */
     int32_t refill_min;     /* refill a wave only when at least this many lanes are idle (1..64; default
-                               64 for the one-frequency torus, gridded-plasma and thin-disk kernels,
-                               1 for the others) */
+                               64, and 1 for eight and more frequencies) */
     int32_t mode;           /* KGRT_LAUNCH_* (default persistent) */
 } kgrt_launch;
 

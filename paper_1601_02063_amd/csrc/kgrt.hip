@@ -233,14 +233,13 @@ template <int MODEL, int NF> struct WavesPerEU {
             : (NF == 1 ? KGRT_WAVES_TORUS
                        : ((AccInLds<NF>::value || RayCountResidency<NF>::value) ? 3 : KGRT_WAVES_TORUS_MULTI));
 };
-// Refill granularity when the caller sets none: the one-frequency torus, gridded-plasma and
-// thin-disk kernels refill a wave only when all 64 lanes are idle (a wave takes 64 consecutive
-// rays of the queue, neighbouring pixels that stay in step: less divergence and refill work,
-// 4-12% faster than refilling lane by lane, measured); the others refill lane by lane (the
-// eight-frequency kernel was 2% slower at 64).
+// Refill granularity when the caller sets none: a wave refills only when all 64 lanes are idle
+// (it takes 64 consecutive rays of the queue, neighbouring pixels that stay in step: less
+// divergence and refill work; 2-13% faster than refilling lane by lane on every model up to four
+// frequencies, measured), except the kernels of eight and more frequencies, which refill lane by
+// lane (the eight-frequency kernel was 2-8% slower at 8..64).
 template <int MODEL, int NF> struct DefaultRefill {
-    static constexpr int value =
-        (NF == 1 && (MODEL == KGRT_MODEL_TORUS || MODEL == KGRT_MODEL_GRID || MODEL == KGRT_MODEL_THIN_DISK)) ? 64 : 1;
+    static constexpr int value = (NF < 8) ? 64 : 1;
 };
 // dynamic LDS bytes of one block of `block` threads
 template <int NF> constexpr size_t acc_lds_bytes(int block) {
