@@ -452,7 +452,7 @@ int kgrt_critical_curve(double a, double incl_deg, float* radius_host, int32_t n
  * second list); `stream` waits for every list before the flux sums, so the
  * call is ordered on `stream` like the others. The integration runs on a
  * context of the network object (its own work queue, so ctx may trace on
- * other streams meanwhile), with lanes refilled once 16 of a wave's are idle
+ * other streams meanwhile), with lanes refilled once 8 of a wave's are idle
  * (kgrt_launch.refill_min), the fastest measured for fallback lists; ctx is
  * the caller's context on the network's device. Outputs (device): intensity [total]
  * (images concatenated, pixel j*nx+i), status [total] or NULL (KGRT_FALLBACK

@@ -1754,11 +1754,12 @@ int ensure_render_ws(kgrt_mlp* m, int64_t seg, int64_t list, int32_t nimg) {
         if (!m->r_ev_done[b] && hipEventCreateWithFlags(&m->r_ev_done[b], hipEventDisableTiming) != hipSuccess)
             return KGRT_E_HIP;
     // A fallback list holds the image's hardest rays (most of them near the critical curve):
-    // lanes are refilled once 16 of a wave's are idle, which measured fastest for such lists
-    // (one lane at a time, the default for whole images, spends more on refills than it saves)
+    // lanes are refilled once 8 of a wave's are idle, which measured fastest for such lists (one
+    // lane at a time spends more on refills than it saves; whole waves leave lanes idle behind
+    // the wave's longest ray, which here differ widely)
     if (!m->r_ctx) {
         if (kgrt_ctx_create(m->device, &m->r_ctx) != KGRT_OK) return KGRT_E_HIP;
-        const kgrt_launch L{256, 0, 16, KGRT_LAUNCH_PERSISTENT};
+        const kgrt_launch L{256, 0, 8, KGRT_LAUNCH_PERSISTENT};
         if (kgrt_ctx_set_launch(m->r_ctx, &L) != KGRT_OK) return KGRT_E_HIP;
     }
     if (nimg > m->r_tab_cap) {
